@@ -1,0 +1,217 @@
+/*
+ * gvm.h -- C-ABI of the GPU virtualization manager (GVM) for MI355X.
+ *
+ * The method (Li, Narayana, El-Ghazawi, "Efficient Resource Sharing Through
+ * GPU Virtualization on Accelerated High Performance Computing Systems"):
+ * many SPMD host processes share one GPU through a single manager process
+ * that owns the only device context (Section 4.2.2, Section 5).  Each
+ * process sees its own virtual GPU (VGPU, Section 5), hands its input to the
+ * manager through a per-process shared-memory space, and the manager runs
+ * every process's copy-in, kernel and copy-out as concurrent device work
+ * instead of time-sliced contexts (Section 4.2.1, concurrency types (a)-(c)).
+ *
+ * Two sides live in one library, libgvm.so:
+ *   - the manager ("daemon") side: gvm_init builds every resource and starts
+ *     the service thread in the calling process, which then owns the HIP
+ *     context of device 0;
+ *   - the rank side: gvm_attach / gvm_submit / gvm_wait / gvm_detach, callable
+ *     from any process (or thread) on the same host; ranks never touch the
+ *     GPU, they talk to the manager through POSIX shared memory only.
+ *
+ * The routines map onto the API of Section 5 as follows:
+ *   REQ()        -> gvm_attach     (acquire the VGPU of a rank)
+ *   SND()+STR()  -> gvm_submit     (input into the rank's shared memory, start)
+ *   STP()+RCV()  -> gvm_wait       (poll for the result, copy it out)
+ *   RLS()        -> gvm_detach     (release the VGPU) / gvm_shutdown
+ *
+ * Conventions
+ *   - Every function returns a gvm_status (0 = GVM_OK, negative = error)
+ *     unless stated otherwise; no C++ exception crosses this boundary.
+ *     gvm_last_error() gives a text for the calling thread's last error.
+ *   - One thread drives one rank at a time (SPMD); different ranks may be
+ *     driven by different threads or processes concurrently.
+ *   - All element data is IEEE-754 binary32, packed, host byte order.
+ *   - Callers own the `in` and `out` buffers; the library owns the shared
+ *     memory, the pinned staging, the device memory and the HIP objects.
+ */
+#ifndef GVM_H
+#define GVM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+enum gvm_status {
+  GVM_OK = 0,
+  GVM_EINVAL = -1,     /* bad argument: rank out of range, n == 0, unknown kernel id, bad config */
+  GVM_ENOMEM = -2,     /* request larger than the rank's shared memory space or the HBM budget */
+  GVM_EAGAIN = -3,     /* request ring full (non-blocking submit) */
+  GVM_ETIMEDOUT = -4,  /* gvm_wait timed out; the request is still pending */
+  GVM_EDEAD = -5,      /* the peer (manager or rank process) has died */
+  GVM_ESTATE = -6,     /* wrong call order: submit before attach, resident input missing, ... */
+  GVM_EDEVICE = -7,    /* HIP runtime error or no usable gfx950 device; see gvm_last_error() */
+  GVM_ESYS = -8,       /* operating-system error (shm_open, mmap, futex, ...) */
+  GVM_ECANCELED = -9   /* request dropped because its rank detached or died */
+};
+
+/* ------------------------------------------------------------ kernel ids
+ * Per-rank GPU tasks of the benchmark profiles (Table 3).  For a request of
+ * size n the packed binary32 layouts of `in` and `out` are:
+ *   GVM_K_VECADD        c = a + b                    in [a(n) | b(n)]            out [c(n)]
+ *   GVM_K_BLACKSCHOLES  European call and put        in [S(n) | K(n) | T(n)]     out [call(n) | put(n)]
+ *                       (rate r, volatility sigma from gvm_config)
+ *   GVM_K_SGEMM         C = A B, n x n row-major     in [A(n*n) | B(n*n)]        out [C(n*n)]
+ *   GVM_K_VECMUL        c = a * b (element-wise)     in [a(n) | b(n)]            out [c(n)]
+ */
+enum gvm_kernel {
+  GVM_K_VECADD = 1,
+  GVM_K_BLACKSCHOLES = 2,
+  GVM_K_SGEMM = 3,
+  GVM_K_VECMUL = 4
+};
+
+/* ------------------------------------------------------------ manager modes */
+enum gvm_mode {
+  GVM_MODE_BATCH = 0,   /* request barrier of Section 5: wait until every attached rank
+                           has a request (or batch_window_us expires), run them together */
+  GVM_MODE_SERVING = 1  /* continuous admission: run requests as soon as device memory
+                           (hbm_budget_bytes) and in-flight slots allow */
+};
+
+/* Enqueue policy for a set of requests run together (Section 4.2.1):
+ *   PS1      all copy-ins, then all kernels, then all copy-outs (Listing PS-1)
+ *   PS2      per rank: copy-in, kernel, copy-out on the rank's stream (Listing PS-2)
+ *   GROUPED  copy-ins per rank, then ONE persistent launch per kernel id that
+ *            covers every rank's request, then copy-outs per rank
+ *   AUTO     the paper's rule (compute-intensive -> PS1, I/O-intensive -> PS2,
+ *            end of Section 4.2.3), with GROUPED for sets of same-kernel requests */
+enum gvm_policy { GVM_POLICY_AUTO = 0, GVM_POLICY_PS1 = 1, GVM_POLICY_PS2 = 2, GVM_POLICY_GROUPED = 3 };
+
+/* Device backend.  HIP is the product path.  LOOPBACK runs the whole host
+ * protocol (shared memory, rings, admission, grouping) without a GPU and
+ * without computing any kernel: it copies each request's input bytes to its
+ * output region unchanged, so that host-logic tests can check routing; it is
+ * never chosen implicitly. */
+enum gvm_backend { GVM_BACKEND_HIP = 0, GVM_BACKEND_LOOPBACK = 1 };
+
+/* Submit flags (gvm_submit_ex). */
+enum gvm_submit_flags {
+  GVM_F_IN_RESIDENT = 1u,   /* the input is the one left on the device by this rank's previous
+                               request with the same kernel id and n; no copy-in, `in` may be NULL */
+  GVM_F_OUT_RESIDENT = 2u,  /* leave the result on the device; no copy-out, `out` may be NULL */
+  GVM_F_NONBLOCK = 4u       /* return GVM_EAGAIN instead of waiting when the ring is full */
+};
+
+#define GVM_NAME_MAX 48
+
+/* Manager configuration (gvm_init).  Call gvm_config_default first, then
+ * override fields.  `size` must be sizeof(gvm_config). */
+typedef struct gvm_config {
+  uint32_t size;
+  uint32_t nranks;              /* number of VGPUs (N_VGPU of Table 2), 1..256 */
+  uint64_t shm_bytes_per_rank;  /* per-rank shared memory space (Section 5); bounds in+out of one request */
+  uint64_t hbm_budget_bytes;    /* device memory the manager may hold for rank buffers */
+  uint64_t staging_bytes;       /* pinned host staging per rank (0 = shm_bytes_per_rank) */
+  uint32_t mode;                /* gvm_mode */
+  uint32_t policy;              /* gvm_policy */
+  uint32_t batch_window_us;     /* batch mode: longest wait for the barrier after the first request */
+  uint32_t max_inflight;        /* serving mode: requests on the device at once (0 = nranks) */
+  uint32_t nstreams;            /* HIP streams for per-rank work (0 = min(nranks, 8)) */
+  uint32_t use_graphs;          /* 1: replay repeated batch templates as HIP graphs */
+  uint32_t backend;             /* gvm_backend */
+  uint32_t copy_threads;        /* host threads for shared-memory <-> pinned copies (0 = 4) */
+  float bs_rate;                /* Black-Scholes risk-free rate r (default 0.02) */
+  float bs_volatility;          /* Black-Scholes volatility sigma (default 0.30) */
+  char name[GVM_NAME_MAX];      /* shared-memory namespace; "" = "gvm.<uid>" */
+} gvm_config;
+
+/* Fill `cfg` with defaults (nranks 8, 64 MiB per rank, budget 16 GiB, batch mode,
+ * AUTO policy, window 2000 us, HIP backend, r 0.02, sigma 0.30). */
+void gvm_config_default(gvm_config* cfg);
+
+/* Manager side (Section 5, "GVM run-time process"): create the control
+ * segment and one shared-memory space per rank, the single HIP context on
+ * device 0, the streams, the device arena (hbm_budget_bytes) and the pinned
+ * staging, then start the service thread and return.  One manager per
+ * process.  GVM_EDEVICE if no gfx950 device is usable (the HIP backend never
+ * falls back to the CPU). */
+int gvm_init(const gvm_config* cfg);
+
+/* Rank side, REQ() of Section 5: map the manager's segments of namespace
+ * `name` (NULL = $GVM_NAME, else "gvm.<uid>") and claim VGPU `rank`
+ * (0 <= rank < nranks).  Waits up to 10 s for the manager to come up.
+ * GVM_ESTATE if the rank is already attached by a live process. */
+int gvm_attach(int rank);
+int gvm_attach_ns(const char* name, int rank);
+
+/* Rank side, SND()+STR() of Section 5: queue one request of `kernel_id` with
+ * size n (see the layouts above).  The input is copied into the rank's
+ * shared memory before the call returns, unless `in` already points inside
+ * the rank's space (gvm_rank_buffer), which is then used in place.  `out`
+ * must stay valid until gvm_wait returns for this ticket; if it points
+ * inside the rank's space the result is left there.  Returns a ticket >= 0
+ * or a negative gvm_status.  Requests of one rank run in submission order. */
+int64_t gvm_submit(int rank, int kernel_id, const void* in, void* out, uint64_t n);
+int64_t gvm_submit_ex(int rank, int kernel_id, const void* in, void* out, uint64_t n, uint32_t flags);
+
+/* Rank side, STP()+RCV() of Section 5: wait until request `ticket` of
+ * `rank` has finished (ticket -1: every outstanding request of the rank),
+ * copy its result to `out` and return its status.  timeout_ns < 0 waits
+ * forever.  GVM_ETIMEDOUT leaves the request pending; GVM_EDEAD if the
+ * manager died. */
+int gvm_wait(int rank, int64_t ticket, int64_t timeout_ns);
+
+/* As gvm_wait for one ticket (>= 0), and on return also stores the
+ * request's timestamps (CLOCK_MONOTONIC ns) in ts[0..4]: submitted by the
+ * rank, admitted by the manager, device work enqueued, device work observed
+ * complete, result posted.  `ts` may be NULL. */
+int gvm_wait_timed(int rank, int64_t ticket, int64_t timeout_ns, uint64_t* ts);
+
+/* Wait for whichever outstanding request of `rank` finishes first; its
+ * ticket goes to *ticket_out.  GVM_EINVAL if nothing is outstanding. */
+int gvm_wait_any(int rank, int64_t timeout_ns, int64_t* ticket_out);
+
+/* Rank side, RLS() of Section 5: wait for the rank's outstanding requests,
+ * release its VGPU and unmap its segments.  Device buffers of the rank are
+ * freed by the manager. */
+int gvm_detach(int rank);
+
+/* Release everything the calling process holds: detach its ranks and, if it
+ * runs the manager, drain the outstanding work, stop the service thread,
+ * free device memory, pinned memory and HIP objects and unlink the shared
+ * memory. */
+int gvm_shutdown(void);
+
+/* Pointer to `bytes` bytes at the start of `rank`'s shared-memory space
+ * (attached rank only), for zero-copy submission; NULL if too large. */
+void* gvm_rank_buffer(int rank, uint64_t bytes);
+
+/* Manager statistics (this process's manager) as a JSON object: per-kernel
+ * launch count and device time from HIP events, request counts, latencies,
+ * admission waits, peak device bytes.  Returns the JSON length, or a
+ * negative status; the text is truncated to cap-1 bytes. */
+int gvm_stats_json(char* buf, uint64_t cap);
+/* Reset the manager's statistics counters. */
+int gvm_stats_reset(void);
+
+/* Text of the calling thread's last error ("" if none). */
+const char* gvm_last_error(void);
+
+/* Plain per-process path without virtualization (the execution cycle of
+ * Section 4.1, Eq. 1): in the calling process, initialise the device
+ * context, allocate device memory, copy `in` from pageable host memory,
+ * run the same kernel code object the manager uses, copy the result back
+ * to `out` and free the device memory.  Timings of the stages (seconds) go
+ * to `t` (may be NULL): t[0] context init, t[1] allocation, t[2] copy-in,
+ * t[3] kernel, t[4] copy-out, t[5] free. */
+int gvm_plain_run(int kernel_id, const void* in, void* out, uint64_t n,
+                  float bs_rate, float bs_volatility, double* t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GVM_H */

@@ -1,0 +1,96 @@
+#include "common.hpp"
+
+#include <errno.h>
+#include <linux/futex.h>
+#include <signal.h>
+#include <stdarg.h>
+#include <sys/syscall.h>
+#include <time.h>
+#include <unistd.h>
+
+#include <climits>
+#include <cstring>
+
+namespace gvm {
+
+namespace {
+thread_local char t_err[512] = {0};
+}
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(t_err, sizeof(t_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+const char* last_error_text() { return t_err; }
+void clear_error() { t_err[0] = 0; }
+
+uint64_t now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return static_cast<uint64_t>(ts.tv_sec) * 1000000000ull + static_cast<uint64_t>(ts.tv_nsec);
+}
+
+bool request_layout(int kernel_id, uint64_t n, Layout* out) {
+  if (n == 0) return false;
+  const uint64_t f = sizeof(float);
+  switch (kernel_id) {
+    case GVM_K_VECADD:
+    case GVM_K_VECMUL:
+      if (n > (1ull << 40)) return false;
+      out->in_bytes = 2 * n * f;
+      out->out_bytes = n * f;
+      return true;
+    case GVM_K_BLACKSCHOLES:
+      if (n > (1ull << 40)) return false;
+      out->in_bytes = 3 * n * f;
+      out->out_bytes = 2 * n * f;
+      return true;
+    case GVM_K_SGEMM:
+      if (n > 65536) return false;  // C must fit 32-bit row/col indexing
+      out->in_bytes = 2 * n * n * f;
+      out->out_bytes = n * n * f;
+      return true;
+    default:
+      return false;
+  }
+}
+
+int futex_wait(std::atomic<uint32_t>* word, uint32_t expected, int64_t timeout_ns) {
+  timespec ts;
+  timespec* tp = nullptr;
+  if (timeout_ns >= 0) {
+    ts.tv_sec = timeout_ns / 1000000000ll;
+    ts.tv_nsec = timeout_ns % 1000000000ll;
+    tp = &ts;
+  }
+  long rc = syscall(SYS_futex, reinterpret_cast<uint32_t*>(word), FUTEX_WAIT, expected, tp, nullptr, 0);
+  if (rc == -1 && errno == ETIMEDOUT) return GVM_ETIMEDOUT;
+  return 0;
+}
+
+void futex_wake_all(std::atomic<uint32_t>* word) {
+  syscall(SYS_futex, reinterpret_cast<uint32_t*>(word), FUTEX_WAKE, INT_MAX, nullptr, nullptr, 0);
+}
+
+bool pid_alive(int32_t pid) {
+  if (pid <= 0) return false;
+  if (kill(pid, 0) != 0 && errno != EPERM) return false;
+  // an exited but unreaped process (zombie) still answers kill(pid, 0)
+  char path[64];
+  snprintf(path, sizeof(path), "/proc/%d/stat", pid);
+  FILE* f = fopen(path, "r");
+  if (!f) return true;
+  char buf[512];
+  size_t len = fread(buf, 1, sizeof(buf) - 1, f);
+  fclose(f);
+  buf[len] = 0;
+  const char* rp = strrchr(buf, ')');
+  if (rp && rp[1] == ' ' && (rp[2] == 'Z' || rp[2] == 'X')) return false;
+  return true;
+}
+
+}  // namespace gvm

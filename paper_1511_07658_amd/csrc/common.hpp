@@ -1,0 +1,52 @@
+// Shared helpers of the GVM library: status/error text, clocks, request
+// layouts, futex doorbells.
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "gvm.h"
+
+namespace gvm {
+
+// Thread-local last error.  Returns `code` so callers can `return fail(...)`.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+const char* last_error_text();
+void clear_error();
+
+uint64_t now_ns();  // CLOCK_MONOTONIC, shared by every process on the host
+
+constexpr uint64_t kAlign = 256;  // device / staging sub-buffer alignment
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Packed binary32 layout of one request (bytes of `in` and `out`).
+struct Layout {
+  uint64_t in_bytes = 0;
+  uint64_t out_bytes = 0;
+};
+// false if the kernel id is unknown, n == 0 or the size overflows.
+bool request_layout(int kernel_id, uint64_t n, Layout* out);
+// Device slot bytes for a request: input, then output at the next aligned offset.
+inline uint64_t slot_bytes(const Layout& l) { return align_up(l.in_bytes, kAlign) + align_up(l.out_bytes, kAlign); }
+inline uint64_t slot_out_offset(const Layout& l) { return align_up(l.in_bytes, kAlign); }
+
+// Futex on a 32-bit word that lives in shared memory (process-shared).
+// Returns 0 when woken or the value differed, GVM_ETIMEDOUT on timeout.
+int futex_wait(std::atomic<uint32_t>* word, uint32_t expected, int64_t timeout_ns);
+void futex_wake_all(std::atomic<uint32_t>* word);
+
+bool pid_alive(int32_t pid);
+
+inline const char* kernel_name(int k) {
+  switch (k) {
+    case GVM_K_VECADD: return "vecadd";
+    case GVM_K_BLACKSCHOLES: return "blackscholes";
+    case GVM_K_SGEMM: return "sgemm";
+    case GVM_K_VECMUL: return "vecmul";
+    default: return "unknown";
+  }
+}
+
+}  // namespace gvm

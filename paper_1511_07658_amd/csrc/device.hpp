@@ -1,0 +1,68 @@
+// Device side of the manager: the GPU resources of Section 5 (one context,
+// streams, per-process device and pinned host memory, prepared kernels) and
+// the enqueue policies of Section 4.2.1.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "shm.hpp"
+
+namespace gvm {
+
+// One admitted request on its way through the device.
+struct Job {
+  int rank = -1;
+  Request req{};
+  Layout lay{};
+  uint8_t* shm = nullptr;       // rank's data space (host)
+  uint8_t* slot = nullptr;      // rank's device buffer: input at 0, output at slot_out_offset
+  uint8_t* pin = nullptr;       // rank's pinned staging: same layout as the slot
+  bool copy_in = true;
+  bool copy_out = true;
+  int status = GVM_OK;
+  uint64_t t_admit_ns = 0;
+  uint64_t t_launch_ns = 0;
+  uint64_t t_device_ns = 0;
+  void* batch = nullptr;        // device-private bookkeeping
+  int done_index = -1;
+};
+
+struct KernelStats {
+  uint64_t launches = 0;
+  uint64_t requests = 0;
+  double device_ms = 0.0;       // sum of launch durations from device events
+  double work_flop = 0.0;       // algorithmic FLOP of the launched requests
+  double work_bytes = 0.0;      // algorithmic HBM bytes of the launched requests
+};
+
+// Algorithmic work of one request (the per-unit figures: 12 B per vector
+// element, 20 B per option, 2 n^3 FLOP and 12 n^2 compulsory bytes per GEMM).
+void request_work(int kernel_id, uint64_t n, double* flop, double* bytes);
+
+class Device {
+ public:
+  virtual ~Device() = default;
+  virtual int open(const gvm_config& cfg) = 0;
+  virtual uint8_t* arena() = 0;                 // hbm_budget_bytes of device memory
+  virtual uint8_t* staging(int rank) = 0;       // pinned staging of a rank (nullptr on failure)
+  // Enqueue the device work of the admitted jobs under `policy`.
+  virtual int launch(std::vector<Job*>& jobs, int policy) = 0;
+  // 1 when the job's device work has finished, 0 if not yet, < 0 on a device error.
+  virtual int query(Job* j) = 0;
+  // After query() == 1: move the result from staging to the rank's data space.
+  virtual void finish(Job* j) = 0;
+  virtual void drain() = 0;
+  virtual void close() = 0;
+  virtual const KernelStats* kernel_stats() const = 0;  // indexed by kernel id (0..4)
+  virtual void reset_stats() = 0;
+  virtual std::string describe() const = 0;
+};
+
+std::unique_ptr<Device> make_hip_device();
+std::unique_ptr<Device> make_loopback_device();
+
+}  // namespace gvm

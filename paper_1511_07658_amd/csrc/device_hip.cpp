@@ -1,0 +1,438 @@
+// HIP device of the manager: the single context of device 0, per-rank
+// streams, compute streams, one device arena, per-rank pinned staging, and
+// the three enqueue policies (PS-1, PS-2 of Section 4.2.1, and the grouped
+// persistent launch).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "copy_pool.hpp"
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace gvm {
+
+namespace {
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(GVM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct TimedLaunch {
+  int kernel_id;
+  hipEvent_t e0, e1;
+  uint32_t requests;
+  double flop, bytes;
+};
+
+struct Batch {
+  std::vector<Job*> jobs;
+  std::vector<hipEvent_t> done;   // per job (several jobs may share one event)
+  std::vector<hipEvent_t> sync;   // events owned by the batch, recycled at the end
+  std::vector<TimedLaunch> timed;
+  size_t remaining = 0;
+};
+
+class HipDevice final : public Device {
+ public:
+  ~HipDevice() override { close(); }
+
+  int open(const gvm_config& cfg) override {
+    cfg_ = cfg;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+      return fail(GVM_EDEVICE, "no HIP device visible (the HIP backend has no CPU fallback)");
+    HIPCHK(hipSetDevice(0));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, 0));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(GVM_EDEVICE, "device 0 is %s; this library is built for gfx950 only", prop.gcnArchName);
+    arch_ = prop.gcnArchName;
+    cus_ = prop.multiProcessorCount;
+    const int ns = cfg.nstreams ? static_cast<int>(cfg.nstreams) : std::min<int>(cfg.nranks, 8);
+    for (int i = 0; i < ns; ++i) {
+      hipStream_t s;
+      HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      rank_streams_.push_back(s);
+    }
+    for (int i = 0; i < 2; ++i) {
+      hipStream_t s;
+      HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      compute_streams_.push_back(s);
+    }
+    HIPCHK(hipMalloc(reinterpret_cast<void**>(&arena_), cfg.hbm_budget_bytes));
+    staging_.assign(cfg.nranks, nullptr);
+    staging_bytes_ = cfg.staging_bytes ? cfg.staging_bytes : cfg.shm_bytes_per_rank;
+    staging_bytes_ = align_up(staging_bytes_ + 2 * kAlign, 4096);
+    pool_.start(cfg.copy_threads ? static_cast<int>(cfg.copy_threads) : 4);
+    int rc = prepare_kernels();
+    if (rc != GVM_OK) return rc;
+    return GVM_OK;
+  }
+
+  uint8_t* arena() override { return arena_; }
+
+  uint8_t* staging(int rank) override {
+    if (rank < 0 || rank >= static_cast<int>(staging_.size())) return nullptr;
+    if (!staging_[rank]) {
+      void* p = nullptr;
+      if (hipHostMalloc(&p, staging_bytes_, hipHostMallocDefault) != hipSuccess) {
+        fail(GVM_EDEVICE, "hipHostMalloc(%llu) failed", (unsigned long long)staging_bytes_);
+        return nullptr;
+      }
+      staging_[rank] = static_cast<uint8_t*>(p);
+    }
+    return staging_[rank];
+  }
+
+  int launch(std::vector<Job*>& jobs, int policy) override {
+    if (jobs.empty()) return GVM_OK;
+    auto* b = new Batch;
+    b->jobs = jobs;
+    b->done.assign(jobs.size(), nullptr);
+    b->remaining = jobs.size();
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      jobs[i]->batch = b;
+      jobs[i]->done_index = static_cast<int>(i);
+      jobs[i]->t_launch_ns = now_ns();
+    }
+    int rc = GVM_OK;
+    if (policy == GVM_POLICY_PS2) {
+      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
+        Job* j = jobs[i];
+        hipStream_t s = rank_stream(j->rank);
+        std::vector<Job*> one{j};
+        rc = enqueue_in(j, s);
+        if (rc == GVM_OK) rc = enqueue_kernels(one, s, b);
+        if (rc == GVM_OK) rc = enqueue_out(j, s);
+        if (rc == GVM_OK) rc = record_done(b, i, s);
+      }
+    } else if (policy == GVM_POLICY_PS1) {
+      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) rc = enqueue_in(jobs[i], rank_stream(jobs[i]->rank));
+      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
+        std::vector<Job*> one{jobs[i]};
+        rc = enqueue_kernels(one, rank_stream(jobs[i]->rank), b);
+      }
+      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
+        hipStream_t s = rank_stream(jobs[i]->rank);
+        rc = enqueue_out(jobs[i], s);
+        if (rc == GVM_OK) rc = record_done(b, i, s);
+      }
+    } else {  // grouped
+      hipStream_t cs = compute_streams_[next_cs_++ % compute_streams_.size()];
+      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
+        Job* j = jobs[i];
+        if (!j->copy_in) continue;
+        hipStream_t s = rank_stream(j->rank);
+        rc = enqueue_in(j, s);
+        if (rc != GVM_OK) break;
+        hipEvent_t ev = sync_event(b);
+        if (!ev) { rc = GVM_EDEVICE; break; }
+        if (hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
+          rc = fail(GVM_EDEVICE, "event record/wait failed");
+      }
+      if (rc == GVM_OK) rc = enqueue_kernels(jobs, cs, b);
+      hipEvent_t comp = nullptr;
+      if (rc == GVM_OK) {
+        comp = sync_event(b);
+        if (!comp || hipEventRecord(comp, cs) != hipSuccess) rc = fail(GVM_EDEVICE, "event record failed");
+      }
+      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
+        Job* j = jobs[i];
+        if (!j->copy_out) {
+          b->done[i] = comp;
+          continue;
+        }
+        hipStream_t s = rank_stream(j->rank);
+        if (hipStreamWaitEvent(s, comp, 0) != hipSuccess) { rc = fail(GVM_EDEVICE, "stream wait failed"); break; }
+        rc = enqueue_out(j, s);
+        if (rc == GVM_OK) rc = record_done(b, i, s);
+      }
+    }
+    batches_.push_back(b);
+    if (rc != GVM_OK) {
+      // Device state is unknown after a failed enqueue: wait for what was
+      // queued, then fail every job of the batch.
+      (void)hipDeviceSynchronize();
+      for (Job* j : jobs) j->status = rc;
+      for (size_t i = 0; i < jobs.size(); ++i) b->done[i] = nullptr;
+    }
+    return rc;
+  }
+
+  int query(Job* j) override {
+    auto* b = static_cast<Batch*>(j->batch);
+    if (j->status != GVM_OK) return 1;
+    hipEvent_t ev = b->done[j->done_index];
+    if (!ev) return 1;
+    hipError_t e = hipEventQuery(ev);
+    if (e == hipSuccess) {
+      if (!j->t_device_ns) j->t_device_ns = now_ns();
+      return 1;
+    }
+    if (e == hipErrorNotReady) return 0;
+    j->status = fail(GVM_EDEVICE, "device work failed: %s", hipGetErrorString(e));
+    return -1;
+  }
+
+  void finish(Job* j) override {
+    auto* b = static_cast<Batch*>(j->batch);
+    if (j->status == GVM_OK && j->copy_out)
+      pool_.copy(j->shm + j->req.off_out, j->pin + slot_out_offset(j->lay), j->lay.out_bytes);
+    j->batch = nullptr;
+    if (b && --b->remaining == 0) retire(b);
+  }
+
+  void drain() override { (void)hipDeviceSynchronize(); }
+
+  void close() override {
+    if (closed_) return;
+    closed_ = true;
+    (void)hipDeviceSynchronize();
+    for (Batch* b : batches_) {
+      for (hipEvent_t e : b->sync) (void)hipEventDestroy(e);
+      for (auto& t : b->timed) {
+        (void)hipEventDestroy(t.e0);
+        (void)hipEventDestroy(t.e1);
+      }
+      delete b;
+    }
+    batches_.clear();
+    for (hipEvent_t e : free_sync_) (void)hipEventDestroy(e);
+    for (hipEvent_t e : free_timed_) (void)hipEventDestroy(e);
+    free_sync_.clear();
+    free_timed_.clear();
+    for (hipStream_t s : rank_streams_) (void)hipStreamDestroy(s);
+    for (hipStream_t s : compute_streams_) (void)hipStreamDestroy(s);
+    rank_streams_.clear();
+    compute_streams_.clear();
+    if (arena_) (void)hipFree(arena_);
+    arena_ = nullptr;
+    for (uint8_t* p : staging_)
+      if (p) (void)hipHostFree(p);
+    staging_.clear();
+    pool_.stop();
+  }
+
+  const KernelStats* kernel_stats() const override { return stats_; }
+  void reset_stats() override {
+    for (auto& s : stats_) s = KernelStats{};
+  }
+  std::string describe() const override {
+    return "{\"backend\":\"hip\",\"arch\":\"" + arch_ + "\",\"cus\":" + std::to_string(cus_) +
+           ",\"rank_streams\":" + std::to_string(rank_streams_.size()) +
+           ",\"compute_streams\":" + std::to_string(compute_streams_.size()) + "}";
+  }
+
+ private:
+  hipStream_t rank_stream(int rank) { return rank_streams_[static_cast<size_t>(rank) % rank_streams_.size()]; }
+
+  hipEvent_t sync_event(Batch* b) {
+    hipEvent_t e = nullptr;
+    if (!free_sync_.empty()) {
+      e = free_sync_.back();
+      free_sync_.pop_back();
+    } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      fail(GVM_EDEVICE, "hipEventCreate failed");
+      return nullptr;
+    }
+    b->sync.push_back(e);
+    return e;
+  }
+
+  hipEvent_t timed_event() {
+    hipEvent_t e = nullptr;
+    if (!free_timed_.empty()) {
+      e = free_timed_.back();
+      free_timed_.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      return nullptr;
+    }
+    return e;
+  }
+
+  int record_done(Batch* b, size_t i, hipStream_t s) {
+    hipEvent_t e = sync_event(b);
+    if (!e) return GVM_EDEVICE;
+    HIPCHK(hipEventRecord(e, s));
+    b->done[i] = e;
+    return GVM_OK;
+  }
+
+  int enqueue_in(Job* j, hipStream_t s) {
+    if (!j->copy_in) return GVM_OK;
+    pool_.copy(j->pin, j->shm + j->req.off_in, j->lay.in_bytes);
+    HIPCHK(hipMemcpyAsync(j->slot, j->pin, j->lay.in_bytes, hipMemcpyHostToDevice, s));
+    return GVM_OK;
+  }
+
+  int enqueue_out(Job* j, hipStream_t s) {
+    if (!j->copy_out) return GVM_OK;
+    const uint64_t o = slot_out_offset(j->lay);
+    HIPCHK(hipMemcpyAsync(j->pin + o, j->slot + o, j->lay.out_bytes, hipMemcpyDeviceToHost, s));
+    return GVM_OK;
+  }
+
+  // One grouped launch per kernel id (per tile configuration for SGEMM), at
+  // most kMaxGroup requests each, bracketed by timing events.
+  int enqueue_kernels(std::vector<Job*>& jobs, hipStream_t s, Batch* b) {
+    std::map<std::pair<int, int>, std::vector<Job*>> groups;
+    for (Job* j : jobs) {
+      const int k = static_cast<int>(j->req.kernel_id);
+      const int cfg = (k == GVM_K_SGEMM) ? gemm_config_for(j->req.n) : 0;
+      groups[{k, cfg}].push_back(j);
+    }
+    for (auto& kv : groups) {
+      const int k = kv.first.first, cfgi = kv.first.second;
+      auto& v = kv.second;
+      for (size_t base = 0; base < v.size(); base += kMaxGroup) {
+        const size_t cnt = std::min<size_t>(kMaxGroup, v.size() - base);
+        TimedLaunch t{};
+        t.kernel_id = k;
+        t.requests = static_cast<uint32_t>(cnt);
+        t.e0 = timed_event();
+        t.e1 = timed_event();
+        if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
+        for (size_t i = 0; i < cnt; ++i) {
+          double f, by;
+          request_work(k, v[base + i]->req.n, &f, &by);
+          t.flop += f;
+          t.bytes += by;
+        }
+        HIPCHK(hipEventRecord(t.e0, s));
+        hipError_t e = hipSuccess;
+        if (k == GVM_K_VECADD || k == GVM_K_VECMUL) {
+          VecGroup g{};
+          g.count = static_cast<uint32_t>(cnt);
+          for (size_t i = 0; i < cnt; ++i) {
+            Job* j = v[base + i];
+            float* in = reinterpret_cast<float*>(j->slot);
+            g.d[i].a = in;
+            g.d[i].b = in + j->req.n;
+            g.d[i].c = reinterpret_cast<float*>(j->slot + slot_out_offset(j->lay));
+            g.d[i].n = j->req.n;
+          }
+          finalize_vec_group(g);
+          e = (k == GVM_K_VECADD) ? launch_vecadd_group(g, s) : launch_vecmul_group(g, s);
+        } else if (k == GVM_K_BLACKSCHOLES) {
+          BsGroup g{};
+          g.count = static_cast<uint32_t>(cnt);
+          g.rate = cfg_.bs_rate;
+          g.volatility = cfg_.bs_volatility;
+          for (size_t i = 0; i < cnt; ++i) {
+            Job* j = v[base + i];
+            const uint64_t n = j->req.n;
+            float* in = reinterpret_cast<float*>(j->slot);
+            float* out = reinterpret_cast<float*>(j->slot + slot_out_offset(j->lay));
+            g.d[i].S = in;
+            g.d[i].K = in + n;
+            g.d[i].T = in + 2 * n;
+            g.d[i].call = out;
+            g.d[i].put = out + n;
+            g.d[i].n = n;
+          }
+          finalize_bs_group(g);
+          e = launch_bs_group(g, s);
+        } else if (k == GVM_K_SGEMM) {
+          GemmGroup g{};
+          g.count = static_cast<uint32_t>(cnt);
+          for (size_t i = 0; i < cnt; ++i) {
+            Job* j = v[base + i];
+            const uint64_t n = j->req.n;
+            float* in = reinterpret_cast<float*>(j->slot);
+            g.d[i].A = in;
+            g.d[i].B = in + n * n;
+            g.d[i].C = reinterpret_cast<float*>(j->slot + slot_out_offset(j->lay));
+            g.d[i].n = static_cast<uint32_t>(n);
+          }
+          finalize_gemm_group(g, cfgi);
+          e = launch_sgemm_group(g, cfgi, s);
+        } else {
+          return fail(GVM_EINVAL, "unknown kernel id %d", k);
+        }
+        if (e != hipSuccess) return fail(GVM_EDEVICE, "kernel launch (%s): %s", kernel_name(k), hipGetErrorString(e));
+        HIPCHK(hipEventRecord(t.e1, s));
+        b->timed.push_back(t);
+      }
+    }
+    return GVM_OK;
+  }
+
+  void retire(Batch* b) {
+    for (auto& t : b->timed) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, t.e0, t.e1) == hipSuccess && t.kernel_id >= 0 && t.kernel_id < 5) {
+        KernelStats& ks = stats_[t.kernel_id];
+        ks.launches += 1;
+        ks.requests += t.requests;
+        ks.device_ms += ms;
+        ks.work_flop += t.flop;
+        ks.work_bytes += t.bytes;
+      }
+      free_timed_.push_back(t.e0);
+      free_timed_.push_back(t.e1);
+    }
+    for (hipEvent_t e : b->sync) free_sync_.push_back(e);
+    batches_.erase(std::remove(batches_.begin(), batches_.end(), b), batches_.end());
+    delete b;
+  }
+
+  // Load every kernel's code object now, as the manager of Section 5 prepares
+  // the kernels at initialisation: one tiny launch of each on arena memory.
+  int prepare_kernels() {
+    if (cfg_.hbm_budget_bytes < (1u << 20)) return GVM_OK;
+    hipStream_t s = compute_streams_[0];
+    float* base = reinterpret_cast<float*>(arena_);
+    HIPCHK(hipMemsetAsync(base, 0, 1 << 20, s));
+    VecGroup vg{};
+    vg.count = 1;
+    vg.d[0] = VecDesc{base, base + 64, base + 128, 64, 0};
+    finalize_vec_group(vg);
+    HIPCHK(launch_vecadd_group(vg, s));
+    HIPCHK(launch_vecmul_group(vg, s));
+    BsGroup bg{};
+    bg.count = 1;
+    bg.rate = cfg_.bs_rate;
+    bg.volatility = cfg_.bs_volatility;
+    bg.d[0] = BsDesc{base, base + 64, base + 128, base + 192, base + 256, 64, 0};
+    finalize_bs_group(bg);
+    HIPCHK(launch_bs_group(bg, s));
+    for (int c = 0; c < gemm_config_count(); ++c) {
+      GemmGroup gg{};
+      gg.count = 1;
+      gg.d[0] = GemmDesc{base, base + 4096, base + 8192, 64, 0, 0, 0};
+      finalize_gemm_group(gg, c);
+      HIPCHK(launch_sgemm_group(gg, c, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return GVM_OK;
+  }
+
+  gvm_config cfg_{};
+  std::string arch_;
+  int cus_ = 0;
+  bool closed_ = false;
+  std::vector<hipStream_t> rank_streams_;
+  std::vector<hipStream_t> compute_streams_;
+  size_t next_cs_ = 0;
+  uint8_t* arena_ = nullptr;
+  std::vector<uint8_t*> staging_;
+  uint64_t staging_bytes_ = 0;
+  CopyPool pool_;
+  std::vector<hipEvent_t> free_sync_;
+  std::vector<hipEvent_t> free_timed_;
+  std::vector<Batch*> batches_;
+  KernelStats stats_[5];
+};
+
+}  // namespace
+
+std::unique_ptr<Device> make_hip_device() { return std::unique_ptr<Device>(new HipDevice()); }
+
+}  // namespace gvm

@@ -1,0 +1,98 @@
+// Device kernels of the GVM for gfx950 and their host-side launchers.
+//
+// Every launcher takes a *group* of requests of one kernel id and covers all
+// of them with one persistent launch; a single request is a group of one, so
+// a rank's result does not depend on what else runs with it (each output
+// element is produced by the same code with the same operation order).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gvm {
+
+constexpr int kMaxGroup = 32;  // requests per grouped launch (kernel-argument capacity, < 2 KiB)
+
+struct VecDesc {
+  const float* a;
+  const float* b;
+  float* c;
+  uint64_t n;
+  uint64_t unit_begin;  // first work unit of this request in the group
+};
+
+struct VecGroup {
+  uint32_t count;
+  uint32_t pad;
+  uint64_t total_units;
+  VecDesc d[kMaxGroup];
+};
+
+struct BsDesc {
+  const float* S;
+  const float* K;
+  const float* T;
+  float* call;
+  float* put;
+  uint64_t n;
+  uint64_t unit_begin;
+};
+
+struct BsGroup {
+  uint32_t count;
+  uint32_t pad;
+  uint64_t total_units;
+  float rate;
+  float volatility;
+  BsDesc d[kMaxGroup];
+};
+
+struct GemmDesc {
+  const float* A;
+  const float* B;
+  float* C;
+  uint32_t n;        // square size
+  uint32_t tiles_n;  // tiles along the columns of C
+  uint32_t unit_begin;
+  uint32_t units;    // tiles of this request
+};
+
+struct GemmGroup {
+  uint32_t count;
+  uint32_t total_units;
+  GemmDesc d[kMaxGroup];
+};
+
+// SGEMM tile configurations available to the tuner.  A configuration is a
+// pure function of n (see gemm_config_for), so a request always runs with the
+// same tiles whatever it is grouped with.
+struct GemmConfig {
+  int id;
+  int bm, bn, bk;   // macro tile of one workgroup
+  int wm, wn;       // waves along M and N (wave tile = bm/wm x bn/wn)
+};
+
+int gemm_config_count();
+const GemmConfig& gemm_config(int idx);
+// Tile configuration used for size n (table written by the tuner, compiled in).
+int gemm_config_for(uint64_t n);
+// Override the table (tuner only): config index for every n, or -1 to restore.
+void gemm_config_force(int idx);
+
+constexpr uint64_t kVecUnit = 4096;   // elements per vector work unit
+constexpr uint64_t kBsUnit = 2048;    // options per Black-Scholes work unit
+
+// Persistent-grid launchers.  `grid_cap` bounds the number of workgroups
+// (0 = default for the kernel).  Return hipSuccess or the launch error.
+hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap = 0);
+hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap = 0);
+hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap = 0);
+hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap = 0);
+
+// Fill the unit bookkeeping of a group (unit_begin, tiles, totals).
+void finalize_vec_group(VecGroup& g);
+void finalize_bs_group(BsGroup& g);
+void finalize_gemm_group(GemmGroup& g, int config_idx);
+
+}  // namespace gvm

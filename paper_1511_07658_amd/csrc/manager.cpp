@@ -1,0 +1,588 @@
+#include "manager.hpp"
+
+#include <immintrin.h>
+#include <sched.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <future>
+#include <new>
+
+#include "common.hpp"
+
+namespace gvm {
+
+// ---------------------------------------------------------------- Arena
+
+void Arena::init(uint64_t bytes) {
+  free_.clear();
+  total_ = bytes / 4096 * 4096;
+  if (total_) free_[0] = total_;
+  used_ = peak_ = 0;
+}
+
+bool Arena::alloc(uint64_t bytes, uint64_t* off) {
+  bytes = round(bytes);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const uint64_t rest = it->second - bytes;
+      const uint64_t at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      used_ += bytes;
+      peak_ = std::max(peak_, used_);
+      return true;
+    }
+  }
+  return false;
+}
+
+void Arena::release(uint64_t off, uint64_t bytes) {
+  bytes = round(bytes);
+  used_ -= bytes;
+  auto it = free_.emplace(off, bytes).first;
+  auto next = std::next(it);
+  if (next != free_.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    free_.erase(next);
+  }
+  if (it != free_.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      free_.erase(it);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Manager
+
+int Manager::init(const gvm_config& cfg_in) {
+  if (started_) return fail(GVM_ESTATE, "a manager already runs in this process");
+  if (cfg_in.size != sizeof(gvm_config)) return fail(GVM_EINVAL, "gvm_config.size mismatch");
+  gvm_config cfg = cfg_in;
+  if (cfg.nranks < 1 || cfg.nranks > static_cast<uint32_t>(kMaxRanks))
+    return fail(GVM_EINVAL, "nranks must be in 1..%d", kMaxRanks);
+  if (cfg.shm_bytes_per_rank < 4096) return fail(GVM_EINVAL, "shm_bytes_per_rank too small");
+  if (cfg.hbm_budget_bytes < (1u << 20)) return fail(GVM_EINVAL, "hbm_budget_bytes must be >= 1 MiB");
+  if (cfg.mode > GVM_MODE_SERVING || cfg.policy > GVM_POLICY_GROUPED || cfg.backend > GVM_BACKEND_LOOPBACK)
+    return fail(GVM_EINVAL, "bad mode/policy/backend");
+  cfg.shm_bytes_per_rank = (cfg.shm_bytes_per_rank + 4095) / 4096 * 4096;
+  if (cfg.max_inflight == 0) cfg.max_inflight = cfg.nranks;
+  cfg.name[GVM_NAME_MAX - 1] = 0;
+  cfg_ = cfg;
+  ns_ = cfg.name[0] ? std::string(cfg.name) : default_namespace();
+  if (ns_.find('/') != std::string::npos) return fail(GVM_EINVAL, "namespace must not contain '/'");
+
+  int rc = ctl_seg_.create(ctl_object_name(ns_), ctl_bytes(cfg.nranks));
+  if (rc != GVM_OK) return rc;
+  ctl_ = new (ctl_seg_.addr) CtlHeader();
+  ctl_->magic = kMagic;
+  ctl_->version = kVersion;
+  ctl_->nranks = cfg.nranks;
+  ctl_->shm_bytes_per_rank = cfg.shm_bytes_per_rank;
+  ctl_->slot_stride = ctl_slot_stride();
+  ctl_->state.store(kStarting);
+  ctl_->manager_pid.store(getpid());
+  ctl_->generation.store(static_cast<uint32_t>(now_ns() & 0xffffffffu));
+  ctl_->bell.store(0);
+  ctl_->manager_sleeping.store(0);
+  ctl_->cfg = cfg;
+  for (uint32_t r = 0; r < cfg.nranks; ++r) {
+    RankSlot* s = new (ctl_slot(ctl_, r)) RankSlot();
+    s->state.store(kSlotFree);
+    s->pid.store(0);
+    s->epoch.store(0);
+    s->resp_bell.store(0);
+    s->rank_sleeping.store(0);
+    s->req.reset();
+    s->resp.reset();
+  }
+  data_.clear();
+  for (uint32_t r = 0; r < cfg.nranks; ++r) {
+    auto seg = std::make_unique<Segment>();
+    rc = seg->create(data_object_name(ns_, r), cfg.shm_bytes_per_rank);
+    if (rc != GVM_OK) {
+      data_.clear();
+      ctl_seg_.close();
+      ctl_ = nullptr;
+      return rc;
+    }
+    data_.push_back(std::move(seg));
+  }
+  ranks_.assign(cfg.nranks, RankRt{});
+  arena_.init(cfg.hbm_budget_bytes);
+  dev_ = (cfg.backend == GVM_BACKEND_LOOPBACK) ? make_loopback_device() : make_hip_device();
+
+  // The service thread opens the device itself so that every HIP call of the
+  // manager is made from one thread.
+  stop_.store(false);
+  std::promise<int> ready;
+  std::future<int> fut = ready.get_future();
+  thread_ = std::thread([this, &ready] { service(&ready); });
+  rc = fut.get();
+  if (rc != GVM_OK) {
+    thread_.join();
+    fail(rc, "%s", open_error_.c_str());
+    dev_.reset();
+    data_.clear();
+    ctl_seg_.close();
+    ctl_ = nullptr;
+    return rc;
+  }
+  started_ = true;
+  return GVM_OK;
+}
+
+void Manager::service(std::promise<int>* ready) {
+  int rc = dev_->open(cfg_);
+  if (rc != GVM_OK) {
+    open_error_ = last_error_text();
+    dev_->close();
+    ready->set_value(rc);
+    return;
+  }
+  ctl_->heartbeat_ns.store(now_ns());
+  ctl_->state.store(kReady, std::memory_order_release);
+  ready->set_value(GVM_OK);
+
+  uint32_t spins = 0;
+  while (!stop_.load(std::memory_order_acquire)) {
+    ctl_->heartbeat_ns.store(now_ns(), std::memory_order_relaxed);
+    if (reset_pending_.exchange(false)) {
+      dev_->reset_stats();
+      arena_.reset_peak();
+    }
+    bool progress = drain_rings();
+    progress |= complete_jobs();
+    check_liveness();
+    progress |= schedule();
+    if (progress) {
+      spins = 0;
+      continue;
+    }
+    if (inflight_ > 0) {
+      // device work outstanding: poll its events, yielding the core politely
+      if (++spins < 64) _mm_pause(); else sched_yield();
+      continue;
+    }
+    // idle: sleep on the doorbell until a rank rings it (or a deadline)
+    int64_t timeout = 2000000;  // 2 ms: liveness checks and batch windows
+    const uint32_t v = ctl_->bell.load(std::memory_order_acquire);
+    ctl_->manager_sleeping.store(1, std::memory_order_seq_cst);
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    if (!any_request_waiting()) {
+      if (cfg_.mode == GVM_MODE_BATCH && cfg_.batch_window_us) {
+        for (const auto& rt : ranks_)
+          if (!rt.queue.empty()) timeout = std::min<int64_t>(timeout, int64_t(cfg_.batch_window_us) * 1000 / 4 + 1000);
+      }
+      futex_wait(&ctl_->bell, v, timeout);
+    }
+    ctl_->manager_sleeping.store(0, std::memory_order_relaxed);
+    spins = 0;
+  }
+
+  // Shutdown: let device work finish, answer what is still queued.
+  while (inflight_ > 0) {
+    complete_jobs();
+    if (inflight_ > 0) sched_yield();
+  }
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    drain_rings();
+    auto& rt = ranks_[r];
+    while (!rt.queue.empty()) {
+      const Queued q = rt.queue.front();
+      rt.queue.pop_front();
+      respond(r, q.req.ticket, q.req.kernel_id, GVM_ECANCELED, nullptr, q.req.t_submit_ns);
+    }
+  }
+  ctl_->state.store(kStopping, std::memory_order_release);
+  dev_->close();
+  ctl_->state.store(kStopped, std::memory_order_release);
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    RankSlot* s = ctl_slot(ctl_, r);
+    s->resp_bell.fetch_add(1);
+    futex_wake_all(&s->resp_bell);
+  }
+}
+
+bool Manager::any_request_waiting() const {
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    RankSlot* s = ctl_slot(ctl_, r);
+    if (s->state.load(std::memory_order_acquire) != kSlotFree && !s->req.empty()) return true;
+  }
+  return false;
+}
+
+bool Manager::drain_rings() {
+  bool any = false;
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    RankSlot* s = ctl_slot(ctl_, r);
+    if (s->state.load(std::memory_order_acquire) == kSlotFree) continue;
+    Request m;
+    while (s->req.pop(&m)) {
+      on_message(static_cast<int>(r), m);
+      any = true;
+    }
+  }
+  return any;
+}
+
+void Manager::on_message(int r, const Request& m) {
+  RankSlot* s = ctl_slot(ctl_, r);
+  RankRt& rt = ranks_[r];
+  if (m.kernel_id == kMsgAttach) {
+    if (rt.attached) release_slot(r);
+    rt = RankRt{};
+    rt.attached = true;
+    rt.pid = s->pid.load(std::memory_order_acquire);
+    rt.last_use_ns = now_ns();
+    s->state.store(kSlotAttached, std::memory_order_release);
+    respond(r, m.ticket, m.kernel_id, GVM_OK, nullptr, m.t_submit_ns);
+    return;
+  }
+  if (!rt.attached) return;  // stray message of a slot that is not attached
+  if (m.kernel_id == kMsgDetach) {
+    rt.detach_pending = true;
+    rt.detach_ticket = m.ticket;
+    return;
+  }
+  Queued q{seq_++, now_ns(), GVM_OK, m};
+  Layout lay;
+  const uint64_t space = cfg_.shm_bytes_per_rank;
+  if (!request_layout(static_cast<int>(m.kernel_id), m.n, &lay) || lay.in_bytes != m.in_bytes ||
+      lay.out_bytes != m.out_bytes) {
+    q.status = GVM_EINVAL;
+  } else if (slot_bytes(lay) > arena_.total()) {
+    q.status = GVM_ENOMEM;
+  } else if (!(m.flags & GVM_F_IN_RESIDENT) && (m.off_in > space || lay.in_bytes > space - m.off_in)) {
+    q.status = GVM_EINVAL;
+  } else if (!(m.flags & GVM_F_OUT_RESIDENT) && (m.off_out > space || lay.out_bytes > space - m.off_out)) {
+    q.status = GVM_EINVAL;
+  } else if (slot_bytes(lay) > align_up((cfg_.staging_bytes ? cfg_.staging_bytes : space) + 2 * kAlign, 4096)) {
+    q.status = GVM_ENOMEM;
+  }
+  rt.queue.push_back(q);
+}
+
+void Manager::respond(int r, uint64_t ticket, uint32_t kernel_id, int status, const Job* j, uint64_t t_submit) {
+  RankSlot* s = ctl_slot(ctl_, r);
+  Response resp{};
+  resp.ticket = ticket;
+  resp.status = status;
+  resp.kernel_id = kernel_id;
+  resp.t_submit_ns = t_submit;
+  if (j) {
+    resp.t_admit_ns = j->t_admit_ns;
+    resp.t_launch_ns = j->t_launch_ns;
+    resp.t_device_ns = j->t_device_ns;
+  }
+  resp.t_done_ns = now_ns();
+  // The rank keeps at most kRingCap - 1 requests outstanding, so there is
+  // always room for a response; spin briefly if the rank is slow to drain.
+  int tries = 0;
+  while (!s->resp.push(resp)) {
+    if (++tries > 1000000) return;  // rank is gone; drop
+    sched_yield();
+  }
+  std::atomic_thread_fence(std::memory_order_seq_cst);
+  s->resp_bell.fetch_add(1, std::memory_order_seq_cst);
+  if (s->rank_sleeping.load(std::memory_order_seq_cst)) futex_wake_all(&s->resp_bell);
+  if (kernel_id >= GVM_K_VECADD && kernel_id <= GVM_K_VECMUL) {
+    std::lock_guard<std::mutex> lk(stats_mu_);
+    if (status == GVM_OK) {
+      ++n_done_;
+      auto& v = lat_us_[kernel_id];
+      if (v.size() < (1u << 20)) v.push_back((resp.t_done_ns - t_submit) * 1e-3);
+      if (j && wait_us_.size() < (1u << 20)) wait_us_.push_back((j->t_admit_ns - t_submit) * 1e-3);
+    } else {
+      ++n_err_;
+    }
+  }
+}
+
+void Manager::release_slot(int r) {
+  RankRt& rt = ranks_[r];
+  if (rt.has_slot) arena_.release(rt.slot_off, rt.slot_size);
+  rt.has_slot = false;
+  rt.slot_off = rt.slot_size = 0;
+  rt.res_valid = false;
+}
+
+// A rank process died: drop its queue, free its memory once its device work
+// is done, and free its slot for a new attach.
+void Manager::reap_rank(int r) {
+  RankRt& rt = ranks_[r];
+  rt.queue.clear();
+  if (rt.running) return;  // finish the device work first; complete_jobs calls back
+  release_slot(r);
+  rt = RankRt{};
+  RankSlot* s = ctl_slot(ctl_, r);
+  Request m;
+  while (s->req.pop(&m)) {
+  }
+  s->pid.store(0, std::memory_order_relaxed);
+  s->state.store(kSlotFree, std::memory_order_release);
+}
+
+void Manager::check_liveness() {
+  const uint64_t now = now_ns();
+  if (now - last_liveness_ns_ < 5000000) return;
+  last_liveness_ns_ = now;
+  const int32_t self = getpid();
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    RankSlot* s = ctl_slot(ctl_, r);
+    RankRt& rt = ranks_[r];
+    const uint32_t st = s->state.load(std::memory_order_acquire);
+    if (st == kSlotFree) continue;
+    const int32_t pid = rt.attached ? rt.pid : s->pid.load(std::memory_order_acquire);
+    if (pid == 0 || pid == self) continue;
+    if (!pid_alive(pid)) reap_rank(static_cast<int>(r));
+  }
+}
+
+bool Manager::complete_jobs() {
+  bool any = false;
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    RankRt& rt = ranks_[r];
+    Job* j = rt.running;
+    if (!j) continue;
+    const int q = dev_->query(j);
+    if (q == 0) continue;
+    dev_->finish(j);
+    const bool alive = rt.attached;
+    if (alive) respond(static_cast<int>(r), j->req.ticket, j->req.kernel_id, j->status, j, j->req.t_submit_ns);
+    if (j->status != GVM_OK) rt.res_valid = false;
+    rt.running = nullptr;
+    rt.last_use_ns = now_ns();
+    delete j;
+    --inflight_;
+    any = true;
+    if (!alive || (rt.attached && !pid_alive(rt.pid) && rt.pid != getpid())) reap_rank(static_cast<int>(r));
+  }
+  if (any) {
+    std::lock_guard<std::mutex> lk(stats_mu_);
+    const KernelStats* ks = dev_->kernel_stats();
+    for (int k = 0; k < 5; ++k) kstats_[k] = ks[k];
+    peak_bytes_ = std::max(peak_bytes_, arena_.peak());
+  }
+  if (cfg_.mode == GVM_MODE_BATCH && batch_open_ && inflight_ == 0) batch_open_ = false;
+  return any;
+}
+
+Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
+  RankRt& rt = ranks_[r];
+  const Queued& q = rt.queue.front();
+  const Request& m = q.req;
+  Layout lay;
+  request_layout(static_cast<int>(m.kernel_id), m.n, &lay);
+  const uint64_t need = slot_bytes(lay);
+  if (m.flags & GVM_F_IN_RESIDENT) {
+    if (!(rt.res_valid && rt.res_kernel == m.kernel_id && rt.res_n == m.n && rt.has_slot)) {
+      respond(r, m.ticket, m.kernel_id, fail(GVM_ESTATE, "no resident input for this request"), nullptr, m.t_submit_ns);
+      rt.queue.pop_front();
+      return kRejected;
+    }
+  }
+  if (!(rt.has_slot && rt.slot_size >= need)) {
+    release_slot(r);
+    uint64_t off = 0;
+    while (!arena_.alloc(need, &off)) {
+      // evict the least recently used idle rank's resident buffer
+      int victim = -1;
+      for (uint32_t v = 0; v < cfg_.nranks; ++v) {
+        const RankRt& o = ranks_[v];
+        if (static_cast<int>(v) == r || !o.has_slot || o.running) continue;
+        if (victim < 0 || o.last_use_ns < ranks_[victim].last_use_ns) victim = static_cast<int>(v);
+      }
+      if (victim < 0) return kWait;
+      release_slot(victim);
+    }
+    rt.has_slot = true;
+    rt.slot_off = off;
+    rt.slot_size = Arena::round(need);
+  }
+  uint8_t* pin = nullptr;
+  const bool copy_in = !(m.flags & GVM_F_IN_RESIDENT);
+  const bool copy_out = !(m.flags & GVM_F_OUT_RESIDENT);
+  if (copy_in || copy_out) {
+    pin = dev_->staging(r);
+    if (!pin) {
+      respond(r, m.ticket, m.kernel_id, GVM_EDEVICE, nullptr, m.t_submit_ns);
+      rt.queue.pop_front();
+      return kRejected;
+    }
+  }
+  Job* j = new Job;
+  j->rank = r;
+  j->req = m;
+  j->lay = lay;
+  j->shm = static_cast<uint8_t*>(data_[r]->addr);
+  j->slot = dev_->arena() + rt.slot_off;
+  j->pin = pin;
+  j->copy_in = copy_in;
+  j->copy_out = copy_out;
+  j->t_admit_ns = now_ns();
+  rt.queue.pop_front();
+  rt.running = j;
+  rt.res_valid = true;
+  rt.res_kernel = m.kernel_id;
+  rt.res_n = m.n;
+  ++inflight_;
+  jobs.push_back(j);
+  return kAdmitted;
+}
+
+int Manager::resolve_policy(const std::vector<Job*>& jobs) const {
+  if (cfg_.policy != GVM_POLICY_AUTO) return static_cast<int>(cfg_.policy);
+  // Resident requests (no copies) are pure kernel work: one grouped launch.
+  // With copies every kernel here is I/O-intensive on this GPU by the test of
+  // Section 4.2.3 (PCIe time exceeds kernel time), so the paper's rule gives
+  // PS-2, which overlaps each rank's copies with the others' kernels.
+  bool copies = false;
+  for (const Job* j : jobs) copies |= j->copy_in || j->copy_out;
+  return copies ? GVM_POLICY_PS2 : GVM_POLICY_GROUPED;
+}
+
+bool Manager::schedule() {
+  bool any = false;
+  // Heads that were invalid on arrival are answered in order.
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    RankRt& rt = ranks_[r];
+    while (!rt.running && !rt.queue.empty() && rt.queue.front().status != GVM_OK) {
+      const Queued q = rt.queue.front();
+      rt.queue.pop_front();
+      respond(static_cast<int>(r), q.req.ticket, q.req.kernel_id, q.status, nullptr, q.req.t_submit_ns);
+      any = true;
+    }
+    if (rt.detach_pending && rt.queue.empty() && !rt.running) {
+      release_slot(static_cast<int>(r));
+      const uint64_t t = rt.detach_ticket;
+      rt = RankRt{};
+      respond(static_cast<int>(r), t, kMsgDetach, GVM_OK, nullptr, now_ns());
+      any = true;
+    }
+  }
+
+  // Candidate heads in global arrival order.
+  std::vector<std::pair<uint64_t, int>> heads;
+  size_t live = 0;
+  uint64_t oldest = UINT64_MAX;
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    const RankRt& rt = ranks_[r];
+    if (!rt.attached) continue;
+    ++live;
+    if (rt.running || rt.queue.empty()) continue;
+    heads.emplace_back(rt.queue.front().seq, static_cast<int>(r));
+    oldest = std::min(oldest, rt.queue.front().t_arrive_ns);
+  }
+  if (heads.empty()) return any;
+  std::sort(heads.begin(), heads.end());
+
+  std::vector<Job*> jobs;
+  if (cfg_.mode == GVM_MODE_BATCH) {
+    // Request barrier (Section 5): run when every attached rank has a
+    // request, or when the window since the oldest one has passed.
+    if (batch_open_) return any;
+    const bool all = heads.size() >= live;
+    const bool expired = now_ns() - oldest >= static_cast<uint64_t>(cfg_.batch_window_us) * 1000ull;
+    if (!all && !expired) return any;
+    for (auto& h : heads) {
+      Admit a = admit(h.second, jobs);
+      if (a == kRejected) any = true;
+    }
+  } else {
+    for (auto& h : heads) {
+      if (inflight_ >= cfg_.max_inflight) break;
+      Admit a = admit(h.second, jobs);
+      if (a == kWait) break;  // first-come first-served: nobody overtakes a waiting head
+      if (a == kRejected) any = true;
+    }
+  }
+  if (jobs.empty()) return any;
+  const int policy = resolve_policy(jobs);
+  dev_->launch(jobs, policy);
+  {
+    std::lock_guard<std::mutex> lk(stats_mu_);
+    ++n_batches_;
+  }
+  if (cfg_.mode == GVM_MODE_BATCH) batch_open_ = true;
+  return true;
+}
+
+int Manager::shutdown() {
+  if (!started_) return GVM_OK;
+  stop_.store(true, std::memory_order_release);
+  ctl_->bell.fetch_add(1);
+  futex_wake_all(&ctl_->bell);
+  thread_.join();
+  started_ = false;
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    while (ranks_[r].running) {  // not reached: the service loop drained
+      delete ranks_[r].running;
+      ranks_[r].running = nullptr;
+    }
+  }
+  dev_.reset();
+  data_.clear();
+  ctl_ = nullptr;
+  ctl_seg_.close();
+  return GVM_OK;
+}
+
+namespace {
+double pct(std::vector<double> v, double p) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  size_t rank = static_cast<size_t>(std::ceil(p / 100.0 * v.size()));
+  if (rank < 1) rank = 1;
+  return v[rank - 1];
+}
+}  // namespace
+
+int Manager::stats_json(std::string* out) {
+  if (!started_) return fail(GVM_ESTATE, "no manager runs in this process");
+  std::lock_guard<std::mutex> lk(stats_mu_);
+  char buf[512];
+  std::string s = "{";
+  s += "\"namespace\":\"" + ns_ + "\",\"device\":" + dev_->describe();
+  snprintf(buf, sizeof(buf), ",\"requests_done\":%llu,\"requests_failed\":%llu,\"batches\":%llu,\"peak_device_bytes\":%llu,\"arena_bytes\":%llu",
+           (unsigned long long)n_done_, (unsigned long long)n_err_, (unsigned long long)n_batches_,
+           (unsigned long long)std::max(peak_bytes_, arena_.peak()), (unsigned long long)arena_.total());
+  s += buf;
+  s += ",\"kernels\":{";
+  bool first = true;
+  for (int k = 1; k < 5; ++k) {
+    const KernelStats& ks = kstats_[k];
+    std::vector<double> all = lat_us_[k];
+    snprintf(buf, sizeof(buf),
+             "%s\"%s\":{\"launches\":%llu,\"requests\":%llu,\"device_ms\":%.6f,\"work_flop\":%.6e,\"work_bytes\":%.6e,"
+             "\"latency_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f,\"max\":%.3f}}",
+             first ? "" : ",", kernel_name(k), (unsigned long long)ks.launches, (unsigned long long)ks.requests,
+             ks.device_ms, ks.work_flop, ks.work_bytes, all.size(), pct(all, 50), pct(all, 99), pct(all, 100));
+    s += buf;
+    first = false;
+  }
+  s += "}";
+  snprintf(buf, sizeof(buf), ",\"admit_wait_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f,\"max\":%.3f}}", wait_us_.size(),
+           pct(wait_us_, 50), pct(wait_us_, 99), pct(wait_us_, 100));
+  s += buf;
+  *out = s;
+  return GVM_OK;
+}
+
+void Manager::reset_stats() {
+  std::lock_guard<std::mutex> lk(stats_mu_);
+  n_done_ = n_err_ = n_batches_ = 0;
+  for (auto& v : lat_us_) v.clear();
+  wait_us_.clear();
+  for (auto& k : kstats_) k = KernelStats{};
+  peak_bytes_ = 0;
+  // the device counters are reset on the service thread's next completion
+  reset_pending_.store(true);
+}
+
+}  // namespace gvm

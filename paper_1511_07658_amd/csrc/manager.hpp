@@ -1,0 +1,111 @@
+// The GPU virtualization manager (GVM) run-time of Section 5: owns the only
+// device context, the per-rank shared-memory spaces and request/response
+// rings, and serves the ranks' requests on the device.
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <deque>
+#include <future>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "device.hpp"
+#include "shm.hpp"
+
+namespace gvm {
+
+// First-fit allocator of offsets inside the device arena (the HBM budget).
+class Arena {
+ public:
+  void init(uint64_t bytes);
+  bool alloc(uint64_t bytes, uint64_t* off);
+  void release(uint64_t off, uint64_t bytes);
+  uint64_t total() const { return total_; }
+  uint64_t used() const { return used_; }
+  uint64_t peak() const { return peak_; }
+  void reset_peak() { peak_ = used_; }
+  static uint64_t round(uint64_t bytes) { return (bytes + 4095) / 4096 * 4096; }
+
+ private:
+  std::map<uint64_t, uint64_t> free_;  // offset -> bytes
+  uint64_t total_ = 0, used_ = 0, peak_ = 0;
+};
+
+class Manager {
+ public:
+  int init(const gvm_config& cfg);
+  int shutdown();
+  int stats_json(std::string* out);
+  void reset_stats();
+  bool running() const { return started_; }
+
+ private:
+  struct Queued {
+    uint64_t seq;
+    uint64_t t_arrive_ns;
+    int status;  // GVM_OK, or an error to report when it reaches the head
+    Request req;
+  };
+  struct RankRt {
+    bool attached = false;
+    int32_t pid = 0;
+    std::deque<Queued> queue;
+    Job* running = nullptr;
+    bool has_slot = false;
+    uint64_t slot_off = 0;
+    uint64_t slot_size = 0;
+    bool res_valid = false;     // the slot holds the input of (res_kernel, res_n)
+    uint32_t res_kernel = 0;
+    uint64_t res_n = 0;
+    uint64_t last_use_ns = 0;
+    bool detach_pending = false;
+    uint64_t detach_ticket = 0;
+  };
+  enum Admit { kAdmitted, kWait, kRejected };
+
+  void service(std::promise<int>* ready);
+  bool drain_rings();
+  void on_message(int r, const Request& m);
+  bool complete_jobs();
+  bool schedule();
+  Admit admit(int r, std::vector<Job*>& jobs);
+  void respond(int r, uint64_t ticket, uint32_t kernel_id, int status, const Job* j, uint64_t t_submit);
+  void release_slot(int r);
+  void reap_rank(int r);
+  void check_liveness();
+  bool any_request_waiting() const;
+  int resolve_policy(const std::vector<Job*>& jobs) const;
+
+  gvm_config cfg_{};
+  std::string ns_;
+  Segment ctl_seg_;
+  CtlHeader* ctl_ = nullptr;
+  std::vector<std::unique_ptr<Segment>> data_;
+  std::unique_ptr<Device> dev_;
+  Arena arena_;
+  std::vector<RankRt> ranks_;
+  std::thread thread_;
+  std::atomic<bool> stop_{false};
+  bool started_ = false;
+  uint64_t seq_ = 0;
+  size_t inflight_ = 0;
+  bool batch_open_ = false;        // batch mode: a batch is on the device
+  uint64_t last_liveness_ns_ = 0;
+  std::atomic<bool> reset_pending_{false};
+  std::string open_error_;
+
+  // statistics (guarded by stats_mu_)
+  std::mutex stats_mu_;
+  uint64_t n_done_ = 0, n_err_ = 0, n_batches_ = 0;
+  std::vector<double> lat_us_[5];      // submit -> result posted, per kernel id
+  std::vector<double> wait_us_;        // submit -> admitted
+  KernelStats kstats_[5];
+  uint64_t peak_bytes_ = 0;
+};
+
+}  // namespace gvm

@@ -1,0 +1,292 @@
+"""Parity of the HIP path with the CPU oracle, through the C-ABI.
+
+Bars: vector add / multiply bit-exact; Black-Scholes relative L2 error of
+each output vector <= 1e-5 (plus a per-element diagnostic and put-call
+parity on the GPU output); SGEMM relative Frobenius error <= 1e-4 against
+the float64 oracle, and bit-exact on small-integer inputs (every partial sum
+is an exactly representable integer).  Virtualisation must not change a
+rank's bytes: alone, in the mix, under every policy and in the plain
+per-process path the outputs are identical.
+"""
+
+import contextlib
+import os
+import threading
+
+import numpy as np
+import pytest
+
+from oracle import kernels as ok
+from paper_1511_07658_amd import gvm as G
+from paper_1511_07658_amd import spmd
+from paper_1511_07658_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+R32 = float(np.float32(wl.BS_RATE))
+V32 = float(np.float32(wl.BS_VOLATILITY))
+
+
+@contextlib.contextmanager
+def hip_manager(name, **kw):
+    base = dict(nranks=8, shm_bytes_per_rank=64 << 20, hbm_budget_bytes=4 << 30, batch_window_us=20000, name=name)
+    base.update(kw)
+    cfg = G.gvm_config_default(**base)
+    G.check(G.gvm_init(cfg), "gvm_init")
+    try:
+        yield cfg
+    finally:
+        G.gvm_shutdown()
+
+
+def run_ranks(ns, jobs_by_rank, zero_copy=False):
+    """Each rank (a thread) runs its job list; returns the per-rank results."""
+    out = [None] * len(jobs_by_rank)
+
+    def body(r):
+        out[r] = spmd.rank_program(ns, r, jobs_by_rank[r], True, zero_copy)
+
+    ths = [threading.Thread(target=body, args=(r,)) for r in range(len(jobs_by_rank)) if jobs_by_rank[r]]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    return out
+
+
+def check_ok(res):
+    assert res["attach"] == 0, res
+    for jr in res["results"]:
+        assert jr["status"] == 0, jr
+    return [jr["out"] for jr in res["results"]]
+
+
+# ------------------------------------------------------------------ checks
+
+def assert_vecadd(out, cfg, rank, n, req=0, mul=False):
+    a, b = wl.vecadd_inputs(cfg, rank, n, req)
+    ref = ok.vecmul_f32(a, b) if mul else ok.vecadd_f32(a, b)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), f"rank {rank} n {n}: not bit-exact"
+
+
+def assert_bs(out, cfg, rank, n, req=0):
+    S, K, T = wl.bs_inputs(cfg, rank, n, req)
+    call, put = ok.black_scholes_f64(S, K, T, R32, V32)
+    gc, gp = out[:n].astype(np.float64), out[n:].astype(np.float64)
+    for got, ref, name in ((gc, call, "call"), (gp, put, "put")):
+        rel = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+        assert rel <= 1e-5, f"rank {rank} n {n} {name}: relative L2 {rel:.3e}"
+    S64, K64, T64 = (x.astype(np.float64) for x in (S, K, T))
+    dk = K64 * np.exp(-R32 * T64)
+    scale = np.maximum.reduce([np.abs(call), S64, dk])
+    assert np.all(np.abs(gc - call) <= 1e-5 * scale), "per-element call diagnostic"
+    assert np.all(np.abs(gp - put) <= 1e-5 * scale), "per-element put diagnostic"
+    assert np.all(np.abs((gc - gp) - (S64 - dk)) <= 1e-5 * (S64 + K64)), "put-call parity"
+
+
+def assert_sgemm(out, cfg, rank, n, req=0, integer=False):
+    gen = wl.sgemm_int_inputs if integer else wl.sgemm_inputs
+    A, B = gen(cfg, rank, n, req)
+    ref = ok.sgemm_f64(A, B)
+    C = out.reshape(n, n).astype(np.float64)
+    if integer:
+        assert np.array_equal(C, ref), f"rank {rank} n {n}: integer GEMM not exact"
+    else:
+        rel = np.linalg.norm(C - ref) / np.linalg.norm(ref)
+        assert rel <= 1e-4, f"rank {rank} n {n}: relative Frobenius {rel:.3e}"
+
+
+# ------------------------------------------------------------------ tests
+
+def test_vecadd_bitexact_ragged(ns_name):
+    sizes = [1, 3, 4, 4095, 4097, 65537, (1 << 20) + 3]
+    with hip_manager(ns_name, nranks=len(sizes)):
+        jobs = [[(1, 11, n, 0, False), (4, 11, n, 1, False)] for n in sizes]
+        res = run_ranks(ns_name, jobs)
+        for r, n in enumerate(sizes):
+            o_add, o_mul = check_ok(res[r])
+            assert_vecadd(o_add, 11, r, n)
+            assert_vecadd(o_mul, 11, r, n, req=1, mul=True)
+
+
+def test_blackscholes_tolerance_ragged(ns_name):
+    sizes = [1, 5, 2047, 2049, 100003, 1 << 20]
+    with hip_manager(ns_name, nranks=len(sizes)):
+        res = run_ranks(ns_name, [[(2, 12, n, 0, False)] for n in sizes])
+        for r, n in enumerate(sizes):
+            (o,) = check_ok(res[r])
+            assert_bs(o, 12, r, n)
+
+
+def test_sgemm_frobenius_ragged(ns_name):
+    sizes = [1, 2, 31, 64, 100, 130, 257, 512]
+    with hip_manager(ns_name, nranks=len(sizes)):
+        res = run_ranks(ns_name, [[(3, 13, n, 0, False)] for n in sizes])
+        for r, n in enumerate(sizes):
+            (o,) = check_ok(res[r])
+            assert_sgemm(o, 13, r, n)
+
+
+def test_sgemm_integer_inputs_bitexact(ns_name):
+    sizes = [7, 64, 100, 257, 1024, 2048]
+    with hip_manager(ns_name, nranks=len(sizes), shm_bytes_per_rank=64 << 20):
+        res = run_ranks(ns_name, [[(3, 14, n, 0, True)] for n in sizes])
+        for r, n in enumerate(sizes):
+            (o,) = check_ok(res[r])
+            assert_sgemm(o, 14, r, n, integer=True)
+
+
+def test_every_tile_configuration(ns_name):
+    # each compiled tile configuration, forced through the plain path
+    for n in (64, 200, 384):
+        A, B = wl.sgemm_inputs(15, 0, n)
+        x = wl.pack_request(3, A, B)
+        outs = []
+        for cfg_idx in range(5):
+            os.environ["GVM_SGEMM_CONFIG"] = str(cfg_idx)
+            try:
+                o = np.empty(n * n, np.float32)
+                rc, _ = G.gvm_plain_run(3, x, o, n)
+                assert rc == 0, G.gvm_last_error()
+            finally:
+                del os.environ["GVM_SGEMM_CONFIG"]
+            assert_sgemm(o, 15, 0, n)
+            outs.append(o)
+
+
+def test_config1_four_ranks_vecadd(ns_name):
+    n = 1 << 20
+    with hip_manager(ns_name, nranks=4, shm_bytes_per_rank=16 << 20):
+        res = run_ranks(ns_name, [[(1, 1, n, 0, False)] for _ in range(4)])
+        for r in range(4):
+            (o,) = check_ok(res[r])
+            assert_vecadd(o, 1, r, n)
+
+
+def test_config2_eight_ranks_sgemm_1024(ns_name):
+    n = 1024
+    with hip_manager(ns_name, nranks=8, shm_bytes_per_rank=16 << 20, policy=G.GVM_POLICY_GROUPED,
+                     batch_window_us=10_000_000):
+        res = run_ranks(ns_name, [[(3, 2, n, 0, False), (3, 2, n, 1, True)] for _ in range(8)])
+        for r in range(8):
+            o, oi = check_ok(res[r])
+            assert_sgemm(o, 2, r, n)
+            assert_sgemm(oi, 2, r, n, req=1, integer=True)
+        st = G.gvm_stats_json()
+        assert st["kernels"]["sgemm"]["requests"] == 16
+        assert st["kernels"]["sgemm"]["launches"] == 2   # one grouped launch per batch
+
+
+def test_config3_sixteen_ranks_blackscholes_4m(ns_name):
+    n = 4 << 20
+    with hip_manager(ns_name, nranks=16, shm_bytes_per_rank=80 << 20, hbm_budget_bytes=8 << 30,
+                     policy=G.GVM_POLICY_GROUPED, batch_window_us=10_000_000):
+        res = run_ranks(ns_name, [[(2, 3, n, 0, False)] for _ in range(16)])
+        for r in range(16):
+            (o,) = check_ok(res[r])
+            assert_bs(o, 3, r, n)
+        st = G.gvm_stats_json()
+        assert st["kernels"]["blackscholes"]["launches"] == 1
+
+
+def _jobs_mix(r):
+    k = [1, 2, 3, 4][r % 4]
+    n = {1: 300001 + r, 2: 70001 + r, 3: 96 + 64 * (r % 3) + r, 4: 5000 + r}[k]
+    return [(k, 21, n, 0, False)]
+
+
+@pytest.mark.parametrize("policy", [G.GVM_POLICY_PS1, G.GVM_POLICY_PS2, G.GVM_POLICY_GROUPED, G.GVM_POLICY_AUTO])
+def test_alone_equals_mix_equals_plain(ns_name, policy):
+    nr = 8
+    mixed = {}
+    with hip_manager(ns_name + f"p{policy}", nranks=nr, policy=policy):
+        res = run_ranks(ns_name + f"p{policy}", [_jobs_mix(r) for r in range(nr)])
+        for r in range(nr):
+            mixed[r] = res[r]["results"][0]
+            assert mixed[r]["status"] == 0
+    with hip_manager(ns_name + f"a{policy}", nranks=nr, policy=policy):
+        for r in range(nr):  # one rank at a time: alone on the device
+            res = run_ranks(ns_name + f"a{policy}", [(_jobs_mix(r) if q == r else []) for q in range(nr)])
+            assert res[r]["results"][0]["digest"] == mixed[r]["digest"], f"rank {r} differs alone vs mix"
+    for r in range(nr):
+        (k, cfg, n, req, integer), = _jobs_mix(r)
+        x = spmd.make_input(k, cfg, r, n, req, integer)
+        o = np.empty(G.out_elems(k, n), np.float32)
+        rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
+        assert rc == 0, G.gvm_last_error()
+        assert spmd.digest(o) == mixed[r]["digest"], f"rank {r} differs plain vs GVM"
+
+
+def test_resident_buffers(ns_name):
+    n = 1024
+    with hip_manager(ns_name, nranks=2, policy=G.GVM_POLICY_GROUPED):
+        errs = []
+
+        def rank(r):
+            try:
+                assert G.gvm_attach_ns(ns_name, r) == 0
+                A, B = wl.sgemm_inputs(31, r, n)
+                out = np.empty(n * n, np.float32)
+                t = G.gvm_submit(r, 3, wl.pack_request(3, A, B), out, n)
+                assert G.gvm_wait(r, t, 60_000_000_000) == 0
+                first = out.copy()
+                assert_sgemm(first, 31, r, n)
+                for _ in range(3):
+                    t = G.gvm_submit_ex(r, 3, None, None, n, G.GVM_F_IN_RESIDENT | G.GVM_F_OUT_RESIDENT)
+                    assert G.gvm_wait(r, t, 60_000_000_000) == 0
+                out[:] = 0
+                t = G.gvm_submit_ex(r, 3, None, out, n, G.GVM_F_IN_RESIDENT)
+                assert G.gvm_wait(r, t, 60_000_000_000) == 0
+                assert np.array_equal(out, first)
+                assert G.gvm_detach(r) == 0
+            except AssertionError as e:
+                errs.append((r, str(e)))
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(2)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+
+
+def test_forked_rank_processes_gpu(ns_name):
+    jobs = [(1, 41, 100003, 0, False), (2, 41, 50001, 0, False), (3, 41, 200, 0, False)]
+    with hip_manager(ns_name, nranks=4):
+        res = spmd.run_processes(spmd.rank_program, [(ns_name, r, jobs, True) for r in range(4)], timeout_s=120)
+    for r in range(4):
+        o1, o2, o3 = check_ok(res[r])
+        assert_vecadd(o1, 41, r, 100003)
+        assert_bs(o2, 41, r, 50001)
+        assert_sgemm(o3, 41, r, 200)
+
+
+def test_serving_mix_matches_alone(ns_name):
+    # continuous admission under a small budget (forces eviction); every
+    # result equals the plain (alone) result byte for byte
+    nr = 8
+    jobs = {r: [((r + i) % 3 + 1, 51, [70001, 30001, 160][(r + i) % 3] + 7 * i, i, False) for i in range(6)]
+            for r in range(nr)}
+    with hip_manager(ns_name, nranks=nr, mode=G.GVM_MODE_SERVING, hbm_budget_bytes=6 << 20, max_inflight=4):
+        res = run_ranks(ns_name, [jobs[r] for r in range(nr)])
+        st = G.gvm_stats_json()
+    assert st["peak_device_bytes"] <= 6 << 20
+    for r in range(nr):
+        assert res[r]["attach"] == 0
+        for (k, cfg, n, req, integer), jr in zip(jobs[r], res[r]["results"]):
+            assert jr["status"] == 0, jr
+            x = spmd.make_input(k, cfg, r, n, req, integer)
+            o = np.empty(G.out_elems(k, n), np.float32)
+            rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
+            assert rc == 0
+            assert spmd.digest(o) == jr["digest"], (r, k, n)
+
+
+def test_request_larger_than_budget(ns_name):
+    with hip_manager(ns_name, nranks=1, hbm_budget_bytes=8 << 20, shm_bytes_per_rank=64 << 20):
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        n = 1 << 20  # 12 MiB of device buffers > 8 MiB budget
+        x = np.zeros(2 * n, np.float32)
+        o = np.zeros(n, np.float32)
+        t = G.gvm_submit(0, 1, x, o, n)
+        assert t > 0
+        assert G.gvm_wait(0, t, 10_000_000_000) == G.GVM_ENOMEM
+        G.gvm_detach(0)

@@ -1,0 +1,333 @@
+"""Host logic of the manager on the loopback backend (no GPU, no kernel
+arithmetic): C-ABI exports, shared-memory rings and allocator, request
+barrier, admission under a device-memory budget, rank and manager failure.
+
+The loopback backend copies each request's first out_bytes of input to its
+output, which lets these tests check routing: every rank must get back its
+own bytes."""
+
+import ctypes
+import glob
+import os
+import signal
+import subprocess
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import serving as sv
+from paper_1511_07658_amd import gvm as G
+from paper_1511_07658_amd import spmd
+
+
+def loop_cfg(name, **kw):
+    base = dict(nranks=4, shm_bytes_per_rank=4 << 20, hbm_budget_bytes=64 << 20,
+                backend=G.GVM_BACKEND_LOOPBACK, batch_window_us=1000, name=name)
+    base.update(kw)
+    return G.gvm_config_default(**base)
+
+
+class Manager:
+    def __init__(self, name, **kw):
+        self.cfg = loop_cfg(name, **kw)
+
+    def __enter__(self):
+        G.check(G.gvm_init(self.cfg), "gvm_init")
+        return self
+
+    def __exit__(self, *a):
+        G.gvm_shutdown()
+
+
+def expect_loopback(kernel_id, inp, n):
+    return inp[: G.out_elems(kernel_id, n)] if inp.size >= G.out_elems(kernel_id, n) else \
+        np.concatenate([inp, np.zeros(G.out_elems(kernel_id, n) - inp.size, np.float32)])
+
+
+def test_library_exports_every_header_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", G.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    declared = G.header_symbols()
+    assert declared, "no declarations found in include/gvm.h"
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    G.lib()  # loads and binds every symbol
+
+
+def test_config_struct_matches_c_layout():
+    cfg = G.gvm_config_default()
+    assert cfg.size == ctypes.sizeof(G.gvm_config)
+    assert cfg.nranks == 8 and abs(cfg.bs_rate - 0.02) < 1e-7 and abs(cfg.bs_volatility - 0.30) < 1e-7
+
+
+def test_bad_config_rejected(ns_name):
+    assert G.gvm_init(loop_cfg(ns_name, nranks=0)) == G.GVM_EINVAL
+    assert G.gvm_init(loop_cfg(ns_name, hbm_budget_bytes=1000)) == G.GVM_EINVAL
+    cfg = loop_cfg(ns_name)
+    cfg.size = 7
+    assert G.gvm_init(cfg) == G.GVM_EINVAL
+
+
+def test_threads_get_their_own_data_back(ns_name):
+    with Manager(ns_name, nranks=4):
+        errs = []
+
+        def rank(r):
+            assert G.gvm_attach_ns(ns_name, r) == 0
+            for i, (k, n) in enumerate([(1, 1), (1, 4097), (2, 333), (3, 17), (4, 5)]):
+                inp = (np.arange(G.in_elems(k, n), dtype=np.float32) + 1000 * r + 10 * i)
+                out = np.full(G.out_elems(k, n), -1, np.float32)
+                t = G.gvm_submit(r, k, inp, out, n)
+                if t < 0 or G.gvm_wait(r, t, 5_000_000_000) != 0:
+                    errs.append((r, i, G.gvm_last_error()))
+                elif not np.array_equal(out, expect_loopback(k, inp, n)):
+                    errs.append((r, i, "wrong bytes"))
+            assert G.gvm_detach(r) == 0
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(4)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+
+
+def test_ring_wraparound_and_many_outstanding(ns_name):
+    # more requests in flight than ring entries, sizes that wrap the allocator
+    with Manager(ns_name, nranks=1, mode=G.GVM_MODE_SERVING, shm_bytes_per_rank=1 << 20):
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        tickets, outs, ins = [], [], []
+        for i in range(300):
+            n = 1000 + (i * 7919) % 20000
+            inp = np.full(2 * n, float(i), np.float32)
+            out = np.zeros(n, np.float32)
+            t = G.gvm_submit(0, G.GVM_K_VECADD, inp, out, n)
+            assert t == i + 1, (t, G.gvm_last_error())
+            tickets.append(t); outs.append(out); ins.append(inp)
+        assert G.gvm_wait(0, -1, 10_000_000_000) == 0
+        for i, out in enumerate(outs):
+            assert np.all(out == float(i))
+        assert G.gvm_detach(0) == 0
+
+
+def test_nonblocking_submit_reports_eagain(ns_name):
+    # batch mode with two ranks: rank 0's requests wait for the barrier
+    with Manager(ns_name, nranks=2, batch_window_us=2_000_000):
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        assert G.gvm_attach_ns(ns_name, 1) == 0
+        inp = np.ones(8, np.float32)
+        outs = [np.zeros(4, np.float32) for _ in range(70)]
+        got = []
+        for o in outs:
+            t = G.gvm_submit_ex(0, G.GVM_K_VECADD, inp, o, 4, G.GVM_F_NONBLOCK)
+            got.append(t)
+            if t == G.GVM_EAGAIN:
+                break
+        assert got[-1] == G.GVM_EAGAIN and len(got) == 64  # ring capacity - 1 outstanding
+        assert G.gvm_wait(0, -1, 10_000_000_000) == 0       # the window expires, all run
+        G.gvm_detach(0)
+        G.gvm_detach(1)
+
+
+def test_batch_barrier_holds_until_all_ranks_submit(ns_name):
+    with Manager(ns_name, nranks=2, batch_window_us=5_000_000):
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        assert G.gvm_attach_ns(ns_name, 1) == 0
+        inp = np.ones(8, np.float32)
+        o0, o1 = np.zeros(4, np.float32), np.zeros(4, np.float32)
+        t0 = G.gvm_submit(0, 1, inp, o0, 4)
+        assert G.gvm_wait(0, t0, 200_000_000) == G.GVM_ETIMEDOUT  # barrier not reached
+        t1 = G.gvm_submit(1, 1, inp, o1, 4)
+        st0, ts0 = G.gvm_wait_timed(0, t0, 5_000_000_000)
+        st1, ts1 = G.gvm_wait_timed(1, t1, 5_000_000_000)
+        assert st0 == 0 and st1 == 0
+        assert abs(int(ts0[1]) - int(ts1[1])) < 50_000_000  # admitted together
+        assert ts0[0] <= ts0[1] <= ts0[2] <= ts0[3] <= ts0[4]
+        G.gvm_detach(0)
+        G.gvm_detach(1)
+
+
+def test_invalid_requests(ns_name):
+    with Manager(ns_name, nranks=1, shm_bytes_per_rank=1 << 20):
+        x = np.zeros(16, np.float32)
+        assert G.gvm_submit(0, 1, x, x, 4) == G.GVM_ESTATE          # not attached
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        assert G.gvm_attach_ns(ns_name, 0) == G.GVM_ESTATE          # twice
+        assert G.gvm_submit(0, 1, x, x, 0) == G.GVM_EINVAL          # n == 0
+        assert G.gvm_submit(0, 99, x, x, 4) == G.GVM_EINVAL         # unknown kernel
+        assert G.gvm_submit(0, 1, None, x, 4) == G.GVM_EINVAL       # no input
+        assert G.gvm_submit(0, 1, x, x, 1 << 20) == G.GVM_ENOMEM    # larger than the space
+        assert G.gvm_submit_ex(0, 1, x, x, 4, 1 << 8) == G.GVM_EINVAL  # unknown flag
+        # resident input that was never uploaded
+        t = G.gvm_submit_ex(0, 1, None, x, 4, G.GVM_F_IN_RESIDENT)
+        assert t > 0 and G.gvm_wait(0, t, 2_000_000_000) == G.GVM_ESTATE
+        assert G.gvm_wait(0, 12345, 1000) == G.GVM_EINVAL            # unknown ticket
+        assert G.gvm_attach_ns(ns_name, 5) == G.GVM_EINVAL           # rank >= nranks
+        G.gvm_detach(0)
+
+
+def test_resident_and_zero_copy(ns_name):
+    with Manager(ns_name, nranks=1):
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        n = 1000
+        view = G.gvm_rank_buffer(0, 3 * n * 4)
+        view[: 2 * n] = np.arange(2 * n, dtype=np.float32)
+        out_view = view[2 * n: 3 * n]
+        t = G.gvm_submit(0, 1, view[: 2 * n], out_view, n)          # zero copy both ways
+        assert G.gvm_wait(0, t, 2_000_000_000) == 0
+        assert np.array_equal(out_view, np.arange(n, dtype=np.float32))
+        out = np.zeros(n, np.float32)
+        t = G.gvm_submit_ex(0, 1, None, out, n, G.GVM_F_IN_RESIDENT)  # reuse the device input
+        assert G.gvm_wait(0, t, 2_000_000_000) == 0
+        assert np.array_equal(out, np.arange(n, dtype=np.float32))
+        t = G.gvm_submit_ex(0, 1, None, None, n, G.GVM_F_IN_RESIDENT | G.GVM_F_OUT_RESIDENT)
+        assert G.gvm_wait(0, t, 2_000_000_000) == 0
+        # a different size invalidates the resident input
+        t = G.gvm_submit_ex(0, 1, None, out, n - 1, G.GVM_F_IN_RESIDENT)
+        assert G.gvm_wait(0, t, 2_000_000_000) == G.GVM_ESTATE
+        G.gvm_detach(0)
+
+
+def test_serving_budget_admission_and_eviction(ns_name):
+    # 8 ranks, budget of 2 MiB: at most a few resident slots; every request
+    # must still complete, with its own data, and the peak stays in budget
+    budget = 2 << 20
+    with Manager(ns_name, nranks=8, mode=G.GVM_MODE_SERVING, hbm_budget_bytes=budget, max_inflight=3):
+        errs, ends = [], []
+
+        def rank(r):
+            assert G.gvm_attach_ns(ns_name, r) == 0
+            for i in range(20):
+                n = 20000 + 1000 * ((r + i) % 7)
+                inp = np.full(2 * n, float(100 * r + i), np.float32)
+                out = np.zeros(n, np.float32)
+                t = G.gvm_submit(r, 1, inp, out, n)
+                st, ts = G.gvm_wait_timed(r, t, 10_000_000_000)
+                if st != 0 or not np.all(out == float(100 * r + i)):
+                    errs.append((r, i, st))
+                ends.append((ts[1], ts[4], (r, t), 2 * 4096 * ((n * 12 + 4095) // 4096)))
+            G.gvm_detach(r)
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(8)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+        st = G.gvm_stats_json()
+        assert st["requests_done"] == 160
+        assert 0 < st["peak_device_bytes"] <= budget
+        # no more than max_inflight requests between admission and completion
+        events = [(a, "admit", k, 1) for a, _, k, _ in ends] + [(d, "complete", k, 1) for _, d, k, _ in ends]
+        assert sv.check_budget(events, 3) <= 3
+        sv.check_lifecycle([k for _, _, k, _ in ends], events)
+
+
+def test_forked_rank_processes(ns_name):
+    with Manager(ns_name, nranks=4):
+        jobs = [(1, 0, 5000, 0, False), (2, 0, 777, 1, False), (3, 0, 33, 2, False)]
+        res = spmd.run_processes(spmd.rank_program, [(ns_name, r, jobs, True) for r in range(4)], timeout_s=60)
+        for r, rr in enumerate(res):
+            assert rr["attach"] == 0 and rr["detach"] == 0
+            for (k, cfg, n, req, integer), jr in zip(jobs, rr["results"]):
+                assert jr["status"] == 0, jr
+                x = spmd.make_input(k, cfg, r, n, req, integer)
+                assert np.array_equal(jr["out"], expect_loopback(k, x, n))
+
+
+def test_forked_ranks_zero_copy(ns_name):
+    with Manager(ns_name, nranks=2):
+        jobs = [(1, 0, 3000, 0, False), (3, 0, 40, 0, False)]
+        res = spmd.run_processes(spmd.rank_program, [(ns_name, r, jobs, True, True) for r in range(2)], timeout_s=60)
+        for r, rr in enumerate(res):
+            for (k, cfg, n, req, integer), jr in zip(jobs, rr["results"]):
+                assert jr["status"] == 0
+                assert np.array_equal(jr["out"], expect_loopback(k, spmd.make_input(k, cfg, r, n, req), n))
+
+
+def _submit_then_hang(ns, rank, ready):
+    assert G.gvm_attach_ns(ns, rank) == 0
+    x = np.ones(8, np.float32)
+    o = np.zeros(4, np.float32)
+    G.gvm_submit(rank, 1, x, o, 4)
+    ready.set()
+    time.sleep(60)
+
+
+def test_dead_rank_is_reclaimed(ns_name):
+    with Manager(ns_name, nranks=2, batch_window_us=30_000_000):
+        ctx = spmd.context()
+        ready = ctx.Event()
+        p = ctx.Process(target=_submit_then_hang, args=(ns_name, 0, ready), daemon=True)
+        p.start()
+        assert ready.wait(20)
+        os.kill(p.pid, signal.SIGKILL)
+        p.join()
+        # the manager notices, drops the request and frees the VGPU
+        deadline = time.time() + 5
+        rc = G.GVM_ESTATE
+        while time.time() < deadline:
+            rc = G.gvm_attach_ns(ns_name, 0)
+            if rc == 0:
+                break
+            time.sleep(0.05)
+        assert rc == 0, G.gvm_last_error()
+        x = np.arange(8, dtype=np.float32)
+        o = np.zeros(4, np.float32)
+        t = G.gvm_submit(0, 1, x, o, 4)
+        # rank 1 is not attached, so the barrier is only rank 0
+        assert G.gvm_wait(0, t, 5_000_000_000) == 0 and np.array_equal(o, x[:4])
+        G.gvm_detach(0)
+
+
+def _manager_process(ns, ready):
+    cfg = loop_cfg(ns, nranks=2, batch_window_us=60_000_000)
+    assert G.gvm_init(cfg) == 0
+    ready.set()
+    time.sleep(120)
+
+
+def test_dead_manager_reported(ns_name):
+    ctx = spmd.context()
+    ready = ctx.Event()
+    p = ctx.Process(target=_manager_process, args=(ns_name, ready), daemon=True)
+    p.start()
+    try:
+        assert ready.wait(20)
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        assert G.gvm_attach_ns(ns_name, 1) == 0
+        x = np.ones(8, np.float32)
+        o = np.zeros(4, np.float32)
+        t = G.gvm_submit(0, 1, x, o, 4)   # held by the barrier (rank 1 silent, long window)
+        assert t > 0
+        assert G.gvm_wait(0, t, 100_000_000) == G.GVM_ETIMEDOUT
+        os.kill(p.pid, signal.SIGKILL)
+        p.join()
+        t0 = time.time()
+        assert G.gvm_wait(0, t, 10_000_000_000) == G.GVM_EDEAD
+        assert time.time() - t0 < 2.0
+        assert G.gvm_detach(0) == 0
+        assert G.gvm_detach(1) == 0
+    finally:
+        if p.is_alive():
+            os.kill(p.pid, signal.SIGKILL)
+        for f in glob.glob(f"/dev/shm/{ns_name}.*"):
+            os.unlink(f)
+
+
+def test_shutdown_removes_shared_memory(ns_name):
+    with Manager(ns_name, nranks=3):
+        assert len(glob.glob(f"/dev/shm/{ns_name}.*")) == 4
+        assert G.gvm_attach_ns(ns_name, 1) == 0
+    assert glob.glob(f"/dev/shm/{ns_name}.*") == []
+    # a second manager in the same process after shutdown
+    with Manager(ns_name, nranks=1):
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        assert G.gvm_init(loop_cfg(ns_name + "x")) == G.GVM_ESTATE  # one manager per process
+
+
+def test_hip_backend_fails_loudly_without_gpu(ns_name):
+    if os.path.exists("/dev/kfd"):
+        pytest.skip("a GPU driver is present")
+    cfg = G.gvm_config_default(nranks=1, shm_bytes_per_rank=1 << 20, hbm_budget_bytes=16 << 20, name=ns_name)
+    assert G.gvm_init(cfg) == G.GVM_EDEVICE
+    assert "HIP" in G.gvm_last_error() or "device" in G.gvm_last_error()
+    assert glob.glob(f"/dev/shm/{ns_name}.*") == []
