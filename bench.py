@@ -38,6 +38,30 @@ from paper_1511_07658_amd import workloads as wl  # noqa: E402
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBPS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE /
+# WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
+# plain 1 GiB copy (fetch x2.000, write x1.000); valid only for the kernel
+# source they were taken on (profiles/sgemm_grouped_8x1024.md).
+MEASURED_TRAFFIC = {
+    "sgemm8": {"kernels_hip_sha256": "2a0ccf4e9380455ada2c7d4cc93d313353274972459332ebf6ebb967c3bb4d22",
+               "fetch_kib": 33068.4, "fetch_factor": 2.000, "write_kib": 32768.0, "write_factor": 1.000},
+}
+
+
+def measured_traffic(workload):
+    """Traffic in bytes per launch, or None if the kernel source changed since
+    the counters were taken."""
+    import hashlib
+
+    m = MEASURED_TRAFFIC.get(workload)
+    if not m:
+        return None
+    src = os.path.join(ROOT, "paper_1511_07658_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != m["kernels_hip_sha256"]:
+            return None
+    return round((m["fetch_kib"] * m["fetch_factor"] + m["write_kib"] * m["write_factor"]) * 1024)
+
 WORKLOADS = {
     # name: (kernel id, ranks, n, config index of the seeded inputs)
     "sgemm8": (G.GVM_K_SGEMM, 8, 1024, 1),
@@ -162,6 +186,8 @@ def main(argv=None):
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--rank-threads", action="store_true",
+                    help="run the ranks as threads of this process (for profilers that cannot follow forks)")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -171,8 +197,13 @@ def main(argv=None):
         return 2
     kernel_id, nranks, n, cfg_idx = WORKLOADS[a.workload]
     flop, byts = work_of(kernel_id, n)
-    spmd.prestart()  # rank processes fork from a GPU-free server
-    ctx = spmd.context()
+    import threading
+
+    if a.rank_threads:
+        a.no_plain = True
+    else:
+        spmd.prestart()  # rank processes fork from a GPU-free server
+    ctx = None if a.rank_threads else spmd.context()
 
     # 1. plain per-process baseline (before this process touches the GPU)
     plain = None
@@ -203,15 +234,25 @@ def main(argv=None):
     log(f"GVM: {nranks} ranks, {a.workload}, n={n}")
     G.check(G.gvm_init(cfg), "gvm_init")
     try:
-        bar = ctx.Barrier(nranks + 1)
-        import threading
-
+        bar = threading.Barrier(nranks + 1) if a.rank_threads else ctx.Barrier(nranks + 1)
         results = {}
+        args = [(ns, r, kernel_id, n, cfg_idx, a.warmup, a.steps, a.e2e_steps, bar) for r in range(nranks)]
 
         def runner():
-            results["r"] = spmd.run_processes(
-                bench_rank, [(ns, r, kernel_id, n, cfg_idx, a.warmup, a.steps, a.e2e_steps, bar) for r in range(nranks)],
-                timeout_s=600)
+            if a.rank_threads:
+                out = [None] * nranks
+
+                def one(r):
+                    out[r] = bench_rank(*args[r])
+
+                ths = [threading.Thread(target=one, args=(r,)) for r in range(nranks)]
+                for t in ths:
+                    t.start()
+                for t in ths:
+                    t.join()
+                results["r"] = out
+            else:
+                results["r"] = spmd.run_processes(bench_rank, args, timeout_s=600)
 
         th = threading.Thread(target=runner)
         th.start()
@@ -238,18 +279,19 @@ def main(argv=None):
         unit = "GFLOP/s"
         achieved = per_launch_work / avg_launch_s / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None}
+                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": measured_traffic(a.workload)}
         e2e_value = nranks * a.e2e_steps * flop / e2e / 1e9
     else:
         value = nranks * a.steps * byts / elapsed / 1e9
         unit = "GB/s"
         achieved = per_launch_work / avg_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None}
+                "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(a.workload)}
         e2e_value = nranks * a.e2e_steps * byts / e2e / 1e9
     roof["kernel"] = f"{kname} grouped launch of {ks['requests'] // launches} requests"
     roof["avg_launch_us"] = round(avg_launch_s * 1e6, 3)
     roof["launches"] = ks["launches"]
+    roof["algorithmic_bytes"] = round(byts * ks["requests"] / launches)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -272,7 +314,8 @@ def main(argv=None):
         "config": {"workload": {"sgemm8": "8 ranks via GVM, FP32 SGEMM 1024x1024 each, grouped MFMA launch, inputs resident in HBM",
                                 "vecadd4": "4 ranks via GVM, FP32 vector add n=2^20 each, inputs resident in HBM",
                                 "bs16": "16 ranks via GVM, FP32 Black-Scholes 4M options each, inputs resident in HBM"}[a.workload],
-                   "ranks": nranks, "n": n, "mode": "batch", "policy": "auto (grouped when resident)"},
+                   "ranks": nranks, "n": n, "mode": "batch", "policy": "auto (grouped when resident)",
+                   "rank_kind": "threads" if a.rank_threads else "processes"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "latency_us": {"p50": ks["latency_us"]["p50"], "p99": ks["latency_us"]["p99"], "count": ks["latency_us"]["count"]},

@@ -177,8 +177,8 @@ __global__ __launch_bounds__(kThreads) void bs_group_kernel(BsGroup g) {
 // is multiplied, then written to the other LDS buffer (one barrier per tile).
 //
 // Persistent grid, XCD-aware: the units (tiles, requests in order, tiles of a
-// request row-major) are cut into 8 contiguous ranges, one per XCD, so that
-// the tiles sharing rows of A and columns of B share an L2.
+// request row-major) are dealt to the 8 XCDs in contiguous blocks, so that
+// tiles sharing rows of A and columns of B share an L2.
 
 template <int BM, int BN, int BK, int WM, int WN, bool VEC>
 __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) {
@@ -203,15 +203,15 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
   const int wm = wave / WN, wn = wave % WN;
   const int li = lane & 31, lg = lane >> 5;
 
+  // XCD-aware order: with G a multiple of 8, workgroup w runs on XCD w % 8;
+  // renumbering it v = (w % 8) * (G / 8) + w / 8 gives each XCD a contiguous
+  // block of units in every round of the stride loop below.
   const uint32_t G = gridDim.x;
   const uint32_t U = g.total_units;
-  const uint32_t xcd = blockIdx.x % kXcds;
-  const uint32_t idx = blockIdx.x / kXcds;
-  const uint32_t gx = (G > xcd) ? (G - xcd + kXcds - 1) / kXcds : 0;  // workgroups on this XCD
-  const uint32_t ubeg = static_cast<uint32_t>((static_cast<uint64_t>(U) * xcd) / kXcds);
-  const uint32_t uend = static_cast<uint32_t>((static_cast<uint64_t>(U) * (xcd + 1)) / kXcds);
+  uint32_t v = blockIdx.x;
+  if (G % kXcds == 0) v = (blockIdx.x % kXcds) * (G / kXcds) + blockIdx.x / kXcds;
 
-  for (uint32_t u = ubeg + idx; u < uend; u += gx) {
+  for (uint32_t u = v; u < U; u += G) {
     const int q = find_request(g, u);
     const GemmDesc& d = g.d[q];
     const int n = static_cast<int>(d.n);
@@ -346,6 +346,7 @@ hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap)
   int cap = grid_cap > 0 ? grid_cap : 256 * 2;
   int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
   if (grid <= 0) return hipSuccess;
+  if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
   if (vec)
     hipLaunchKernelGGL((sgemm_group_kernel<BM, BN, BK, WM, WN, true>), dim3(grid), dim3(NT), 0, s, g);
   else
