@@ -41,9 +41,10 @@ PEAK_HBM_GBPS = 8000.0
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # plain 1 GiB copy (fetch x2.000, write x1.000); valid only for the kernel
-# source they were taken on (profiles/sgemm_grouped_8x1024.md).
+# source and tile table they were taken on (sha256 of csrc/kernels.hip then
+# csrc/gemm_tiles.inc; profiles/sgemm_grouped_8x1024.md).
 MEASURED_TRAFFIC = {
-    "sgemm8": {"kernels_hip_sha256": "2a0ccf4e9380455ada2c7d4cc93d313353274972459332ebf6ebb967c3bb4d22",
+    "sgemm8": {"kernels_sha256": "2a0ccf4e9380455ada2c7d4cc93d313353274972459332ebf6ebb967c3bb4d22",
                "fetch_kib": 33068.4, "fetch_factor": 2.000, "write_kib": 32768.0, "write_factor": 1.000},
 }
 
@@ -56,18 +57,35 @@ def measured_traffic(workload):
     m = MEASURED_TRAFFIC.get(workload)
     if not m:
         return None
-    src = os.path.join(ROOT, "paper_1511_07658_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != m["kernels_hip_sha256"]:
-            return None
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "gemm_tiles.inc"):
+        with open(os.path.join(ROOT, "paper_1511_07658_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != m["kernels_sha256"]:
+        return None
     return round((m["fetch_kib"] * m["fetch_factor"] + m["write_kib"] * m["write_factor"]) * 1024)
 
 WORKLOADS = {
-    # name: (kernel id, ranks, n, config index of the seeded inputs)
-    "sgemm8": (G.GVM_K_SGEMM, 8, 1024, 1),
-    "vecadd4": (G.GVM_K_VECADD, 4, 1 << 20, 0),
-    "bs16": (G.GVM_K_BLACKSCHOLES, 16, 4 << 20, 2),
+    "sgemm8": "8 ranks via GVM, FP32 SGEMM 1024x1024 each, grouped MFMA launch, inputs resident in HBM",
+    "vecadd4": "4 ranks via GVM, FP32 vector add n=2^20 each, inputs resident in HBM",
+    "bs16": "16 ranks via GVM, FP32 Black-Scholes 4M options each, one fused launch, inputs resident in HBM",
+    "mixed32": "32 ranks via GVM with uneven sizes: 16 vector adds n=floor(2^U[16,24]) and 16 SGEMMs "
+               "n in {256..2048 step 64}, tuned tiles, one grouped launch per kernel per step, inputs resident in HBM",
 }
+
+
+def rank_specs(workload):
+    """Per-rank (kernel id, n, config index of the seeded inputs)."""
+    if workload == "sgemm8":
+        return [(G.GVM_K_SGEMM, 1024, 1)] * 8
+    if workload == "vecadd4":
+        return [(G.GVM_K_VECADD, 1 << 20, 0)] * 4
+    if workload == "bs16":
+        return [(G.GVM_K_BLACKSCHOLES, 4 << 20, 2)] * 16
+    if workload == "mixed32":
+        return ([(G.GVM_K_VECADD, n, 3) for n in wl.uneven_vecadd_sizes(3, 16)] +
+                [(G.GVM_K_SGEMM, n, 3) for n in wl.uneven_sgemm_sizes(3, 16)])
+    raise ValueError(workload)
 
 
 def log(msg):
@@ -101,11 +119,20 @@ def bench_rank(ns, rank, kernel_id, n, cfg_idx, warmup, steps, e2e_steps, barrie
         G.check(G.gvm_wait(rank, t, 120_000_000_000), "warmup wait")
     barrier.wait()                       # 2: warm-up done
     barrier.wait()                       # 3: statistics reset, go
-    t0 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
+    clock = time.clock_gettime_ns
+    mono = time.CLOCK_MONOTONIC
+    parts = np.zeros(6)
+    t0 = clock(mono)
+    seen = t0
     for _ in range(steps):
         t = G.check(G.gvm_submit_ex(rank, kernel_id, None, None, n, flags), "step")
-        G.check(G.gvm_wait(rank, t, 120_000_000_000), "step wait")
-    t1 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
+        st, ts = G.gvm_wait_timed(rank, t, 120_000_000_000)
+        G.check(st, "step wait")
+        now = clock(mono)
+        # submit->admit, admit->launch, launch->device done, device->posted, posted->seen, seen->next submit
+        parts += [ts[1] - ts[0], ts[2] - ts[1], ts[3] - ts[2], ts[4] - ts[3], now - ts[4], ts[0] - seen]
+        seen = now
+    t1 = clock(mono)
     barrier.wait()                       # 4: timed steps done
     # PCIe-inclusive steps: copy-in from the rank's shared memory, copy-out back
     barrier.wait()                       # 5: statistics read, go
@@ -116,7 +143,8 @@ def bench_rank(ns, rank, kernel_id, n, cfg_idx, warmup, steps, e2e_steps, barrie
     e1 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
     same = spmd.digest(out) == first
     G.gvm_detach(rank)
-    return {"t0": t0, "t1": t1, "e0": e0, "e1": e1, "same_bytes": same, "digest": first}
+    return {"t0": t0, "t1": t1, "e0": e0, "e1": e1, "same_bytes": same, "digest": first,
+            "parts_ns": (parts / max(steps, 1)).tolist()}
 
 
 def plain_rank(kernel_id, n, cfg_idx, rank, barrier):
@@ -186,6 +214,7 @@ def main(argv=None):
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--graphs", type=int, default=None, help="replay repeated batches as HIP graphs (switched off in this build)")
     ap.add_argument("--rank-threads", action="store_true",
                     help="run the ranks as threads of this process (for profilers that cannot follow forks)")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
@@ -195,8 +224,14 @@ def main(argv=None):
               f"context; --gpus {a.gpus} is not supported (one manager per GPU would shard ranks "
               f"with no exchange step).", file=sys.stderr)
         return 2
-    kernel_id, nranks, n, cfg_idx = WORKLOADS[a.workload]
-    flop, byts = work_of(kernel_id, n)
+    specs = rank_specs(a.workload)
+    if a.graphs is None:
+        a.graphs = 0  # graph replay is switched off in the library
+    nranks = len(specs)
+    kinds = sorted({k for k, _, _ in specs})
+    main_kernel = G.GVM_K_SGEMM if G.GVM_K_SGEMM in kinds else kinds[0]
+    flop_total = sum(work_of(k, n)[0] for k, n, _ in specs)
+    bytes_total = sum(work_of(k, n)[1] for k, n, _ in specs)
     import threading
 
     if a.rank_threads:
@@ -204,39 +239,39 @@ def main(argv=None):
     else:
         spmd.prestart()  # rank processes fork from a GPU-free server
     ctx = None if a.rank_threads else spmd.context()
+    mixed = len(kinds) > 1
 
     # 1. plain per-process baseline (before this process touches the GPU)
     plain = None
-    if not a.no_plain and not a.loopback:
+    if not a.no_plain and not a.loopback and nranks <= 16:
         log(f"plain baseline: {nranks} processes, each its own context")
         bar = ctx.Barrier(nranks)
-        res = spmd.run_processes(plain_rank, [(kernel_id, n, cfg_idx, r, bar) for r in range(nranks)], timeout_s=300)
+        res = spmd.run_processes(plain_rank, [(k, n, c, r, bar) for r, (k, n, c) in enumerate(specs)], timeout_s=300)
         bad = [r for r in res if r["rc"] != 0]
         if bad:
             raise SystemExit(f"plain baseline failed: {bad}")
         turn = (max(r["t1"] for r in res) - min(r["t0"] for r in res)) * 1e-9
         stages = np.array([r["stages"] for r in res])
         plain = {"turnaround_s": round(turn, 6),
-                 "value": round(nranks * (flop if kernel_id == G.GVM_K_SGEMM else byts) / turn / 1e9, 3),
+                 "value": round((flop_total if main_kernel == G.GVM_K_SGEMM else bytes_total) / turn / 1e9, 3),
                  "mean_stage_s": dict(zip(["init", "alloc", "copy_in", "kernel", "copy_out", "free"],
                                           [round(float(v), 6) for v in stages.mean(axis=0)])),
                  "digests": [r["digest"] for r in res]}
 
     # 2. the GVM manager in this process, ranks in forked processes
     ns = f"gvm.bench.{os.getpid()}"
-    in_b = G.in_elems(kernel_id, n) * 4
-    out_b = G.out_elems(kernel_id, n) * 4
-    cfg = G.gvm_config_default(nranks=nranks, shm_bytes_per_rank=in_b + out_b + (1 << 20),
-                               hbm_budget_bytes=max(2 << 30, 2 * nranks * (in_b + out_b)),
+    space = max((G.in_elems(k, n) + G.out_elems(k, n)) * 4 for k, n, _ in specs) + (1 << 20)
+    cfg = G.gvm_config_default(nranks=nranks, shm_bytes_per_rank=space,
+                               hbm_budget_bytes=max(2 << 30, 2 * nranks * space),
                                mode=G.GVM_MODE_BATCH, policy=G.GVM_POLICY_AUTO, batch_window_us=5_000_000,
-                               copy_threads=8, name=ns,
+                               use_graphs=1 if a.graphs else 0, copy_threads=8, name=ns,
                                backend=G.GVM_BACKEND_LOOPBACK if a.loopback else G.GVM_BACKEND_HIP)
-    log(f"GVM: {nranks} ranks, {a.workload}, n={n}")
+    log(f"GVM: {nranks} ranks, {a.workload}")
     G.check(G.gvm_init(cfg), "gvm_init")
     try:
         bar = threading.Barrier(nranks + 1) if a.rank_threads else ctx.Barrier(nranks + 1)
         results = {}
-        args = [(ns, r, kernel_id, n, cfg_idx, a.warmup, a.steps, a.e2e_steps, bar) for r in range(nranks)]
+        args = [(ns, r, k, n, c, a.warmup, a.steps, a.e2e_steps, bar) for r, (k, n, c) in enumerate(specs)]
 
         def runner():
             if a.rank_threads:
@@ -269,34 +304,44 @@ def main(argv=None):
         G.gvm_shutdown()
     elapsed = (max(r["t1"] for r in rr) - min(r["t0"] for r in rr)) * 1e-9
     e2e = (max(r["e1"] for r in rr) - min(r["e0"] for r in rr)) * 1e-9
-    kname = {1: "vecadd", 2: "blackscholes", 3: "sgemm", 4: "vecmul"}[kernel_id]
+    knames = {0: "mixed_graph", 1: "vecadd", 2: "blackscholes", 3: "sgemm", 4: "vecmul"}
+    kname = "mixed_graph" if (mixed and a.graphs and "mixed_graph" in stats["kernels"]) else knames[main_kernel]
     ks = stats["kernels"][kname]
     launches = max(ks["launches"], 1)
     avg_launch_s = max(ks["device_ms"] / launches * 1e-3, 1e-12)
-    per_launch_work = (flop if kernel_id == G.GVM_K_SGEMM else byts) * ks["requests"] / launches
-    if kernel_id == G.GVM_K_SGEMM:
-        value = nranks * a.steps * flop / elapsed / 1e9
+    # the launch of the dominant kernel covers every request of its kind in a step
+    main_specs = [(k, n) for k, n, _ in specs if k == main_kernel]
+    main_flop = sum(work_of(k, n)[0] for k, n in main_specs)
+    main_bytes = sum(work_of(k, n)[1] for k, n in main_specs)
+    if main_kernel == G.GVM_K_SGEMM:
+        value = a.steps * main_flop / elapsed / 1e9
         unit = "GFLOP/s"
-        achieved = per_launch_work / avg_launch_s / 1e12
+        achieved = main_flop / avg_launch_s / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": measured_traffic(a.workload)}
-        e2e_value = nranks * a.e2e_steps * flop / e2e / 1e9
+        e2e_value = a.e2e_steps * main_flop / e2e / 1e9
     else:
-        value = nranks * a.steps * byts / elapsed / 1e9
+        value = a.steps * main_bytes / elapsed / 1e9
         unit = "GB/s"
-        achieved = per_launch_work / avg_launch_s / 1e9
+        achieved = main_bytes / avg_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(a.workload)}
-        e2e_value = nranks * a.e2e_steps * byts / e2e / 1e9
-    roof["kernel"] = f"{kname} grouped launch of {ks['requests'] // launches} requests"
+        e2e_value = a.e2e_steps * main_bytes / e2e / 1e9
+    roof["kernel"] = f"{kname} launch of {ks['requests'] // launches} requests"
     roof["avg_launch_us"] = round(avg_launch_s * 1e6, 3)
     roof["launches"] = ks["launches"]
-    roof["algorithmic_bytes"] = round(byts * ks["requests"] / launches)
+    roof["algorithmic_bytes"] = round(main_bytes)
+    extra = {}
+    if mixed:
+        extra["vecadd_GBps"] = round(a.steps * sum(work_of(k, n)[1] for k, n, _ in specs if k == G.GVM_K_VECADD)
+                                     / elapsed / 1e9, 3)
+        extra["sizes"] = [[k, n] for k, n, _ in specs]
 
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(kernel_id, nranks, n, cfg_idx, a.cpu_seconds)
+        k0, n0, c0 = next(sp for sp in specs if sp[0] == main_kernel)
+        cpu = cpu_baseline(k0, len(main_specs), n0, c0, a.cpu_seconds)
 
     line = {
         "metric": "aggregate GB/s & GFLOP/s, N ranks on 1 GPU, GVM vs plain; p50/p99 req latency",
@@ -311,18 +356,22 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded by rank)",
-        "config": {"workload": {"sgemm8": "8 ranks via GVM, FP32 SGEMM 1024x1024 each, grouped MFMA launch, inputs resident in HBM",
-                                "vecadd4": "4 ranks via GVM, FP32 vector add n=2^20 each, inputs resident in HBM",
-                                "bs16": "16 ranks via GVM, FP32 Black-Scholes 4M options each, inputs resident in HBM"}[a.workload],
-                   "ranks": nranks, "n": n, "mode": "batch", "policy": "auto (grouped when resident)",
+        "config": {"workload": WORKLOADS[a.workload], "name": a.workload,
+                   "ranks": nranks, "mode": "batch", "policy": "auto (grouped when resident)",
+                   "graphs": bool(a.graphs),
                    "rank_kind": "threads" if a.rank_threads else "processes"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "latency_us": {"p50": ks["latency_us"]["p50"], "p99": ks["latency_us"]["p99"], "count": ks["latency_us"]["count"]},
+        "step_breakdown_us": dict(zip(
+            ["barrier_and_drain", "admit_to_launch", "launch_to_device_done", "device_done_to_posted",
+             "posted_to_seen", "rank_loop"],
+            [round(float(x) * 1e-3, 2) for x in np.mean([r["parts_ns"] for r in rr], axis=0)])),
         "e2e_pcie": {"value": round(e2e_value, 3), "unit": unit, "steps": a.e2e_steps,
                      "ms_per_step": round(e2e / max(a.e2e_steps, 1) * 1e3, 3)},
         "plain": None if plain is None else {k: v for k, v in plain.items() if k != "digests"},
         "gvm_vs_plain_turnaround": None if plain is None else round(plain["turnaround_s"] / (e2e / max(a.e2e_steps, 1)), 3),
+        **extra,
         "results_unchanged_by_virtualization": all(r["same_bytes"] for r in rr) and (
             plain is None or [r["digest"] for r in rr] == plain["digests"]),
         "host": {"nproc": os.cpu_count(), "machine": platform.machine(),

@@ -9,6 +9,7 @@
 #include <unistd.h>
 
 #include <climits>
+#include <cstdlib>
 #include <cstring>
 
 namespace gvm {
@@ -74,6 +75,13 @@ int futex_wait(std::atomic<uint32_t>* word, uint32_t expected, int64_t timeout_n
 
 void futex_wake_all(std::atomic<uint32_t>* word) {
   syscall(SYS_futex, reinterpret_cast<uint32_t*>(word), FUTEX_WAKE, INT_MAX, nullptr, nullptr, 0);
+}
+
+uint64_t spin_env_ns(const char* var, uint64_t default_us) {
+  uint64_t us = default_us;
+  if (const char* e = getenv(var)) us = strtoull(e, nullptr, 10);
+  if (us > 100000) us = 100000;
+  return us * 1000ull;
 }
 
 bool pid_alive(int32_t pid) {

@@ -39,6 +39,9 @@ void futex_wake_all(std::atomic<uint32_t>* word);
 
 bool pid_alive(int32_t pid);
 
+// Spin budget (ns) read from an environment variable given in microseconds.
+uint64_t spin_env_ns(const char* var, uint64_t default_us);
+
 inline const char* kernel_name(int k) {
   switch (k) {
     case GVM_K_VECADD: return "vecadd";

@@ -93,6 +93,8 @@ class HipDevice final : public Device {
 
   int launch(std::vector<Job*>& jobs, int policy) override {
     if (jobs.empty()) return GVM_OK;
+    if (policy != GVM_POLICY_PS1 && policy != GVM_POLICY_PS2)
+      std::stable_sort(jobs.begin(), jobs.end(), [](const Job* x, const Job* y) { return x->rank < y->rank; });
     auto* b = new Batch;
     b->jobs = jobs;
     b->done.assign(jobs.size(), nullptr);
@@ -109,7 +111,7 @@ class HipDevice final : public Device {
         hipStream_t s = rank_stream(j->rank);
         std::vector<Job*> one{j};
         rc = enqueue_in(j, s);
-        if (rc == GVM_OK) rc = enqueue_kernels(one, s, b);
+        if (rc == GVM_OK) rc = enqueue_kernels(one, {s}, b, true, nullptr);
         if (rc == GVM_OK) rc = enqueue_out(j, s);
         if (rc == GVM_OK) rc = record_done(b, i, s);
       }
@@ -117,43 +119,15 @@ class HipDevice final : public Device {
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) rc = enqueue_in(jobs[i], rank_stream(jobs[i]->rank));
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         std::vector<Job*> one{jobs[i]};
-        rc = enqueue_kernels(one, rank_stream(jobs[i]->rank), b);
+        rc = enqueue_kernels(one, {rank_stream(jobs[i]->rank)}, b, true, nullptr);
       }
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         hipStream_t s = rank_stream(jobs[i]->rank);
         rc = enqueue_out(jobs[i], s);
         if (rc == GVM_OK) rc = record_done(b, i, s);
       }
-    } else {  // grouped
-      hipStream_t cs = compute_streams_[next_cs_++ % compute_streams_.size()];
-      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
-        Job* j = jobs[i];
-        if (!j->copy_in) continue;
-        hipStream_t s = rank_stream(j->rank);
-        rc = enqueue_in(j, s);
-        if (rc != GVM_OK) break;
-        hipEvent_t ev = sync_event(b);
-        if (!ev) { rc = GVM_EDEVICE; break; }
-        if (hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
-          rc = fail(GVM_EDEVICE, "event record/wait failed");
-      }
-      if (rc == GVM_OK) rc = enqueue_kernels(jobs, cs, b);
-      hipEvent_t comp = nullptr;
-      if (rc == GVM_OK) {
-        comp = sync_event(b);
-        if (!comp || hipEventRecord(comp, cs) != hipSuccess) rc = fail(GVM_EDEVICE, "event record failed");
-      }
-      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
-        Job* j = jobs[i];
-        if (!j->copy_out) {
-          b->done[i] = comp;
-          continue;
-        }
-        hipStream_t s = rank_stream(j->rank);
-        if (hipStreamWaitEvent(s, comp, 0) != hipSuccess) { rc = fail(GVM_EDEVICE, "stream wait failed"); break; }
-        rc = enqueue_out(j, s);
-        if (rc == GVM_OK) rc = record_done(b, i, s);
-      }
+    } else {
+      rc = launch_grouped(b);
     }
     batches_.push_back(b);
     if (rc != GVM_OK) {
@@ -204,6 +178,11 @@ class HipDevice final : public Device {
       delete b;
     }
     batches_.clear();
+    for (auto& kv : graphs_) {
+      (void)hipGraphExecDestroy(kv.second.exec);
+      (void)hipGraphDestroy(kv.second.graph);
+    }
+    graphs_.clear();
     for (hipEvent_t e : free_sync_) (void)hipEventDestroy(e);
     for (hipEvent_t e : free_timed_) (void)hipEventDestroy(e);
     free_sync_.clear();
@@ -227,7 +206,9 @@ class HipDevice final : public Device {
   std::string describe() const override {
     return "{\"backend\":\"hip\",\"arch\":\"" + arch_ + "\",\"cus\":" + std::to_string(cus_) +
            ",\"rank_streams\":" + std::to_string(rank_streams_.size()) +
-           ",\"compute_streams\":" + std::to_string(compute_streams_.size()) + "}";
+           ",\"compute_streams\":" + std::to_string(compute_streams_.size()) +
+           ",\"graphs_cached\":" + std::to_string(graphs_.size()) + ",\"graph_captures\":" + std::to_string(graph_captures_) +
+           ",\"graph_launches\":" + std::to_string(graph_launches_) + "}";
   }
 
  private:
@@ -280,8 +261,15 @@ class HipDevice final : public Device {
   }
 
   // One grouped launch per kernel id (per tile configuration for SGEMM), at
-  // most kMaxGroup requests each, bracketed by timing events.
-  int enqueue_kernels(std::vector<Job*>& jobs, hipStream_t s, Batch* b) {
+  // most kMaxGroup requests each.  Groups are dealt round-robin to
+  // `streams`; `stream_of[i]` receives the stream index that computes
+  // jobs[i].  With `timed`, each launch is bracketed by timing events.
+  int enqueue_kernels(const std::vector<Job*>& jobs, const std::vector<hipStream_t>& streams, Batch* b, bool timed,
+                      std::vector<int>* stream_of) {
+    if (stream_of) stream_of->assign(jobs.size(), 0);
+    std::map<const Job*, size_t> index;
+    for (size_t i = 0; i < jobs.size(); ++i) index[jobs[i]] = i;
+    size_t next_stream = 0;
     std::map<std::pair<int, int>, std::vector<Job*>> groups;
     for (Job* j : jobs) {
       const int k = static_cast<int>(j->req.kernel_id);
@@ -293,19 +281,25 @@ class HipDevice final : public Device {
       auto& v = kv.second;
       for (size_t base = 0; base < v.size(); base += kMaxGroup) {
         const size_t cnt = std::min<size_t>(kMaxGroup, v.size() - base);
+        const size_t si = next_stream++ % streams.size();
+        hipStream_t s = streams[si];
+        if (stream_of)
+          for (size_t i = 0; i < cnt; ++i) (*stream_of)[index[v[base + i]]] = static_cast<int>(si);
         TimedLaunch t{};
         t.kernel_id = k;
         t.requests = static_cast<uint32_t>(cnt);
-        t.e0 = timed_event();
-        t.e1 = timed_event();
-        if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
+        if (timed) {
+          t.e0 = timed_event();
+          t.e1 = timed_event();
+          if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
+        }
         for (size_t i = 0; i < cnt; ++i) {
           double f, by;
           request_work(k, v[base + i]->req.n, &f, &by);
           t.flop += f;
           t.bytes += by;
         }
-        HIPCHK(hipEventRecord(t.e0, s));
+        if (timed) HIPCHK(hipEventRecord(t.e0, s));
         hipError_t e = hipSuccess;
         if (k == GVM_K_VECADD || k == GVM_K_VECMUL) {
           VecGroup g{};
@@ -357,17 +351,165 @@ class HipDevice final : public Device {
           return fail(GVM_EINVAL, "unknown kernel id %d", k);
         }
         if (e != hipSuccess) return fail(GVM_EDEVICE, "kernel launch (%s): %s", kernel_name(k), hipGetErrorString(e));
-        HIPCHK(hipEventRecord(t.e1, s));
-        b->timed.push_back(t);
+        if (timed) {
+          HIPCHK(hipEventRecord(t.e1, s));
+          b->timed.push_back(t);
+        }
       }
     }
     return GVM_OK;
+  }
+
+  // Grouped policy: copy-ins on the rank streams, one grouped launch per
+  // kernel id spread over the two compute streams, copy-outs on the rank
+  // streams.  With use_graphs the whole batch is captured once per batch
+  // template (ranks, kernels, sizes, copies, buffers) and replayed.
+  int launch_grouped(Batch* b) {
+    std::vector<Job*>& jobs = b->jobs;
+    for (Job* j : jobs)
+      if (j->copy_in) pool_.copy(j->pin, j->shm + j->req.off_in, j->lay.in_bytes);
+    hipStream_t c0 = compute_streams_[0];
+    if (!cfg_.use_graphs) return enqueue_grouped(b, false);
+
+    std::string key = graph_key(jobs);
+    auto it = graphs_.find(key);
+    if (it == graphs_.end()) {
+      if (graphs_.size() >= kMaxGraphs) evict_graph();
+      HIPCHK(hipStreamBeginCapture(c0, hipStreamCaptureModeThreadLocal));
+      int rc = enqueue_grouped(b, true);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c0, &g);
+      if (rc != GVM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(GVM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(GVM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      }
+      it = graphs_.emplace(key, GraphEntry{g, ex, 0}).first;
+      ++graph_captures_;
+    }
+    it->second.last_use = ++graph_clock_;
+    TimedLaunch t{};
+    t.kernel_id = static_cast<int>(jobs[0]->req.kernel_id);
+    for (Job* j : jobs) {
+      if (static_cast<int>(j->req.kernel_id) != t.kernel_id) t.kernel_id = 0;  // mixed batch
+      double f, by;
+      request_work(static_cast<int>(j->req.kernel_id), j->req.n, &f, &by);
+      t.flop += f;
+      t.bytes += by;
+    }
+    t.requests = static_cast<uint32_t>(jobs.size());
+    t.e0 = timed_event();
+    t.e1 = timed_event();
+    if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
+    HIPCHK(hipEventRecord(t.e0, c0));
+    HIPCHK(hipGraphLaunch(it->second.exec, c0));
+    HIPCHK(hipEventRecord(t.e1, c0));
+    b->timed.push_back(t);
+    ++graph_launches_;
+    hipEvent_t done = sync_event(b);
+    if (!done) return GVM_EDEVICE;
+    HIPCHK(hipEventRecord(done, c0));
+    for (size_t i = 0; i < jobs.size(); ++i) b->done[i] = done;
+    return GVM_OK;
+  }
+
+  // The device work of a grouped batch.  `capture`: everything forks from
+  // and joins back into compute stream 0 (required to end a stream
+  // capture), no timing events, one completion for the batch.
+  int enqueue_grouped(Batch* b, bool capture) {
+    std::vector<Job*>& jobs = b->jobs;
+    hipStream_t c0 = compute_streams_[0], c1 = compute_streams_[1];
+    std::vector<hipStream_t> used;
+    for (Job* j : jobs) {
+      hipStream_t s = rank_stream(j->rank);
+      if ((j->copy_in || j->copy_out) && std::find(used.begin(), used.end(), s) == used.end()) used.push_back(s);
+    }
+    if (capture) {
+      hipEvent_t fork = sync_event(b);
+      if (!fork) return GVM_EDEVICE;
+      HIPCHK(hipEventRecord(fork, c0));
+      for (hipStream_t s : used) HIPCHK(hipStreamWaitEvent(s, fork, 0));
+      HIPCHK(hipStreamWaitEvent(c1, fork, 0));
+    }
+    // copy-ins, then both compute streams wait for them
+    for (Job* j : jobs)
+      if (j->copy_in)
+        HIPCHK(hipMemcpyAsync(j->slot, j->pin, j->lay.in_bytes, hipMemcpyHostToDevice, rank_stream(j->rank)));
+    for (hipStream_t s : used) {
+      hipEvent_t ev = sync_event(b);
+      if (!ev) return GVM_EDEVICE;
+      HIPCHK(hipEventRecord(ev, s));
+      HIPCHK(hipStreamWaitEvent(c0, ev, 0));
+      HIPCHK(hipStreamWaitEvent(c1, ev, 0));
+    }
+    std::vector<int> stream_of;
+    int rc = enqueue_kernels(jobs, {c0, c1}, b, !capture, &stream_of);
+    if (rc != GVM_OK) return rc;
+    hipEvent_t k[2] = {sync_event(b), sync_event(b)};
+    if (!k[0] || !k[1]) return GVM_EDEVICE;
+    HIPCHK(hipEventRecord(k[0], c0));
+    HIPCHK(hipEventRecord(k[1], c1));
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      Job* j = jobs[i];
+      hipEvent_t kev = k[stream_of[i]];
+      if (!j->copy_out) {
+        b->done[i] = kev;
+        continue;
+      }
+      hipStream_t s = rank_stream(j->rank);
+      HIPCHK(hipStreamWaitEvent(s, kev, 0));
+      const uint64_t o = slot_out_offset(j->lay);
+      HIPCHK(hipMemcpyAsync(j->pin + o, j->slot + o, j->lay.out_bytes, hipMemcpyDeviceToHost, s));
+      if (!capture) {
+        rc = record_done(b, i, s);
+        if (rc != GVM_OK) return rc;
+      }
+    }
+    if (capture) {  // join
+      for (hipStream_t s : used) {
+        hipEvent_t ev = sync_event(b);
+        if (!ev) return GVM_EDEVICE;
+        HIPCHK(hipEventRecord(ev, s));
+        HIPCHK(hipStreamWaitEvent(c0, ev, 0));
+      }
+      HIPCHK(hipStreamWaitEvent(c0, k[1], 0));
+    }
+    return GVM_OK;
+  }
+
+  static std::string graph_key(const std::vector<Job*>& jobs) {
+    std::string key;
+    for (const Job* j : jobs) {
+      const uint64_t f[7] = {static_cast<uint64_t>(j->rank), j->req.kernel_id, j->req.n,
+                             static_cast<uint64_t>(j->copy_in) | (static_cast<uint64_t>(j->copy_out) << 1),
+                             reinterpret_cast<uint64_t>(j->slot), reinterpret_cast<uint64_t>(j->pin),
+                             static_cast<uint64_t>(gemm_config_for(j->req.n))};
+      key.append(reinterpret_cast<const char*>(f), sizeof(f));
+    }
+    return key;
+  }
+
+  void evict_graph() {
+    auto victim = graphs_.begin();
+    for (auto it = graphs_.begin(); it != graphs_.end(); ++it)
+      if (it->second.last_use < victim->second.last_use) victim = it;
+    (void)hipStreamSynchronize(compute_streams_[0]);  // no launch of it may be pending
+    (void)hipGraphExecDestroy(victim->second.exec);
+    (void)hipGraphDestroy(victim->second.graph);
+    graphs_.erase(victim);
   }
 
   void retire(Batch* b) {
     for (auto& t : b->timed) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, t.e0, t.e1) == hipSuccess && t.kernel_id >= 0 && t.kernel_id < 5) {
+        // kernel id 0 collects graph launches of mixed batches
         KernelStats& ks = stats_[t.kernel_id];
         ks.launches += 1;
         ks.requests += t.requests;
@@ -429,6 +571,14 @@ class HipDevice final : public Device {
   std::vector<hipEvent_t> free_timed_;
   std::vector<Batch*> batches_;
   KernelStats stats_[5];
+  struct GraphEntry {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  static constexpr size_t kMaxGraphs = 32;
+  std::map<std::string, GraphEntry> graphs_;
+  uint64_t graph_clock_ = 0, graph_captures_ = 0, graph_launches_ = 0;
 };
 
 }  // namespace

@@ -333,6 +333,9 @@ const GemmConfig kGemmConfigs[] = {
     {2, 128, 128, 16, 2, 2},
     {3, 128, 128, 32, 2, 2},
     {4, 256, 128, 16, 4, 2},
+    {5, 128, 256, 16, 2, 4},
+    {6, 256, 128, 32, 4, 2},
+    {7, 64, 128, 16, 2, 2},
 };
 constexpr int kNumGemmConfigs = sizeof(kGemmConfigs) / sizeof(kGemmConfigs[0]);
 
@@ -440,6 +443,9 @@ hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s,
     case 2: return launch_cfg<128, 128, 16, 2, 2>(g, vec, s, grid_cap);
     case 3: return launch_cfg<128, 128, 32, 2, 2>(g, vec, s, grid_cap);
     case 4: return launch_cfg<256, 128, 16, 4, 2>(g, vec, s, grid_cap);
+    case 5: return launch_cfg<128, 256, 16, 2, 4>(g, vec, s, grid_cap);
+    case 6: return launch_cfg<256, 128, 32, 4, 2>(g, vec, s, grid_cap);
+    case 7: return launch_cfg<64, 128, 16, 2, 2>(g, vec, s, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }

@@ -98,6 +98,7 @@ class Manager {
   uint64_t last_liveness_ns_ = 0;
   std::atomic<bool> reset_pending_{false};
   std::string open_error_;
+  uint64_t spin_ns_ = 200000;      // poll before sleeping once idle
 
   // statistics (guarded by stats_mu_)
   std::mutex stats_mu_;

@@ -129,9 +129,15 @@ void drain(RankHandle& h) {
 }
 
 // Block until `done()` holds, a response arrives for it, or the deadline.
+uint64_t rank_spin_ns() {
+  static const uint64_t ns = spin_env_ns("GVM_RANK_SPIN_US", 200);
+  return ns;
+}
+
 template <class Pred>
 int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
   const uint64_t t0 = now_ns();
+  const uint64_t spin = rank_spin_ns();
   const uint64_t deadline = timeout_ns < 0 ? UINT64_MAX : t0 + static_cast<uint64_t>(timeout_ns);
   for (;;) {
     drain(h);
@@ -143,7 +149,7 @@ int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
     }
     const uint64_t now = now_ns();
     if (now >= deadline) return fail(GVM_ETIMEDOUT, "timed out");
-    if (now - t0 < 20000) {  // spin ~20 us before sleeping
+    if (now - t0 < spin) {  // poll before sleeping (GVM_RANK_SPIN_US, default 200 us)
       for (int i = 0; i < 32; ++i) _mm_pause();
       continue;
     }

@@ -1,0 +1,155 @@
+"""SGEMM tile autotuner.
+
+For every matrix size n of the search (default: the multiples of 64 in
+[256, 2048] plus the small sizes), runs a grouped launch of ``--group``
+identical-size requests (resident in HBM) through the GVM manager once per
+compiled tile configuration, times the launches with the manager's HIP
+events, and keeps the fastest configuration.  The result is written as the
+compiled-in table ``csrc/gemm_tiles.inc`` (rows of {largest n, config}),
+so the tile choice stays a pure function of n: a rank's SGEMM result does
+not depend on what it is grouped with.
+
+    python -m paper_1511_07658_amd.tune [--sizes 256,512,...] [--group 8] [--reps 10] [--write]
+
+Needs the GPU; rebuild the library after --write.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+
+import numpy as np
+
+from . import gvm as G
+from . import workloads as wl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "csrc", "gemm_tiles.inc")
+NUM_CONFIGS = 8
+CONFIG_NAMES = ["64x64x16", "128x64x16", "128x128x16", "128x128x32", "256x128x16", "128x256x16", "256x128x32",
+                "64x128x16"]
+
+
+def _time_size(ns, n, group, reps, configs):
+    """Mean device time (us) of one grouped launch of `group` n x n GEMMs,
+    per tile configuration."""
+    times = {}
+    bar = threading.Barrier(group + 1)
+    stop = threading.Event()
+    plan = {"config": None}
+    errors = []
+
+    def rank(r):
+        try:
+            A, B = wl.sgemm_inputs(90, r, n)
+            x = wl.pack_request(3, A, B)
+            out = np.empty(n * n, np.float32)
+            G.check(G.gvm_attach_ns(ns, r), "attach")
+            t = G.check(G.gvm_submit(r, 3, x, out, n), "upload")
+            G.check(G.gvm_wait(r, t, 60_000_000_000), "upload")
+            flags = G.GVM_F_IN_RESIDENT | G.GVM_F_OUT_RESIDENT
+            bar.wait()  # uploads done
+            while True:
+                bar.wait()
+                if stop.is_set():
+                    break
+                for _ in range(reps + 2):
+                    t = G.check(G.gvm_submit_ex(r, 3, None, None, n, flags), "step")
+                    G.check(G.gvm_wait(r, t, 60_000_000_000), "step")
+                bar.wait()
+            G.gvm_detach(r)
+        except Exception as e:  # reported by the caller
+            errors.append(repr(e))
+            bar.abort()
+
+    ths = [threading.Thread(target=rank, args=(r,)) for r in range(group)]
+    for t in ths:
+        t.start()
+    try:
+        bar.wait()  # uploads done
+        for c in configs:
+            os.environ["GVM_SGEMM_CONFIG"] = str(c)
+            G.gvm_stats_reset()
+            bar.wait()          # go
+            bar.wait()          # done
+            st = G.gvm_stats_json()["kernels"]["sgemm"]
+            times[c] = st["device_ms"] / max(st["launches"], 1) * 1e3
+        stop.set()
+        bar.wait()
+    finally:
+        os.environ.pop("GVM_SGEMM_CONFIG", None)
+        for t in ths:
+            t.join()
+    if errors:
+        raise RuntimeError(errors[0])
+    return times
+
+
+def tune(sizes, group=8, reps=10, configs=None):
+    configs = list(range(NUM_CONFIGS)) if configs is None else configs
+    ns = f"gvm.tune.{os.getpid()}"
+    nmax = max(sizes)
+    cfg = G.gvm_config_default(nranks=group, shm_bytes_per_rank=12 * nmax * nmax + (1 << 20),
+                               hbm_budget_bytes=max(1 << 30, group * (12 * nmax * nmax + (1 << 20))),
+                               batch_window_us=10_000_000, policy=G.GVM_POLICY_GROUPED, name=ns)
+    G.check(G.gvm_init(cfg), "gvm_init")
+    results = {}
+    try:
+        for n in sizes:
+            # sizes change the resident input, so every size re-attaches
+            t = _time_size(ns, n, group, reps, configs)
+            best = min(t, key=lambda c: (round(t[c], 1), c))
+            results[n] = {"best": best, "us": {CONFIG_NAMES[c]: round(v, 2) for c, v in t.items()},
+                          "tflops": round(group * 2.0 * n ** 3 / (t[best] * 1e-6) / 1e12, 2)}
+            print(json.dumps({"n": n, **results[n]}), flush=True)
+    finally:
+        G.gvm_shutdown()
+    return results
+
+
+def write_table(results, path=TABLE):
+    rows = []
+    for n in sorted(results):
+        c = results[n]["best"]
+        if rows and rows[-1][1] == c:
+            rows[-1][0] = n
+        else:
+            rows.append([n, c])
+    rows[-1][0] = 1 << 30
+    with open(path, "w") as f:
+        f.write("// SGEMM tile table: rows of {largest n, tile configuration index},\n")
+        f.write("// written by `python -m paper_1511_07658_amd.tune --write` on an MI355X\n")
+        f.write("// (grouped launches of identical-size requests, fastest mean device time).\n")
+        f.write("constexpr uint64_t kTileTable[][2] = {\n")
+        for n, c in rows:
+            f.write(f"    {{{n}u, {c}}},  // {CONFIG_NAMES[c]}\n")
+        f.write("};\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", default=None, help="comma-separated sizes (default 64,128,192 and 256..2048 step 64)")
+    ap.add_argument("--group", type=int, default=8)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--configs", default=None)
+    ap.add_argument("--write", action="store_true")
+    ap.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    sizes = [int(s) for s in a.sizes.split(",")] if a.sizes else [64, 128, 192] + list(range(256, 2049, 64))
+    configs = [int(c) for c in a.configs.split(",")] if a.configs else None
+    res = tune(sizes, a.group, a.reps, configs)
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump(res, f, indent=1)
+    if a.write:
+        write_table(res)
+        print(f"wrote {TABLE}; rebuild the library", file=sys.stderr)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -142,7 +142,7 @@ def test_every_tile_configuration(ns_name):
         A, B = wl.sgemm_inputs(15, 0, n)
         x = wl.pack_request(3, A, B)
         outs = []
-        for cfg_idx in range(5):
+        for cfg_idx in range(8):
             os.environ["GVM_SGEMM_CONFIG"] = str(cfg_idx)
             try:
                 o = np.empty(n * n, np.float32)
@@ -290,3 +290,61 @@ def test_request_larger_than_budget(ns_name):
         assert t > 0
         assert G.gvm_wait(0, t, 10_000_000_000) == G.GVM_ENOMEM
         G.gvm_detach(0)
+
+
+GRAPH_SKIP = ("HIP graph replay is switched off: its first GPU run ended in a host segmentation "
+              "fault whose cause is not yet shown (gvm_init rejects use_graphs)")
+
+
+@pytest.mark.skip(reason=GRAPH_SKIP)
+def test_graph_replays_match_eager(ns_name):
+    # one batch template replayed as a HIP graph: every replay, with fresh
+    # inputs copied in between, must equal the plain (eager) result
+    nr = 6
+    jobs = {r: [((r % 3) + 1, 61, [300001, 50001, 192][r % 3], i, False) for i in range(5)] for r in range(nr)}
+    with hip_manager(ns_name, nranks=nr, policy=G.GVM_POLICY_GROUPED, use_graphs=1, batch_window_us=10_000_000):
+        res = run_ranks(ns_name, [jobs[r] for r in range(nr)])
+        st = G.gvm_stats_json()
+    assert st["device"]["graph_captures"] >= 1
+    assert st["device"]["graph_launches"] >= 5
+    assert st["device"]["graph_captures"] < st["device"]["graph_launches"]
+    for r in range(nr):
+        assert res[r]["attach"] == 0
+        for (k, cfg, n, req, integer), jr in zip(jobs[r], res[r]["results"]):
+            assert jr["status"] == 0, jr
+            x = spmd.make_input(k, cfg, r, n, req, integer)
+            o = np.empty(G.out_elems(k, n), np.float32)
+            rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
+            assert rc == 0
+            assert spmd.digest(o) == jr["digest"], (r, k, n, req)
+
+
+@pytest.mark.skip(reason=GRAPH_SKIP)
+def test_graph_resident_sgemm_matches_oracle(ns_name):
+    n = 1024
+    with hip_manager(ns_name, nranks=8, policy=G.GVM_POLICY_GROUPED, use_graphs=1, batch_window_us=10_000_000):
+        errs = []
+
+        def rank(r):
+            try:
+                assert G.gvm_attach_ns(ns_name, r) == 0
+                A, B = wl.sgemm_inputs(62, r, n)
+                out = np.empty(n * n, np.float32)
+                t = G.gvm_submit(r, 3, wl.pack_request(3, A, B), out, n)
+                assert G.gvm_wait(r, t, 60_000_000_000) == 0
+                assert_sgemm(out, 62, r, n)
+                for _ in range(4):
+                    out[:] = 0
+                    t = G.gvm_submit_ex(r, 3, None, out, n, G.GVM_F_IN_RESIDENT)
+                    assert G.gvm_wait(r, t, 60_000_000_000) == 0
+                    assert_sgemm(out, 62, r, n)
+                assert G.gvm_detach(r) == 0
+            except AssertionError as e:
+                errs.append((r, str(e)))
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(8)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+        st = G.gvm_stats_json()
+        assert st["device"]["graph_launches"] >= 5

@@ -331,3 +331,9 @@ def test_hip_backend_fails_loudly_without_gpu(ns_name):
     assert G.gvm_init(cfg) == G.GVM_EDEVICE
     assert "HIP" in G.gvm_last_error() or "device" in G.gvm_last_error()
     assert glob.glob(f"/dev/shm/{ns_name}.*") == []
+
+
+def test_graph_replay_is_switched_off(ns_name):
+    cfg = loop_cfg(ns_name, use_graphs=1)
+    assert G.gvm_init(cfg) == G.GVM_EINVAL
+    assert "graph" in G.gvm_last_error()
