@@ -1,17 +1,14 @@
 #include "copy_pool.hpp"
 
-#include <immintrin.h>
-
 #include <cstring>
 
 namespace gvm {
 
 namespace {
-constexpr size_t kSerialBytes = size_t(2) << 20;  // below this one thread is as fast
-constexpr size_t kChunk = size_t(1) << 20;
+constexpr size_t kChunk = size_t(4) << 20;
 }  // namespace
 
-void CopyPool::start(int nthreads) {
+void CopyEngine::start(int nthreads) {
   stop();
   {
     std::lock_guard<std::mutex> lk(mu_);
@@ -20,7 +17,7 @@ void CopyPool::start(int nthreads) {
   for (int i = 0; i < nthreads; ++i) threads_.emplace_back([this] { worker(); });
 }
 
-void CopyPool::stop() {
+void CopyEngine::stop() {
   {
     std::lock_guard<std::mutex> lk(mu_);
     stopping_ = true;
@@ -28,59 +25,46 @@ void CopyPool::stop() {
   cv_.notify_all();
   for (auto& t : threads_) t.join();
   threads_.clear();
-}
-
-void CopyPool::run_chunks(const Job& j) {
-  uint64_t cur = cursor_.load(std::memory_order_acquire);
-  for (;;) {
-    if ((cur >> 32) != j.gen || (cur & 0xffffffffull) >= j.nchunks) return;
-    if (!cursor_.compare_exchange_weak(cur, cur + 1, std::memory_order_acq_rel)) continue;
-    const size_t c = static_cast<size_t>(cur & 0xffffffffull);
-    const size_t off = c * kChunk;
-    const size_t len = (off + kChunk <= j.bytes) ? kChunk : j.bytes - off;
-    memcpy(j.dst + off, j.src + off, len);
-    done_.fetch_add(1, std::memory_order_acq_rel);
-    cur = cursor_.load(std::memory_order_acquire);
+  // anything still queued is copied here so that no waiter is left behind
+  for (Chunk& c : queue_) {
+    memcpy(c.dst, c.src, c.bytes);
+    c.pending->fetch_sub(1, std::memory_order_acq_rel);
   }
+  queue_.clear();
 }
 
-void CopyPool::worker() {
-  uint32_t seen = 0;
+void CopyEngine::worker() {
   for (;;) {
-    Job j;
+    Chunk c;
     {
       std::unique_lock<std::mutex> lk(mu_);
-      cv_.wait(lk, [&] { return stopping_ || job_.gen != seen; });
-      if (stopping_) return;
-      j = job_;
-      seen = j.gen;
+      cv_.wait(lk, [&] { return stopping_ || !queue_.empty(); });
+      if (queue_.empty()) return;  // stopping and drained
+      c = queue_.front();
+      queue_.pop_front();
     }
-    run_chunks(j);
+    memcpy(c.dst, c.src, c.bytes);
+    c.pending->fetch_sub(1, std::memory_order_acq_rel);
   }
 }
 
-void CopyPool::copy(void* dst, const void* src, size_t bytes) {
+void CopyEngine::submit(void* dst, const void* src, size_t bytes, std::atomic<int>* pending) {
   if (bytes == 0) return;
-  if (threads_.empty() || bytes < kSerialBytes) {
+  if (threads_.empty()) {
     memcpy(dst, src, bytes);
     return;
   }
-  Job j;
+  const size_t n = (bytes + kChunk - 1) / kChunk;
+  pending->fetch_add(static_cast<int>(n), std::memory_order_acq_rel);
   {
     std::lock_guard<std::mutex> lk(mu_);
-    j.dst = static_cast<char*>(dst);
-    j.src = static_cast<const char*>(src);
-    j.bytes = bytes;
-    j.nchunks = (bytes + kChunk - 1) / kChunk;
-    j.gen = job_.gen + 1;
-    if (j.gen == 0) j.gen = 1;
-    done_.store(0, std::memory_order_relaxed);
-    cursor_.store(static_cast<uint64_t>(j.gen) << 32, std::memory_order_release);
-    job_ = j;
+    for (size_t i = 0; i < n; ++i) {
+      const size_t off = i * kChunk;
+      const size_t len = (off + kChunk <= bytes) ? kChunk : bytes - off;
+      queue_.push_back(Chunk{static_cast<char*>(dst) + off, static_cast<const char*>(src) + off, len, pending});
+    }
   }
-  cv_.notify_all();
-  run_chunks(j);
-  while (done_.load(std::memory_order_acquire) < j.nchunks) _mm_pause();
+  if (n == 1) cv_.notify_one(); else cv_.notify_all();
 }
 
 }  // namespace gvm

@@ -3,6 +3,7 @@
 // the enqueue policies of Section 4.2.1.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <memory>
 #include <string>
@@ -13,7 +14,12 @@
 
 namespace gvm {
 
-// One admitted request on its way through the device.
+// Stages of an admitted request in the manager.
+enum JobStage : int { kStageCopyIn = 0, kStageReady = 1, kStageDevice = 2, kStageCopyOut = 3 };
+
+// One admitted request on its way through the device.  The manager moves its
+// input shm -> pinned before launch() and its result pinned -> shm after the
+// device work; the Device only moves pinned <-> device memory.
 struct Job {
   int rank = -1;
   Request req{};
@@ -29,6 +35,8 @@ struct Job {
   uint64_t t_device_ns = 0;
   void* batch = nullptr;        // device-private bookkeeping
   int done_index = -1;
+  int stage = kStageCopyIn;
+  std::atomic<int> copies{0};   // host copy chunks still in flight
 };
 
 struct KernelStats {
@@ -53,7 +61,11 @@ class Device {
   virtual int launch(std::vector<Job*>& jobs, int policy) = 0;
   // 1 when the job's device work has finished, 0 if not yet, < 0 on a device error.
   virtual int query(Job* j) = 0;
-  // After query() == 1: move the result from staging to the rank's data space.
+  // Start a polling round: query() may then ask the runtime about each
+  // completion event at most once until the next round.
+  virtual void begin_poll() {}
+  // After query() == 1: release the device bookkeeping of the job (the
+  // result is in the pinned staging).
   virtual void finish(Job* j) = 0;
   virtual void drain() = 0;
   virtual void close() = 0;

@@ -10,7 +10,6 @@
 #include <string>
 #include <vector>
 
-#include "copy_pool.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -31,7 +30,14 @@ struct TimedLaunch {
   double flop, bytes;
 };
 
+struct EventState {
+  uint64_t round;
+  bool done;
+  hipError_t err;
+};
+
 struct Batch {
+  std::map<hipEvent_t, EventState> state;  // polled completion events
   std::vector<Job*> jobs;
   std::vector<hipEvent_t> done;   // per job (several jobs may share one event)
   std::vector<hipEvent_t> sync;   // events owned by the batch, recycled at the end
@@ -70,7 +76,6 @@ class HipDevice final : public Device {
     staging_.assign(cfg.nranks, nullptr);
     staging_bytes_ = cfg.staging_bytes ? cfg.staging_bytes : cfg.shm_bytes_per_rank;
     staging_bytes_ = align_up(staging_bytes_ + 2 * kAlign, 4096);
-    pool_.start(cfg.copy_threads ? static_cast<int>(cfg.copy_threads) : 4);
     int rc = prepare_kernels();
     if (rc != GVM_OK) return rc;
     return GVM_OK;
@@ -140,25 +145,32 @@ class HipDevice final : public Device {
     return rc;
   }
 
+  // Several jobs of a batch often share one completion event: its state is
+  // queried once per polling round (begin_poll) and remembered once done.
   int query(Job* j) override {
     auto* b = static_cast<Batch*>(j->batch);
     if (j->status != GVM_OK) return 1;
     hipEvent_t ev = b->done[j->done_index];
     if (!ev) return 1;
-    hipError_t e = hipEventQuery(ev);
-    if (e == hipSuccess) {
+    auto it = b->state.find(ev);
+    if (it == b->state.end() || (it->second.round != poll_round_ && !it->second.done)) {
+      const hipError_t e = hipEventQuery(ev);
+      EventState st{poll_round_, e == hipSuccess, e};
+      it = b->state.insert_or_assign(ev, st).first;
+    }
+    if (it->second.done) {
       if (!j->t_device_ns) j->t_device_ns = now_ns();
       return 1;
     }
-    if (e == hipErrorNotReady) return 0;
-    j->status = fail(GVM_EDEVICE, "device work failed: %s", hipGetErrorString(e));
+    if (it->second.err == hipErrorNotReady) return 0;
+    j->status = fail(GVM_EDEVICE, "device work failed: %s", hipGetErrorString(it->second.err));
     return -1;
   }
 
+  void begin_poll() override { ++poll_round_; }
+
   void finish(Job* j) override {
     auto* b = static_cast<Batch*>(j->batch);
-    if (j->status == GVM_OK && j->copy_out)
-      pool_.copy(j->shm + j->req.off_out, j->pin + slot_out_offset(j->lay), j->lay.out_bytes);
     j->batch = nullptr;
     if (b && --b->remaining == 0) retire(b);
   }
@@ -196,7 +208,6 @@ class HipDevice final : public Device {
     for (uint8_t* p : staging_)
       if (p) (void)hipHostFree(p);
     staging_.clear();
-    pool_.stop();
   }
 
   const KernelStats* kernel_stats() const override { return stats_; }
@@ -248,7 +259,6 @@ class HipDevice final : public Device {
 
   int enqueue_in(Job* j, hipStream_t s) {
     if (!j->copy_in) return GVM_OK;
-    pool_.copy(j->pin, j->shm + j->req.off_in, j->lay.in_bytes);
     HIPCHK(hipMemcpyAsync(j->slot, j->pin, j->lay.in_bytes, hipMemcpyHostToDevice, s));
     return GVM_OK;
   }
@@ -366,8 +376,6 @@ class HipDevice final : public Device {
   // template (ranks, kernels, sizes, copies, buffers) and replayed.
   int launch_grouped(Batch* b) {
     std::vector<Job*>& jobs = b->jobs;
-    for (Job* j : jobs)
-      if (j->copy_in) pool_.copy(j->pin, j->shm + j->req.off_in, j->lay.in_bytes);
     hipStream_t c0 = compute_streams_[0];
     if (!cfg_.use_graphs) return enqueue_grouped(b, false);
 
@@ -563,10 +571,10 @@ class HipDevice final : public Device {
   std::vector<hipStream_t> rank_streams_;
   std::vector<hipStream_t> compute_streams_;
   size_t next_cs_ = 0;
+  uint64_t poll_round_ = 0;
   uint8_t* arena_ = nullptr;
   std::vector<uint8_t*> staging_;
   uint64_t staging_bytes_ = 0;
-  CopyPool pool_;
   std::vector<hipEvent_t> free_sync_;
   std::vector<hipEvent_t> free_timed_;
   std::vector<Batch*> batches_;

@@ -119,6 +119,7 @@ int Manager::init(const gvm_config& cfg_in) {
   }
   ranks_.assign(cfg.nranks, RankRt{});
   arena_.init(cfg.hbm_budget_bytes);
+  copy_.start(cfg.copy_threads ? static_cast<int>(cfg.copy_threads) : 4);
   dev_ = (cfg.backend == GVM_BACKEND_LOOPBACK) ? make_loopback_device() : make_hip_device();
 
   // The service thread opens the device itself so that every HIP call of the
@@ -130,6 +131,7 @@ int Manager::init(const gvm_config& cfg_in) {
   rc = fut.get();
   if (rc != GVM_OK) {
     thread_.join();
+    copy_.stop();
     fail(rc, "%s", open_error_.c_str());
     dev_.reset();
     data_.clear();
@@ -165,6 +167,7 @@ void Manager::service(std::promise<int>* ready) {
     progress |= complete_jobs();
     check_liveness();
     progress |= schedule();
+    progress |= launch_ready();
     if (progress) {
       spins = 0;
       idle_since = 0;
@@ -202,9 +205,11 @@ void Manager::service(std::promise<int>* ready) {
 
   // Shutdown: let device work finish, answer what is still queued.
   while (inflight_ > 0) {
+    launch_ready();
     complete_jobs();
     if (inflight_ > 0) sched_yield();
   }
+  copy_.stop();
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
     drain_rings();
     auto& rt = ranks_[r];
@@ -359,15 +364,26 @@ void Manager::check_liveness() {
   }
 }
 
+// Device completions and host copy-outs, per rank (one job in flight each).
 bool Manager::complete_jobs() {
   bool any = false;
+  dev_->begin_poll();
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
     RankRt& rt = ranks_[r];
     Job* j = rt.running;
     if (!j) continue;
-    const int q = dev_->query(j);
-    if (q == 0) continue;
-    dev_->finish(j);
+    if (j->stage == kStageDevice) {
+      if (dev_->query(j) == 0) continue;
+      dev_->finish(j);
+      any = true;
+      if (j->status == GVM_OK && j->copy_out) {
+        copy_.submit(j->shm + j->req.off_out, j->pin + slot_out_offset(j->lay), j->lay.out_bytes, &j->copies);
+        j->stage = kStageCopyOut;
+      } else {
+        j->stage = kStageCopyOut;  // nothing to copy
+      }
+    }
+    if (j->stage != kStageCopyOut || j->copies.load(std::memory_order_acquire) != 0) continue;
     const bool alive = rt.attached;
     if (alive) respond(static_cast<int>(r), j->req.ticket, j->req.kernel_id, j->status, j, j->req.t_submit_ns);
     if (j->status != GVM_OK) rt.res_valid = false;
@@ -386,6 +402,40 @@ bool Manager::complete_jobs() {
   }
   if (cfg_.mode == GVM_MODE_BATCH && batch_open_ && inflight_ == 0) batch_open_ = false;
   return any;
+}
+
+// Launch admitted jobs whose inputs have reached the pinned staging.  A
+// batch (batch mode) goes to the device as a whole once every input is in;
+// in serving mode every ready job goes as soon as its copy-in lands.
+bool Manager::launch_ready() {
+  if (staged_.empty()) return false;
+  bool all = true;
+  for (Job* j : staged_) {
+    if (j->stage == kStageCopyIn && j->copies.load(std::memory_order_acquire) == 0) j->stage = kStageReady;
+    all &= (j->stage == kStageReady);
+  }
+  // A batch of kernels that run as one grouped launch waits for all of its
+  // inputs; per-rank launches (PS-2, what AUTO picks when data moves) start
+  // as soon as each input has landed, overlapping the others' copies.
+  bool incremental = cfg_.mode == GVM_MODE_SERVING || cfg_.policy == GVM_POLICY_PS2;
+  if (cfg_.policy == GVM_POLICY_AUTO)
+    for (const Job* j : staged_) incremental |= (j->copy_in || j->copy_out);
+  std::vector<Job*> ready;
+  if (!incremental) {
+    if (!all) return false;
+    ready.swap(staged_);
+  } else {
+    std::vector<Job*> keep;
+    for (Job* j : staged_) (j->stage == kStageReady ? ready : keep).push_back(j);
+    staged_.swap(keep);
+    if (ready.empty()) return false;
+  }
+  const int policy = resolve_policy(ready);
+  for (Job* j : ready) j->stage = kStageDevice;
+  dev_->launch(ready, policy);
+  std::lock_guard<std::mutex> lk(stats_mu_);
+  ++n_batches_;
+  return true;
 }
 
 Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
@@ -441,6 +491,12 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   j->copy_in = copy_in;
   j->copy_out = copy_out;
   j->t_admit_ns = now_ns();
+  if (copy_in) {
+    j->stage = kStageCopyIn;
+    copy_.submit(j->pin, j->shm + m.off_in, lay.in_bytes, &j->copies);
+  } else {
+    j->stage = kStageReady;
+  }
   rt.queue.pop_front();
   rt.running = j;
   rt.res_valid = true;
@@ -518,12 +574,7 @@ bool Manager::schedule() {
     }
   }
   if (jobs.empty()) return any;
-  const int policy = resolve_policy(jobs);
-  dev_->launch(jobs, policy);
-  {
-    std::lock_guard<std::mutex> lk(stats_mu_);
-    ++n_batches_;
-  }
+  staged_.insert(staged_.end(), jobs.begin(), jobs.end());
   if (cfg_.mode == GVM_MODE_BATCH) batch_open_ = true;
   return true;
 }

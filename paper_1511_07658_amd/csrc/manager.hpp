@@ -14,6 +14,7 @@
 #include <thread>
 #include <vector>
 
+#include "copy_pool.hpp"
 #include "device.hpp"
 #include "shm.hpp"
 
@@ -73,6 +74,7 @@ class Manager {
   void on_message(int r, const Request& m);
   bool complete_jobs();
   bool schedule();
+  bool launch_ready();
   Admit admit(int r, std::vector<Job*>& jobs);
   void respond(int r, uint64_t ticket, uint32_t kernel_id, int status, const Job* j, uint64_t t_submit);
   void release_slot(int r);
@@ -89,6 +91,8 @@ class Manager {
   std::unique_ptr<Device> dev_;
   Arena arena_;
   std::vector<RankRt> ranks_;
+  CopyEngine copy_;                // shm <-> pinned staging copies
+  std::vector<Job*> staged_;       // admitted, waiting for their copy-in
   std::thread thread_;
   std::atomic<bool> stop_{false};
   bool started_ = false;

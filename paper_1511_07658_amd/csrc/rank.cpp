@@ -129,15 +129,19 @@ void drain(RankHandle& h) {
 }
 
 // Block until `done()` holds, a response arrives for it, or the deadline.
-uint64_t rank_spin_ns() {
-  static const uint64_t ns = spin_env_ns("GVM_RANK_SPIN_US", 200);
-  return ns;
+// Poll budget before a futex sleep: 200 us when every rank and the manager
+// can have a core of their own, 10 us when the host is oversubscribed (a
+// spinning rank would then steal the core of the one it waits for).
+uint64_t rank_spin_ns(const CtlHeader* hdr) {
+  if (getenv("GVM_RANK_SPIN_US")) return spin_env_ns("GVM_RANK_SPIN_US", 200);
+  static const long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
+  return (static_cast<long>(hdr->nranks) + 2 > ncpu) ? 10000ull : 200000ull;
 }
 
 template <class Pred>
 int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
   const uint64_t t0 = now_ns();
-  const uint64_t spin = rank_spin_ns();
+  const uint64_t spin = rank_spin_ns(hdr);
   const uint64_t deadline = timeout_ns < 0 ? UINT64_MAX : t0 + static_cast<uint64_t>(timeout_ns);
   for (;;) {
     drain(h);
