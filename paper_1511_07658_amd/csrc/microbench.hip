@@ -3,10 +3,13 @@
 //                         also the reference kernel for scaling FETCH_SIZE/WRITE_SIZE)
 //   mfma   <iters>        FP32 MFMA issue rate (v_mfma_f32_32x32x2_f32 chains)
 //   pcie   <MiB>          pinned host<->device copy rates, one direction and both
+//   latency <iters>       launch -> completion seen by the host (event query,
+//                         stream synchronize, kernel-written host flag)
 //   init                  time to create the device context in a fresh process
 // Prints one JSON object per test.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -30,6 +33,27 @@ __global__ __launch_bounds__(256) void copy_kernel(const f32x4* __restrict__ src
     __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Streaming variants: plain (cached) loads/stores, U float4 per thread per round.
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void copy_var_kernel(const f32x4* __restrict__ src, f32x4* __restrict__ dst, size_t n4) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * 256ull * U;
+  for (size_t base = blockIdx.x * 256ull * U + threadIdx.x; base < n4; base += stride) {
+    f32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = base + u * 256ull;
+      if (i < n4) v[u] = NT ? __builtin_nontemporal_load(src + i) : src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = base + u * 256ull;
+      if (i < n4) {
+        if (NT) __builtin_nontemporal_store(v[u], dst + i); else dst[i] = v[u];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void mfma_kernel(float* out, int iters) {
   f32x16 a0 = {0}, a1 = {0}, a2 = {0}, a3 = {0};
   const float x = threadIdx.x * 1e-3f, y = 1.0f;
@@ -44,13 +68,30 @@ __global__ __launch_bounds__(256) void mfma_kernel(float* out, int iters) {
   out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+__global__ void empty_kernel(int x) {
+  if (x < 0 && threadIdx.x == 0) asm volatile("s_nop 0");
+}
+
+// Lane 0 publishes `v` to pinned host memory (global store, system scope).
+__global__ void signal_kernel(uint32_t* flag, uint32_t v) {
+  if (threadIdx.x == 0) __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+struct Big {
+  float v[320];  // 1280 bytes, like a grouped launch's request table
+};
+
+__global__ void big_arg_kernel(Big b) {
+  if (b.v[0] < 0.0f && threadIdx.x == 0) asm volatile("s_nop 0");
+}
+
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 int main(int argc, char** argv) {
   if (argc < 2) {
-    fprintf(stderr, "usage: %s copy <MiB> <reps> | mfma <iters> | pcie <MiB> | init\n", argv[0]);
+    fprintf(stderr, "usage: %s copy <MiB> <reps> | mfma <iters> | pcie <MiB> | latency <iters> | init\n", argv[0]);
     return 1;
   }
   const std::string what = argv[1];
@@ -100,6 +141,40 @@ int main(int argc, char** argv) {
            2.0 * bytes / (total / reps * 1e-3) / 1e9);
     CK(hipFree(s));
     CK(hipFree(d));
+  } else if (what == "copyvar") {
+    // HBM streaming variants over a 4 GiB copy (well above the 256 MB MALL)
+    const size_t bytes = size_t(argc > 2 ? strtoull(argv[2], nullptr, 10) : 4096) << 20;
+    const size_t n4 = bytes / 16;
+    f32x4 *src, *dst;
+    CK(hipMalloc(&src, bytes));
+    CK(hipMalloc(&dst, bytes));
+    CK(hipMemset(src, 0, bytes));
+    CK(hipMemset(dst, 0, bytes));
+    auto timeit = [&](auto launch) {
+      launch();
+      CK(hipDeviceSynchronize());
+      float best = 1e30f;
+      for (int r = 0; r < 5; ++r) {
+        CK(hipEventRecord(e0));
+        launch();
+        CK(hipEventRecord(e1));
+        CK(hipEventSynchronize(e1));
+        float ms;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+      }
+      return 2.0 * bytes / (best * 1e-3) / 1e9;
+    };
+    for (int grid : {512, 1024, 2048, 4096, 8192}) {
+      const double a = timeit([&] { hipLaunchKernelGGL((copy_var_kernel<1, false>), dim3(grid), dim3(256), 0, nullptr, src, dst, n4); });
+      const double b = timeit([&] { hipLaunchKernelGGL((copy_var_kernel<1, true>), dim3(grid), dim3(256), 0, nullptr, src, dst, n4); });
+      const double c = timeit([&] { hipLaunchKernelGGL((copy_var_kernel<4, false>), dim3(grid), dim3(256), 0, nullptr, src, dst, n4); });
+      const double d = timeit([&] { hipLaunchKernelGGL((copy_var_kernel<4, true>), dim3(grid), dim3(256), 0, nullptr, src, dst, n4); });
+      printf("{\"test\":\"copyvar\",\"bytes\":%zu,\"grid\":%d,\"u1_cached_GBps\":%.1f,\"u1_nt_GBps\":%.1f,"
+             "\"u4_cached_GBps\":%.1f,\"u4_nt_GBps\":%.1f}\n", bytes, grid, a, b, c, d);
+    }
+    CK(hipFree(src));
+    CK(hipFree(dst));
   } else if (what == "mfma") {
     const int iters = argc > 2 ? atoi(argv[2]) : 20000;
     const int blocks = p.multiProcessorCount * 8;
@@ -117,39 +192,95 @@ int main(int argc, char** argv) {
     printf("{\"test\":\"mfma_f32\",\"TFLOPs\":%.2f,\"ms\":%.3f}\n", flop / (ms * 1e-3) / 1e12, ms);
     CK(hipFree(o));
   } else if (what == "pcie") {
+    // pinned host <-> device copy rates: warm buffers, 5 repetitions each,
+    // for the default and the non-coherent pinned allocation
     const size_t bytes = (argc > 2 ? strtoull(argv[2], nullptr, 10) : 256) << 20;
-    void *h1, *h2, *d1, *d2;
-    CK(hipHostMalloc(&h1, bytes, hipHostMallocDefault));
-    CK(hipHostMalloc(&h2, bytes, hipHostMallocDefault));
+    const unsigned flag_sets[2] = {hipHostMallocDefault, hipHostMallocNonCoherent};
+    const char* names[2] = {"default", "noncoherent"};
+    void *d1, *d2;
     CK(hipMalloc(&d1, bytes));
     CK(hipMalloc(&d2, bytes));
-    memset(h1, 1, bytes);
-    memset(h2, 2, bytes);
+    CK(hipMemset(d1, 1, bytes));
+    CK(hipMemset(d2, 2, bytes));
     hipStream_t s1, s2;
     CK(hipStreamCreateWithFlags(&s1, hipStreamNonBlocking));
     CK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
-    CK(hipMemcpyAsync(d1, h1, bytes, hipMemcpyHostToDevice, s1));
-    CK(hipStreamSynchronize(s1));
-    double t0 = now_s();
-    CK(hipMemcpyAsync(d1, h1, bytes, hipMemcpyHostToDevice, s1));
-    CK(hipStreamSynchronize(s1));
-    const double h2d = bytes / (now_s() - t0) / 1e9;
-    t0 = now_s();
-    CK(hipMemcpyAsync(h2, d2, bytes, hipMemcpyDeviceToHost, s2));
-    CK(hipStreamSynchronize(s2));
-    const double d2h = bytes / (now_s() - t0) / 1e9;
-    t0 = now_s();
-    CK(hipMemcpyAsync(d1, h1, bytes, hipMemcpyHostToDevice, s1));
-    CK(hipMemcpyAsync(h2, d2, bytes, hipMemcpyDeviceToHost, s2));
-    CK(hipStreamSynchronize(s1));
-    CK(hipStreamSynchronize(s2));
-    const double both = 2.0 * bytes / (now_s() - t0) / 1e9;
-    printf("{\"test\":\"pcie_pinned\",\"bytes\":%zu,\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n", bytes,
-           h2d, d2h, both);
+    for (int f = 0; f < 2; ++f) {
+      void *h1, *h2;
+      CK(hipHostMalloc(&h1, bytes, flag_sets[f]));
+      CK(hipHostMalloc(&h2, bytes, flag_sets[f]));
+      memset(h1, 1, bytes);
+      memset(h2, 2, bytes);
+      double best[3] = {0, 0, 0};
+      for (int rep = 0; rep < 6; ++rep) {
+        double t0 = now_s();
+        CK(hipMemcpyAsync(d1, h1, bytes, hipMemcpyHostToDevice, s1));
+        CK(hipStreamSynchronize(s1));
+        const double h2d = bytes / (now_s() - t0) / 1e9;
+        t0 = now_s();
+        CK(hipMemcpyAsync(h2, d2, bytes, hipMemcpyDeviceToHost, s2));
+        CK(hipStreamSynchronize(s2));
+        const double d2h = bytes / (now_s() - t0) / 1e9;
+        t0 = now_s();
+        CK(hipMemcpyAsync(d1, h1, bytes, hipMemcpyHostToDevice, s1));
+        CK(hipMemcpyAsync(h2, d2, bytes, hipMemcpyDeviceToHost, s2));
+        CK(hipStreamSynchronize(s1));
+        CK(hipStreamSynchronize(s2));
+        const double both = 2.0 * bytes / (now_s() - t0) / 1e9;
+        if (rep > 0) {  // the first repetition is a warm-up
+          best[0] = std::max(best[0], h2d);
+          best[1] = std::max(best[1], d2h);
+          best[2] = std::max(best[2], both);
+        }
+      }
+      printf("{\"test\":\"pcie_pinned\",\"alloc\":\"%s\",\"bytes\":%zu,\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n",
+             names[f], bytes, best[0], best[1], best[2]);
+      CK(hipHostFree(h1));
+      CK(hipHostFree(h2));
+    }
     CK(hipFree(d1));
     CK(hipFree(d2));
-    CK(hipHostFree(h1));
-    CK(hipHostFree(h2));
+  } else if (what == "latency") {
+    // launch -> completion observed by the host, for an empty kernel, by
+    // event query, by stream synchronize and by a flag in pinned host memory
+    // that a trailing kernel stores (vector store, system-scope release);
+    // and the cost of a 1.3 KiB kernel argument
+    const int iters = argc > 2 ? atoi(argv[2]) : 2000;
+    hipStream_t s;
+    CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t ev;
+    CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    uint32_t* flag = nullptr;
+    CK(hipHostMalloc(reinterpret_cast<void**>(&flag), 4096, hipHostMallocDefault));
+    *flag = 0;
+    Big big;
+    memset(&big, 0, sizeof(big));
+    hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, s, 0);
+    CK(hipStreamSynchronize(s));
+    auto run = [&](int mode) {
+      double t0 = now_s();
+      for (int i = 0; i < iters; ++i) {
+        if (mode == 3) hipLaunchKernelGGL(big_arg_kernel, dim3(1), dim3(64), 0, s, big);
+        else hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, s, i);
+        if (mode == 0 || mode == 3) {
+          CK(hipEventRecord(ev, s));
+          while (hipEventQuery(ev) == hipErrorNotReady) {
+          }
+        } else if (mode == 1) {
+          CK(hipStreamSynchronize(s));
+        } else {
+          hipLaunchKernelGGL(signal_kernel, dim3(1), dim3(64), 0, s, flag, static_cast<uint32_t>(i + 1));
+          while (__atomic_load_n(flag, __ATOMIC_ACQUIRE) != static_cast<uint32_t>(i + 1)) {
+          }
+        }
+      }
+      return (now_s() - t0) / iters * 1e6;
+    };
+    const double q = run(0), sy = run(1), wv = run(2), big_q = run(3);
+    printf("{\"test\":\"latency\",\"iters\":%d,\"event_query_us\":%.2f,\"stream_sync_us\":%.2f,"
+           "\"host_flag_us\":%.2f,\"big_arg_event_query_us\":%.2f,\"big_arg_bytes\":%zu}\n",
+           iters, q, sy, wv, big_q, sizeof(Big));
+    CK(hipHostFree(flag));
   } else {
     fprintf(stderr, "unknown test %s\n", what.c_str());
     return 1;
