@@ -173,6 +173,9 @@ int gvm_wait_timed(int rank, int64_t ticket, int64_t timeout_ns, uint64_t* ts);
 /* Wait for whichever outstanding request of `rank` finishes first; its
  * ticket goes to *ticket_out.  GVM_EINVAL if nothing is outstanding. */
 int gvm_wait_any(int rank, int64_t timeout_ns, int64_t* ticket_out);
+/* As gvm_wait_any, and stores the request's timestamps in ts[0..4] as
+ * gvm_wait_timed does (`ts` may be NULL). */
+int gvm_wait_any_timed(int rank, int64_t timeout_ns, int64_t* ticket_out, uint64_t* ts);
 
 /* Rank side, RLS() of Section 5: wait for the rank's outstanding requests,
  * release its VGPU and unmap its segments.  Device buffers of the rank are

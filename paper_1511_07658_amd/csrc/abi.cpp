@@ -87,6 +87,11 @@ int gvm_wait_any(int rank, int64_t timeout_ns, int64_t* ticket_out) {
   return gvm::rank_wait_any(rank, timeout_ns, ticket_out);
 }
 
+int gvm_wait_any_timed(int rank, int64_t timeout_ns, int64_t* ticket_out, uint64_t* ts) {
+  gvm::clear_error();
+  return gvm::rank_wait_any(rank, timeout_ns, ticket_out, ts);
+}
+
 int gvm_detach(int rank) {
   gvm::clear_error();
   return gvm::rank_detach(rank);

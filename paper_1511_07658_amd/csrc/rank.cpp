@@ -402,7 +402,7 @@ int rank_wait(int rank, int64_t ticket, int64_t timeout_ns, uint64_t* ts) {
   return st;
 }
 
-int rank_wait_any(int rank, int64_t timeout_ns, int64_t* ticket_out) {
+int rank_wait_any(int rank, int64_t timeout_ns, int64_t* ticket_out, uint64_t* ts) {
   if (rank < 0 || rank >= kMaxRanks) return fail(GVM_EINVAL, "rank %d out of range", rank);
   RankHandle& h = g_ranks[rank];
   std::lock_guard<std::mutex> lk(h.mu);
@@ -416,7 +416,18 @@ int rank_wait_any(int rank, int64_t timeout_ns, int64_t* ticket_out) {
     if (jt->first < it->first) it = jt;
   if (ticket_out) *ticket_out = static_cast<int64_t>(it->first);
   const int st = it->second;
-  h.timing.erase(it->first);
+  auto tt = h.timing.find(it->first);
+  if (ts) {
+    for (int i = 0; i < 5; ++i) ts[i] = 0;
+    if (tt != h.timing.end()) {
+      ts[0] = tt->second.t_submit_ns;
+      ts[1] = tt->second.t_admit_ns;
+      ts[2] = tt->second.t_launch_ns;
+      ts[3] = tt->second.t_device_ns;
+      ts[4] = tt->second.t_done_ns;
+    }
+  }
+  if (tt != h.timing.end()) h.timing.erase(tt);
   h.finished.erase(it);
   return st;
 }

@@ -105,6 +105,8 @@ def lib():
         L.gvm_wait_timed.restype = i32
         L.gvm_wait_any.argtypes = [i32, i64, ctypes.POINTER(i64)]
         L.gvm_wait_any.restype = i32
+        L.gvm_wait_any_timed.argtypes = [i32, i64, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_uint64)]
+        L.gvm_wait_any_timed.restype = i32
         L.gvm_detach.argtypes = [i32]
         L.gvm_detach.restype = i32
         L.gvm_shutdown.argtypes = []
@@ -180,6 +182,14 @@ def gvm_wait_any(rank, timeout_ns=-1):
     t = ctypes.c_int64(-1)
     rc = lib().gvm_wait_any(rank, timeout_ns, ctypes.byref(t))
     return rc, t.value
+
+
+def gvm_wait_any_timed(rank, timeout_ns=-1):
+    """Returns (status, ticket, [t_submit, t_admit, t_launch, t_device, t_done])."""
+    t = ctypes.c_int64(-1)
+    ts = (ctypes.c_uint64 * 5)()
+    rc = lib().gvm_wait_any_timed(rank, timeout_ns, ctypes.byref(t), ts)
+    return rc, t.value, list(ts)
 
 
 def gvm_detach(rank) -> int:

@@ -60,8 +60,10 @@ class _Inputs:
         self.B = g.standard_normal(MAX_GEMM * MAX_GEMM, dtype=np.float32)
         self.buf = np.empty(max(2 * MAX_VEC, 3 * MAX_BS, 2 * MAX_GEMM * MAX_GEMM), np.float32)
 
-    def packed(self, k, n):
-        b = self.buf
+    def packed(self, k, n, b=None):
+        """The packed input of a request (k, n), written into `b` (default:
+        a private buffer) and returned as a view."""
+        b = self.buf if b is None else b
         if k == G.GVM_K_VECADD:
             b[:n] = self.a[:n]
             b[n:2 * n] = self.b[:n]
@@ -85,11 +87,23 @@ def _work(k, n):
     return float(n), 12.0 * n
 
 
-def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier):
+def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot_bytes=0, nslots=2):
     """One open-loop rank against the manager; returns per-request records
-    (arrival offset s, kernel, n, latency s, status)."""
+    (arrival offset s, kernel, n, latency s, status).
+
+    With `zero_copy` the rank builds each input directly in its shared-memory
+    space (`nslots` request slots of `slot_bytes` from gvm_rank_buffer) and
+    takes the result there, so the API copies nothing on the rank side."""
     inp = _Inputs(rank)
     G.check(G.gvm_attach_ns(ns, rank), "attach")
+    space = None
+    free_slots = []
+    if zero_copy:
+        space = G.gvm_rank_buffer(rank, slot_bytes * nslots)
+        if space is None:
+            raise RuntimeError(f"rank {rank}: no zero-copy space: {G.gvm_last_error()}")
+        per = slot_bytes // 4
+        free_slots = [space[i * per:(i + 1) * per] for i in range(nslots)]
     barrier.wait()
     barrier.wait()  # the parent has written the common start time
     t0 = start_box.value
@@ -98,26 +112,43 @@ def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier):
     i = 0
     while i < len(trace) or pending:
         now = _now()
-        if i < len(trace) and now >= t0 + int(trace[i][0] * 1e9):
+        if i < len(trace) and now >= t0 + int(trace[i][0] * 1e9) and (free_slots or not zero_copy):
             ta, k, n = trace[i]
-            o = np.empty(G.out_elems(k, n), np.float32)
-            t = G.gvm_submit(rank, k, inp.packed(k, n), o, n)
-            if t < 0:
-                out.append((ta, k, n, -1.0, int(t)))
+            if zero_copy:
+                slot = free_slots.pop()
+                ni, no = G.in_elems(k, n), G.out_elems(k, n)
+                x = inp.packed(k, n, slot)
+                o = slot[ni:ni + no]
             else:
-                pending[t] = (ta, k, n, o)
+                slot = None
+                x = inp.packed(k, n)
+                o = np.empty(G.out_elems(k, n), np.float32)
+            t = G.gvm_submit(rank, k, x, o, n)
+            if t < 0:
+                out.append((ta, k, n, -1.0, int(t), None))
+                if slot is not None:
+                    free_slots.append(slot)
+            else:
+                pending[t] = (ta, k, n, slot)
             i += 1
             continue
         if not pending:
             time.sleep(max(0.0, (t0 + int(trace[i][0] * 1e9) - now) * 1e-9))
             continue
+        # all slots busy: the arrival waits in the rank (its latency counts)
         wait_ns = (t0 + int(trace[i][0] * 1e9) - now) if i < len(trace) else 60_000_000_000
-        rc, t = G.gvm_wait_any(rank, max(wait_ns, 0))
+        rc, t, ts = G.gvm_wait_any_timed(rank, max(wait_ns, 0))
         if rc == G.GVM_ETIMEDOUT:
             continue
         if t in pending:
-            ta, k, n, o = pending.pop(t)
-            out.append((ta, k, n, (_now() - t0) * 1e-9 - ta, rc))
+            ta, k, n, slot = pending.pop(t)
+            arrive = t0 + int(ta * 1e9)
+            # arrival->submit (rank queue), submit->admit, admit->launch (copy-in),
+            # launch->device done, device done->posted (copy-out)
+            stages = (ts[0] - arrive, ts[1] - ts[0], ts[2] - ts[1], ts[3] - ts[2], ts[4] - ts[3]) if ts[4] else None
+            out.append((ta, k, n, (_now() - t0) * 1e-9 - ta, rc, stages))
+            if slot is not None:
+                free_slots.append(slot)
         elif rc < 0:
             raise RuntimeError(f"rank {rank}: wait failed {rc}: {G.gvm_last_error()}")
     G.gvm_detach(rank)
@@ -142,7 +173,7 @@ def plain_proc(traces, start_box, barrier, rate_r, rate_v):
             time.sleep((tgt - now) * 1e-9)
         o = np.empty(G.out_elems(k, n), np.float32)
         rc, _ = G.gvm_plain_run(k, pools[r].packed(k, n), o, n, rate_r, rate_v)
-        out.append((ta, k, n, (_now() - t0) * 1e-9 - ta, rc))
+        out.append((ta, k, n, (_now() - t0) * 1e-9 - ta, rc, None))
     return out
 
 
@@ -158,8 +189,13 @@ def summarize(records, warmup_s, duration_s):
         return round(v[idx - 1] * 1e3, 3)
 
     window = duration_s - warmup_s
-    flop = sum(_work(k, n)[0] for _, k, n, _, _ in ok)
-    byts = sum(_work(k, n)[1] for _, k, n, _, _ in ok)
+    flop = sum(_work(x[1], x[2])[0] for x in ok)
+    byts = sum(_work(x[1], x[2])[1] for x in ok)
+    st = [x[5] for x in ok if x[5] is not None]
+    stage_ms = None
+    if st:
+        names = ["rank_queue", "submit_to_admit", "admit_to_launch", "launch_to_device_done", "device_done_to_posted"]
+        stage_ms = {nm: round(float(np.mean([s[i] for s in st])) * 1e-6, 3) for i, nm in enumerate(names)}
     per_kernel = {}
     for name, kid in (("vecadd", 1), ("blackscholes", 2), ("sgemm", 3)):
         lk = sorted(x[3] for x in ok if x[1] == kid)
@@ -168,7 +204,7 @@ def summarize(records, warmup_s, duration_s):
             "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": pct(lat, 100),
             "throughput_req_s": round(len(ok) / window, 2),
             "gemm_GFLOPs": round(flop / window / 1e9, 2), "algorithmic_GBs": round(byts / window / 1e9, 2),
-            "per_kernel": per_kernel}
+            "per_kernel": per_kernel, "mean_stage_ms": stage_ms}
 
 
 def main(argv=None):
@@ -180,6 +216,8 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--plain-procs", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-api", action="store_true",
+                    help="ranks pass private buffers (the API copies them) instead of building in shared memory")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
     a = ap.parse_args(argv)
     if a.loopback:
@@ -188,7 +226,7 @@ def main(argv=None):
     spmd.prestart()
     ctx = spmd.context()
     r32, v32 = float(np.float32(wl.BS_RATE)), float(np.float32(wl.BS_VOLATILITY))
-    result = {"config": {"ranks": a.ranks, "rate_req_s": a.rate, "duration_s": a.duration, "warmup_s": a.warmup,
+    result = {"config": {"ranks": a.ranks, "rank_buffers": "copied by the API" if a.copy_api else "zero-copy in shm", "rate_req_s": a.rate, "duration_s": a.duration, "warmup_s": a.warmup,
                          "budget_GiB": a.budget_gib, "kernels": "vecadd n<=2^24, Black-Scholes n<=4M, SGEMM n<=2048",
                          "requests_in_trace": sum(len(t) for t in traces)}}
 
@@ -216,7 +254,8 @@ def main(argv=None):
               flush=True)
 
     ns = f"gvm.serve.{os.getpid()}"
-    space = (2 * MAX_VEC + MAX_VEC) * 4 * 2 + (1 << 20)   # two largest vector requests in flight
+    slot = (2 * MAX_VEC + MAX_VEC) * 4                    # the largest request: vector add of 2^24, in + out
+    space = slot * 2 + (1 << 20)                          # two requests in flight per rank
     cfg = G.gvm_config_default(nranks=a.ranks, shm_bytes_per_rank=space, staging_bytes=(3 * MAX_VEC) * 4 + (1 << 20),
                                hbm_budget_bytes=int(a.budget_gib * (1 << 30)), mode=G.GVM_MODE_SERVING,
                                policy=G.GVM_POLICY_AUTO, max_inflight=a.ranks, copy_threads=8, name=ns,
@@ -228,8 +267,9 @@ def main(argv=None):
         res = {}
 
         def run_gvm():
-            res["r"] = spmd.run_processes(gvm_rank, [(ns, r, traces[r], start, a.warmup, bar) for r in range(a.ranks)],
-                                          timeout_s=a.duration * 20 + 300)
+            res["r"] = spmd.run_processes(
+                gvm_rank, [(ns, r, traces[r], start, a.warmup, bar, not a.copy_api, slot, 2) for r in range(a.ranks)],
+                timeout_s=a.duration * 20 + 300)
 
         th = threading.Thread(target=run_gvm)
         th.start()
