@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <string>
 #include <vector>
@@ -161,18 +162,15 @@ class HipDevice final : public Device {
     return rc;
   }
 
-  // Several jobs of a batch often share one completion event: its state is
-  // queried once per polling round (begin_poll) and remembered once done.
   int query(Job* j) override {
     auto* b = static_cast<Batch*>(j->batch);
     if (j->status != GVM_OK) return 1;
     hipEvent_t ev = b->done[j->done_index];
     if (!ev) return 1;
     auto it = b->state.find(ev);
-    if (it == b->state.end() || (it->second.round != poll_round_ && !it->second.done)) {
+    if (it == b->state.end()) {  // not tracked (cannot happen): ask directly
       const hipError_t e = hipEventQuery(ev);
-      EventState st{poll_round_, e == hipSuccess, e};
-      it = b->state.insert_or_assign(ev, st).first;
+      it = b->state.insert_or_assign(ev, EventState{0, e == hipSuccess, e}).first;
     }
     if (it->second.done) {
       if (!j->t_device_ns) j->t_device_ns = now_ns();
@@ -183,7 +181,19 @@ class HipDevice final : public Device {
     return -1;
   }
 
-  void begin_poll() override { ++poll_round_; }
+  // One polling round: per stream, settle the pending events in order.
+  void begin_poll() override {
+    for (auto& kv : fifo_) {
+      auto& q = kv.second;
+      while (!q.empty()) {
+        FifoEntry& e = q.front();
+        const hipError_t r = hipEventQuery(e.ev);
+        if (r == hipErrorNotReady) break;
+        e.b->state[e.ev] = EventState{0, r == hipSuccess, r};
+        q.pop_front();
+      }
+    }
+  }
 
   void finish(Job* j) override {
     auto* b = static_cast<Batch*>(j->batch);
@@ -270,7 +280,17 @@ class HipDevice final : public Device {
     if (!e) return GVM_EDEVICE;
     HIPCHK(hipEventRecord(e, s));
     b->done[i] = e;
+    track(b, e, s);
     return GVM_OK;
+  }
+
+  // Completion events in the order they were recorded on each stream; an
+  // event can only complete after every earlier one of its stream, so a
+  // polling round asks the runtime about the oldest pending one per stream.
+  void track(Batch* b, hipEvent_t ev, hipStream_t s) {
+    if (b->state.count(ev)) return;
+    b->state[ev] = EventState{0, false, hipErrorNotReady};
+    fifo_[s].push_back(FifoEntry{b, ev});
   }
 
   int enqueue_in(Job* j, hipStream_t s) {
@@ -441,6 +461,7 @@ class HipDevice final : public Device {
     hipEvent_t done = sync_event(b);
     if (!done) return GVM_EDEVICE;
     HIPCHK(hipEventRecord(done, c0));
+    track(b, done, c0);
     for (size_t i = 0; i < jobs.size(); ++i) b->done[i] = done;
     return GVM_OK;
   }
@@ -494,6 +515,7 @@ class HipDevice final : public Device {
       hipEvent_t kev = k[stream_of[i]];
       if (!j->copy_out) {
         b->done[i] = kev;
+        if (!capture) track(b, kev, stream_of[i] == 0 ? c0 : c1);
         continue;
       }
       hipStream_t s = rank_stream(j->rank);
@@ -540,6 +562,10 @@ class HipDevice final : public Device {
   }
 
   void retire(Batch* b) {
+    for (auto& kv : fifo_) {
+      auto& q = kv.second;
+      for (auto it = q.begin(); it != q.end();) it = (it->b == b) ? q.erase(it) : std::next(it);
+    }
     for (auto& t : b->timed) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, t.e0, t.e1) == hipSuccess && t.kernel_id >= 0 && t.kernel_id < 5) {
@@ -597,7 +623,11 @@ class HipDevice final : public Device {
   std::vector<hipStream_t> rank_streams_;
   std::vector<hipStream_t> compute_streams_;
   size_t next_cs_ = 0;
-  uint64_t poll_round_ = 0;
+  struct FifoEntry {
+    Batch* b;
+    hipEvent_t ev;
+  };
+  std::map<hipStream_t, std::deque<FifoEntry>> fifo_;
   uint8_t* arena_ = nullptr;
   std::vector<uint8_t*> staging_;
   uint64_t staging_bytes_ = 0;

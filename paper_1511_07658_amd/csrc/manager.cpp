@@ -350,7 +350,7 @@ void Manager::reap_rank(int r) {
 
 void Manager::check_liveness() {
   const uint64_t now = now_ns();
-  if (now - last_liveness_ns_ < 5000000) return;
+  if (now - last_liveness_ns_ < 20000000) return;  // every 20 ms
   last_liveness_ns_ = now;
   const int32_t self = getpid();
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {

@@ -3,6 +3,7 @@
 //                         also the reference kernel for scaling FETCH_SIZE/WRITE_SIZE)
 //   mfma   <iters>        FP32 MFMA issue rate (v_mfma_f32_32x32x2_f32 chains)
 //   pcie   <MiB>          pinned host<->device copy rates, one direction and both
+//   hostcopy <MiB>        CPU memcpy pageable <-> pinned, 1 and 8 threads
 //   latency <iters>       launch -> completion seen by the host (event query,
 //                         stream synchronize, kernel-written host flag)
 //   init                  time to create the device context in a fresh process
@@ -15,6 +16,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
+#include <vector>
 
 #define CK(x)                                                                          \
   do {                                                                                 \
@@ -240,6 +243,45 @@ int main(int argc, char** argv) {
     }
     CK(hipFree(d1));
     CK(hipFree(d2));
+  } else if (what == "hostcopy") {
+    // CPU memcpy between pageable memory and pinned staging, as the manager's
+    // copy engine does it: 1 and 8 threads, default and non-coherent pinned
+    const size_t bytes = (argc > 2 ? strtoull(argv[2], nullptr, 10) : 512) << 20;
+    const unsigned flag_sets[2] = {hipHostMallocDefault, hipHostMallocNonCoherent};
+    const char* names[2] = {"default", "noncoherent"};
+    char* pageable = static_cast<char*>(aligned_alloc(4096, bytes));
+    memset(pageable, 3, bytes);
+    for (int f = 0; f < 2; ++f) {
+      char* pin = nullptr;
+      CK(hipHostMalloc(reinterpret_cast<void**>(&pin), bytes, flag_sets[f]));
+      memset(pin, 4, bytes);
+      for (int nt : {1, 8}) {
+        auto par = [&](char* dst, const char* src) {
+          std::vector<std::thread> th;
+          const size_t part = bytes / nt;
+          for (int t = 0; t < nt; ++t)
+            th.emplace_back([=] { memcpy(dst + t * part, src + t * part, part); });
+          for (auto& x : th) x.join();
+        };
+        double in_best = 0, out_best = 0;
+        for (int rep = 0; rep < 4; ++rep) {
+          double t0 = now_s();
+          par(pin, pageable);
+          const double in = bytes / (now_s() - t0) / 1e9;
+          t0 = now_s();
+          par(pageable, pin);
+          const double out = bytes / (now_s() - t0) / 1e9;
+          if (rep > 0) {
+            in_best = std::max(in_best, in);
+            out_best = std::max(out_best, out);
+          }
+        }
+        printf("{\"test\":\"hostcopy\",\"pinned\":\"%s\",\"threads\":%d,\"to_pinned_GBps\":%.1f,\"from_pinned_GBps\":%.1f}\n",
+               names[f], nt, in_best, out_best);
+      }
+      CK(hipHostFree(pin));
+    }
+    free(pageable);
   } else if (what == "latency") {
     // launch -> completion observed by the host, for an empty kernel, by
     // event query, by stream synchronize and by a flag in pinned host memory
