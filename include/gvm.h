@@ -125,6 +125,9 @@ typedef struct gvm_config {
   uint32_t copy_threads;        /* host threads for shared-memory <-> pinned copies (0 = 4) */
   float bs_rate;                /* Black-Scholes risk-free rate r (default 0.02) */
   float bs_volatility;          /* Black-Scholes volatility sigma (default 0.30) */
+  uint32_t batch_timing;        /* 1: time every batch's device phase (first copy-in to last
+                                   copy-out) and every copy with device events (gvm_stats_json) */
+  uint32_t reserved;
   char name[GVM_NAME_MAX];      /* shared-memory namespace; "" = "gvm.<uid>" */
 } gvm_config;
 

@@ -72,6 +72,8 @@ class Device {
   virtual const KernelStats* kernel_stats() const = 0;  // indexed by kernel id (0..4)
   virtual void reset_stats() = 0;
   virtual std::string describe() const = 0;
+  // Batch device phases and copy timings (batch_timing), as a JSON object.
+  virtual std::string timing_json() const { return "{}"; }
 };
 
 std::unique_ptr<Device> make_hip_device();

@@ -37,8 +37,16 @@ struct EventState {
   hipError_t err;
 };
 
+struct TimedCopy {
+  int dir;  // 0 host->device, 1 device->host
+  hipEvent_t e0, e1;
+  uint64_t bytes;
+};
+
 struct Batch {
   std::map<hipEvent_t, EventState> state;  // polled completion events
+  hipEvent_t span0 = nullptr, span1 = nullptr;  // device phase of the batch (batch_timing)
+  std::vector<TimedCopy> copies;                // timed copies (batch_timing)
   std::vector<Job*> jobs;
   std::vector<hipEvent_t> done;   // per job (several jobs may share one event)
   std::vector<hipEvent_t> sync;   // events owned by the batch, recycled at the end
@@ -127,7 +135,26 @@ class HipDevice final : public Device {
       jobs[i]->t_launch_ns = now_ns();
     }
     int rc = GVM_OK;
-    if (policy == GVM_POLICY_PS2) {
+    // device phase of the batch: every stream it uses starts after span0 and
+    // span1 follows them all (batch_timing; not combined with graph replay)
+    std::vector<hipStream_t> span_streams;
+    const bool span = cfg_.batch_timing && !cfg_.use_graphs;
+    if (span) {
+      hipStream_t c0 = compute_streams_[0];
+      span_streams = {compute_streams_[1]};
+      for (Job* j : jobs) {
+        hipStream_t s = rank_stream(j->rank);
+        if (std::find(span_streams.begin(), span_streams.end(), s) == span_streams.end()) span_streams.push_back(s);
+      }
+      b->span0 = timed_event();
+      b->span1 = timed_event();
+      if (!b->span0 || !b->span1) rc = fail(GVM_EDEVICE, "hipEventCreate failed");
+      if (rc == GVM_OK && hipEventRecord(b->span0, c0) != hipSuccess) rc = fail(GVM_EDEVICE, "event record failed");
+      for (hipStream_t s : span_streams)
+        if (rc == GVM_OK && hipStreamWaitEvent(s, b->span0, 0) != hipSuccess) rc = fail(GVM_EDEVICE, "stream wait failed");
+    }
+    if (rc != GVM_OK) {
+    } else if (policy == GVM_POLICY_PS2) {
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         Job* j = jobs[i];
         hipStream_t s = rank_stream(j->rank);
@@ -150,6 +177,21 @@ class HipDevice final : public Device {
       }
     } else {
       rc = launch_grouped(b);
+    }
+    if (span && rc == GVM_OK) {
+      hipStream_t c0 = compute_streams_[0];
+      for (hipStream_t s : span_streams) {
+        hipEvent_t ev = sync_event(b);
+        if (!ev || hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(c0, ev, 0) != hipSuccess) {
+          rc = fail(GVM_EDEVICE, "span join failed");
+          break;
+        }
+      }
+      if (rc == GVM_OK && hipEventRecord(b->span1, c0) != hipSuccess) rc = fail(GVM_EDEVICE, "event record failed");
+      if (rc == GVM_OK) {  // the jobs complete with the span
+        track(b, b->span1, c0);
+        for (size_t i = 0; i < jobs.size(); ++i) b->done[i] = b->span1;
+      }
     }
     batches_.push_back(b);
     if (rc != GVM_OK) {
@@ -213,6 +255,12 @@ class HipDevice final : public Device {
         (void)hipEventDestroy(t.e0);
         (void)hipEventDestroy(t.e1);
       }
+      for (auto& c : b->copies) {
+        (void)hipEventDestroy(c.e0);
+        (void)hipEventDestroy(c.e1);
+      }
+      if (b->span0) (void)hipEventDestroy(b->span0);
+      if (b->span1) (void)hipEventDestroy(b->span1);
       delete b;
     }
     batches_.clear();
@@ -239,6 +287,22 @@ class HipDevice final : public Device {
   const KernelStats* kernel_stats() const override { return stats_; }
   void reset_stats() override {
     for (auto& s : stats_) s = KernelStats{};
+    batch_us_.clear();
+    for (int d = 0; d < 2; ++d) copy_ms_[d] = copy_bytes_[d] = 0.0, copy_n_[d] = 0;
+  }
+
+  std::string timing_json() const override {
+    std::string s = "{\"batch_device_us\":[";
+    const size_t first = batch_us_.size() > 512 ? batch_us_.size() - 512 : 0;
+    for (size_t i = first; i < batch_us_.size(); ++i) {
+      if (i > first) s += ",";
+      s += std::to_string(batch_us_[i]);
+    }
+    char buf[256];
+    snprintf(buf, sizeof(buf), "],\"h2d\":{\"count\":%llu,\"ms\":%.6f,\"bytes\":%.0f},\"d2h\":{\"count\":%llu,\"ms\":%.6f,\"bytes\":%.0f}}",
+             (unsigned long long)copy_n_[0], copy_ms_[0], copy_bytes_[0], (unsigned long long)copy_n_[1], copy_ms_[1],
+             copy_bytes_[1]);
+    return s + buf;
   }
   std::string describe() const override {
     return "{\"backend\":\"hip\",\"arch\":\"" + arch_ + "\",\"cus\":" + std::to_string(cus_) +
@@ -293,17 +357,35 @@ class HipDevice final : public Device {
     fifo_[s].push_back(FifoEntry{b, ev});
   }
 
+  // One copy of a job between its pinned staging and its device slot; with
+  // batch_timing (and outside a capture) bracketed by timing events.
+  int timed_copy(void* dst, const void* src, uint64_t bytes, hipMemcpyKind kind, hipStream_t s, Batch* b) {
+    TimedCopy t{kind == hipMemcpyHostToDevice ? 0 : 1, nullptr, nullptr, bytes};
+    const bool timed = cfg_.batch_timing && !capturing_ && b;
+    if (timed) {
+      t.e0 = timed_event();
+      t.e1 = timed_event();
+      if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
+      HIPCHK(hipEventRecord(t.e0, s));
+    }
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, kind, s));
+    if (timed) {
+      HIPCHK(hipEventRecord(t.e1, s));
+      b->copies.push_back(t);
+    }
+    return GVM_OK;
+  }
+
   int enqueue_in(Job* j, hipStream_t s) {
     if (!j->copy_in) return GVM_OK;
-    HIPCHK(hipMemcpyAsync(j->slot, j->pin, j->lay.in_bytes, hipMemcpyHostToDevice, s));
-    return GVM_OK;
+    return timed_copy(j->slot, j->pin, j->lay.in_bytes, hipMemcpyHostToDevice, s, static_cast<Batch*>(j->batch));
   }
 
   int enqueue_out(Job* j, hipStream_t s) {
     if (!j->copy_out) return GVM_OK;
     const uint64_t o = slot_out_offset(j->lay);
-    HIPCHK(hipMemcpyAsync(j->pin + o, j->slot + o, j->lay.out_bytes, hipMemcpyDeviceToHost, s));
-    return GVM_OK;
+    return timed_copy(j->pin + o, j->slot + o, j->lay.out_bytes, hipMemcpyDeviceToHost, s,
+                      static_cast<Batch*>(j->batch));
   }
 
   // One grouped launch per kernel id (per tile configuration for SGEMM), at
@@ -422,7 +504,9 @@ class HipDevice final : public Device {
     if (it == graphs_.end()) {
       if (graphs_.size() >= kMaxGraphs) evict_graph();
       HIPCHK(hipStreamBeginCapture(c0, hipStreamCaptureModeThreadLocal));
+      capturing_ = true;
       int rc = enqueue_grouped(b, true);
+      capturing_ = false;
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(c0, &g);
       if (rc != GVM_OK) {
@@ -485,9 +569,10 @@ class HipDevice final : public Device {
       HIPCHK(hipStreamWaitEvent(c1, fork, 0));
     }
     // copy-ins, then both compute streams wait for them
-    for (Job* j : jobs)
-      if (j->copy_in)
-        HIPCHK(hipMemcpyAsync(j->slot, j->pin, j->lay.in_bytes, hipMemcpyHostToDevice, rank_stream(j->rank)));
+    for (Job* j : jobs) {
+      const int rc0 = enqueue_in(j, rank_stream(j->rank));
+      if (rc0 != GVM_OK) return rc0;
+    }
     for (hipStream_t s : used) {
       hipEvent_t ev = sync_event(b);
       if (!ev) return GVM_EDEVICE;
@@ -520,8 +605,8 @@ class HipDevice final : public Device {
       }
       hipStream_t s = rank_stream(j->rank);
       HIPCHK(hipStreamWaitEvent(s, kev, 0));
-      const uint64_t o = slot_out_offset(j->lay);
-      HIPCHK(hipMemcpyAsync(j->pin + o, j->slot + o, j->lay.out_bytes, hipMemcpyDeviceToHost, s));
+      rc = enqueue_out(j, s);
+      if (rc != GVM_OK) return rc;
       if (!capture) {
         rc = record_done(b, i, s);
         if (rc != GVM_OK) return rc;
@@ -580,6 +665,23 @@ class HipDevice final : public Device {
       free_timed_.push_back(t.e0);
       free_timed_.push_back(t.e1);
     }
+    if (b->span0 && b->span1) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, b->span0, b->span1) == hipSuccess && batch_us_.size() < 65536)
+        batch_us_.push_back(ms * 1e3);
+      free_timed_.push_back(b->span0);
+      free_timed_.push_back(b->span1);
+    }
+    for (auto& c : b->copies) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, c.e0, c.e1) == hipSuccess) {
+        copy_ms_[c.dir] += ms;
+        copy_bytes_[c.dir] += static_cast<double>(c.bytes);
+        copy_n_[c.dir] += 1;
+      }
+      free_timed_.push_back(c.e0);
+      free_timed_.push_back(c.e1);
+    }
     for (hipEvent_t e : b->sync) free_sync_.push_back(e);
     batches_.erase(std::remove(batches_.begin(), batches_.end(), b), batches_.end());
     delete b;
@@ -628,6 +730,10 @@ class HipDevice final : public Device {
     hipEvent_t ev;
   };
   std::map<hipStream_t, std::deque<FifoEntry>> fifo_;
+  bool capturing_ = false;
+  std::vector<double> batch_us_;
+  double copy_ms_[2] = {0, 0}, copy_bytes_[2] = {0, 0};
+  uint64_t copy_n_[2] = {0, 0};
   uint8_t* arena_ = nullptr;
   std::vector<uint8_t*> staging_;
   uint64_t staging_bytes_ = 0;

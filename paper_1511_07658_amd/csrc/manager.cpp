@@ -399,6 +399,7 @@ bool Manager::complete_jobs() {
     const KernelStats* ks = dev_->kernel_stats();
     for (int k = 0; k < 5; ++k) kstats_[k] = ks[k];
     peak_bytes_ = std::max(peak_bytes_, arena_.peak());
+    if (cfg_.batch_timing) timing_json_ = dev_->timing_json();
   }
   if (cfg_.mode == GVM_MODE_BATCH && batch_open_ && inflight_ == 0) batch_open_ = false;
   return any;
@@ -614,7 +615,7 @@ int Manager::stats_json(std::string* out) {
   std::lock_guard<std::mutex> lk(stats_mu_);
   char buf[512];
   std::string s = "{";
-  s += "\"namespace\":\"" + ns_ + "\",\"device\":" + dev_->describe();
+  s += "\"namespace\":\"" + ns_ + "\",\"device\":" + dev_->describe() + ",\"timing\":" + timing_json_;
   snprintf(buf, sizeof(buf), ",\"requests_done\":%llu,\"requests_failed\":%llu,\"batches\":%llu,\"peak_device_bytes\":%llu,\"arena_bytes\":%llu",
            (unsigned long long)n_done_, (unsigned long long)n_err_, (unsigned long long)n_batches_,
            (unsigned long long)std::max(peak_bytes_, arena_.peak()), (unsigned long long)arena_.total());
@@ -648,6 +649,7 @@ void Manager::reset_stats() {
   wait_us_.clear();
   for (auto& k : kstats_) k = KernelStats{};
   peak_bytes_ = 0;
+  timing_json_ = "{}";
   // the device counters are reset on the service thread's next completion
   reset_pending_.store(true);
 }

@@ -111,6 +111,7 @@ class Manager {
   std::vector<double> wait_us_;        // submit -> admitted
   KernelStats kstats_[5];
   uint64_t peak_bytes_ = 0;
+  std::string timing_json_ = "{}";
 };
 
 }  // namespace gvm

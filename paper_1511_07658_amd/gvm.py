@@ -72,6 +72,8 @@ class gvm_config(ctypes.Structure):
         ("copy_threads", ctypes.c_uint32),
         ("bs_rate", ctypes.c_float),
         ("bs_volatility", ctypes.c_float),
+        ("batch_timing", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
         ("name", ctypes.c_char * GVM_NAME_MAX),
     ]
 

@@ -1,0 +1,116 @@
+"""The execution model of Section 4.2.3 against the GVM on an MI355X (the
+paper's model-validation experiment of Section 6).
+
+For each kernel and programming style, the per-rank transfer and compute
+times are profiled with one rank, then N = 1..8 ranks run one request each
+as one batch, and the device phase of the batch (first copy-in to last
+copy-out, device events) is compared with the closed forms (Eq. 2/4 for
+PS-1, Eq. 3/7 for PS-2) and with the discrete-event schedule under the
+paper's single-queue rules and under independent queues.  Every kernel here
+is I/O-intensive on this machine (PCIe ~57 GB/s against ~110 TFLOP/s FP32).
+
+The table goes to stdout (and to $GVM_VALIDATION_OUT as JSON when set).  The
+assertions are loose sanity bounds: the point is the reported deviations.
+"""
+
+import json
+import os
+import statistics
+import threading
+
+import numpy as np
+import pytest
+
+from oracle import des
+from oracle import model
+from paper_1511_07658_amd import gvm as G
+from paper_1511_07658_amd import spmd
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("vecadd", G.GVM_K_VECADD, 1 << 22), ("sgemm", G.GVM_K_SGEMM, 1024)]
+NS_LIST = [1, 2, 4, 8]
+REPS = 5
+
+
+def _run(ns, kernel_id, n, nranks, reps):
+    """`nranks` rank threads, `reps` batches of one request per rank (inputs
+    built in shared memory); returns the manager statistics."""
+    errs = []
+    bar = threading.Barrier(nranks)
+
+    def rank(r):
+        try:
+            assert G.gvm_attach_ns(ns, r) == 0
+            ni, no = G.in_elems(kernel_id, n), G.out_elems(kernel_id, n)
+            view = G.gvm_rank_buffer(r, (ni + no) * 4)
+            view[:ni] = spmd.make_input(kernel_id, 71, r, n)
+            for _ in range(reps):
+                bar.wait()
+                t = G.gvm_submit(r, kernel_id, view[:ni], view[ni:ni + no], n)
+                assert t > 0 and G.gvm_wait(r, t, 60_000_000_000) == 0
+            assert G.gvm_detach(r) == 0
+        except Exception as e:  # collected
+            errs.append(repr(e))
+            bar.abort()
+
+    ths = [threading.Thread(target=rank, args=(r,)) for r in range(nranks)]
+    [t.start() for t in ths]
+    [t.join() for t in ths]
+    assert not errs, errs
+    return G.gvm_stats_json()
+
+
+def test_execution_model_on_mi355x(ns_name):
+    rows = []
+    for name, kid, n in CASES:
+        for policy, pname in ((G.GVM_POLICY_PS1, "PS1"), (G.GVM_POLICY_PS2, "PS2")):
+            ns = f"{ns_name}.{name}.{pname}"
+            cfg = G.gvm_config_default(nranks=8, shm_bytes_per_rank=64 << 20, hbm_budget_bytes=2 << 30,
+                                       policy=policy, batch_timing=1, batch_window_us=10_000_000, name=ns)
+            G.check(G.gvm_init(cfg), "gvm_init")
+            try:
+                # profile one rank: T_in, T_out from the timed copies, T_comp from the kernel events
+                G.gvm_stats_reset()
+                st = _run(ns, kid, n, 1, REPS)
+                tm = st["timing"]
+                t_in = tm["h2d"]["ms"] / tm["h2d"]["count"] * 1e-3
+                t_out = tm["d2h"]["ms"] / tm["d2h"]["count"] * 1e-3
+                ks = st["kernels"][name]
+                t_comp = ks["device_ms"] / ks["launches"] * 1e-3
+                for N in NS_LIST:
+                    G.gvm_stats_reset()
+                    st = _run(ns, kid, n, N, REPS)
+                    spans = st["timing"]["batch_device_us"]
+                    assert len(spans) == REPS, (N, spans)
+                    meas = statistics.median(spans) * 1e-6
+                    closed = model.modelled_total(pname, N, t_in, t_comp, t_out)
+                    des_paper = des.simulate(pname, N, t_in, t_comp, t_out, "paper")
+                    des_multi = des.simulate(pname, N, t_in, t_comp, t_out, "multiqueue")
+                    rows.append({
+                        "kernel": name, "n": n, "style": pname, "N": N,
+                        "class": model.classify(t_in, t_comp, t_out),
+                        "t_in_us": round(t_in * 1e6, 2), "t_comp_us": round(t_comp * 1e6, 2),
+                        "t_out_us": round(t_out * 1e6, 2), "measured_us": round(meas * 1e6, 2),
+                        "closed_form_us": round(closed * 1e6, 2), "des_paper_us": round(des_paper * 1e6, 2),
+                        "des_multiqueue_us": round(des_multi * 1e6, 2),
+                        "dev_closed": round(abs(meas - closed) / meas, 4),
+                        "dev_des_multiqueue": round(abs(meas - des_multi) / meas, 4),
+                    })
+            finally:
+                G.gvm_shutdown()
+    hdr = ["kernel", "style", "N", "class", "t_in_us", "t_comp_us", "t_out_us", "measured_us", "closed_form_us",
+           "des_multiqueue_us", "dev_closed", "dev_des_multiqueue"]
+    print("\n" + " | ".join(hdr))
+    for r in rows:
+        print(" | ".join(str(r[h]) for h in hdr))
+    out = os.environ.get("GVM_VALIDATION_OUT")
+    if out:
+        with open(out, "w") as f:
+            json.dump(rows, f, indent=1)
+    # sanity: one rank's device phase is its copy-in + kernel + copy-out
+    for r in rows:
+        if r["N"] == 1:
+            one = r["t_in_us"] + r["t_comp_us"] + r["t_out_us"]
+            assert 0.5 * one <= r["measured_us"] <= 2.0 * one + 50, r
+        assert r["measured_us"] > 0
