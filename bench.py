@@ -41,27 +41,31 @@ PEAK_HBM_GBPS = 8000.0
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # plain 1 GiB copy (fetch x2.000, write x1.000); valid only for the kernel
-# source and tile table they were taken on (sha256 of csrc/kernels.hip then
-# csrc/gemm_tiles.inc; profiles/sgemm_grouped_8x1024.md).
+# sources they were taken on (sha256 over `sources` in csrc/, in order;
+# profiles/sgemm_grouped_8x1024.md).
+SGEMM_SOURCES = ("sgemm.hip", "group_device.hpp", "kernels.hpp", "gemm_tiles.inc")
+STREAM_SOURCES = ("stream_kernels.hip", "group_device.hpp", "kernels.hpp")
 MEASURED_TRAFFIC = {
-    "sgemm8": {"kernels_sha256": "116bf617c6be038fa746ba3accdb8d64a1f8d36ed5435a742e1599160aae70f5",
-               "fetch_kib": 32828.4, "fetch_factor": 2.000, "write_kib": 32768.0, "write_factor": 1.000},
+    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "",
+               "fetch_kib": 0.0, "fetch_factor": 2.000, "write_kib": 0.0, "write_factor": 1.000},
 }
+
+
+def sources_sha256(sources):
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sources:
+        with open(os.path.join(ROOT, "paper_1511_07658_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload):
     """Traffic in bytes per launch, or None if the kernel source changed since
     the counters were taken."""
-    import hashlib
-
     m = MEASURED_TRAFFIC.get(workload)
-    if not m:
-        return None
-    h = hashlib.sha256()
-    for name in ("kernels.hip", "gemm_tiles.inc"):
-        with open(os.path.join(ROOT, "paper_1511_07658_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != m["kernels_sha256"]:
+    if not m or sources_sha256(m["sources"]) != m["kernels_sha256"]:
         return None
     return round((m["fetch_kib"] * m["fetch_factor"] + m["write_kib"] * m["write_factor"]) * 1024)
 

@@ -126,7 +126,10 @@ typedef struct gvm_config {
   float bs_rate;                /* Black-Scholes risk-free rate r (default 0.02) */
   float bs_volatility;          /* Black-Scholes volatility sigma (default 0.30) */
   uint32_t batch_timing;        /* 1: time every batch's device phase (first copy-in to last
-                                   copy-out) and every copy with device events (gvm_stats_json) */
+                                   copy-out) and every copy with device events (gvm_stats_json);
+                                   in batch mode a batch is then enqueued as a whole once all of
+                                   its inputs are staged, as in the execution model of Section
+                                   4.2.3, so that its device phase is one span */
   uint32_t reserved;
   char name[GVM_NAME_MAX];      /* shared-memory namespace; "" = "gvm.<uid>" */
 } gvm_config;

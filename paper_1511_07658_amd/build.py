@@ -38,7 +38,8 @@ HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__", f
               "-I/opt/rocm/include"]
 
 LIB_SOURCES = [
-    ("kernels.hip", "hip"),
+    ("stream_kernels.hip", "hip"),
+    ("sgemm.hip", "hip"),
     ("device_hip.cpp", "hip"),
     ("plain.cpp", "hip"),
     ("device_loopback.cpp", "host"),

@@ -8,6 +8,7 @@
 // HIP backend.
 #include <sys/mman.h>
 
+#include <cstdio>
 #include <cstring>
 
 #include "device.hpp"
@@ -66,14 +67,15 @@ class LoopbackDevice final : public Device {
   }
 
   int launch(std::vector<Job*>& jobs, int /*policy*/) override {
+    const uint64_t t_batch = now_ns();
     for (Job* j : jobs) {
       j->t_launch_ns = now_ns();
-      if (j->copy_in) memcpy(j->slot, j->pin, j->lay.in_bytes);
+      if (j->copy_in) timed_copy(0, j->slot, j->pin, j->lay.in_bytes);
       const uint64_t o = slot_out_offset(j->lay);
       const uint64_t keep = j->lay.in_bytes < j->lay.out_bytes ? j->lay.in_bytes : j->lay.out_bytes;
       memmove(j->slot + o, j->slot, keep);
       memset(j->slot + o + keep, 0, j->lay.out_bytes - keep);
-      if (j->copy_out) memcpy(j->pin + o, j->slot + o, j->lay.out_bytes);
+      if (j->copy_out) timed_copy(1, j->pin + o, j->slot + o, j->lay.out_bytes);
       KernelStats& ks = stats_[j->req.kernel_id < 5 ? j->req.kernel_id : 0];
       ks.launches += 1;
       ks.requests += 1;
@@ -82,6 +84,7 @@ class LoopbackDevice final : public Device {
       ks.work_flop += f;
       ks.work_bytes += b;
     }
+    if (cfg_.batch_timing) batch_us_.push_back((now_ns() - t_batch) * 1e-3);
     return GVM_OK;
   }
 
@@ -105,11 +108,41 @@ class LoopbackDevice final : public Device {
   const KernelStats* kernel_stats() const override { return stats_; }
   void reset_stats() override {
     for (auto& s : stats_) s = KernelStats{};
+    batch_us_.clear();
+    for (int d = 0; d < 2; ++d) copy_ms_[d] = copy_bytes_[d] = 0.0, copy_n_[d] = 0;
   }
   std::string describe() const override { return "{\"backend\":\"loopback\"}"; }
 
+  // Same layout as the HIP backend's, on the host clock (batch_timing).
+  std::string timing_json() const override {
+    if (!cfg_.batch_timing) return "{}";
+    std::string s = "{\"batch_device_us\":[";
+    const size_t first = batch_us_.size() > 512 ? batch_us_.size() - 512 : 0;
+    for (size_t i = first; i < batch_us_.size(); ++i) {
+      if (i > first) s += ",";
+      s += std::to_string(batch_us_[i]);
+    }
+    char buf[256];
+    snprintf(buf, sizeof(buf), "],\"h2d\":{\"count\":%llu,\"ms\":%.6f,\"bytes\":%.0f},\"d2h\":{\"count\":%llu,\"ms\":%.6f,\"bytes\":%.0f}}",
+             (unsigned long long)copy_n_[0], copy_ms_[0], copy_bytes_[0], (unsigned long long)copy_n_[1], copy_ms_[1],
+             copy_bytes_[1]);
+    return s + buf;
+  }
+
  private:
+  void timed_copy(int dir, void* dst, const void* src, uint64_t bytes) {
+    const uint64_t t0 = now_ns();
+    memcpy(dst, src, bytes);
+    if (!cfg_.batch_timing) return;
+    copy_ms_[dir] += (now_ns() - t0) * 1e-6;
+    copy_bytes_[dir] += static_cast<double>(bytes);
+    copy_n_[dir] += 1;
+  }
+
   gvm_config cfg_{};
+  std::vector<double> batch_us_;
+  double copy_ms_[2] = {0, 0}, copy_bytes_[2] = {0, 0};
+  uint64_t copy_n_[2] = {0, 0};
   uint8_t* arena_ = nullptr;
   uint64_t arena_bytes_ = 0;
   std::vector<uint8_t*> staging_;

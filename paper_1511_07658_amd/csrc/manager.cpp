@@ -417,10 +417,12 @@ bool Manager::launch_ready() {
   }
   // A batch of kernels that run as one grouped launch waits for all of its
   // inputs; per-rank launches (PS-2, what AUTO picks when data moves) start
-  // as soon as each input has landed, overlapping the others' copies.
+  // as soon as each input has landed, overlapping the others' copies.  With
+  // batch_timing a batch is enqueued as a whole (one device-phase span).
   bool incremental = cfg_.mode == GVM_MODE_SERVING || cfg_.policy == GVM_POLICY_PS2;
   if (cfg_.policy == GVM_POLICY_AUTO)
     for (const Job* j : staged_) incremental |= (j->copy_in || j->copy_out);
+  if (cfg_.mode == GVM_MODE_BATCH && cfg_.batch_timing) incremental = false;
   std::vector<Job*> ready;
   if (!incremental) {
     if (!all) return false;

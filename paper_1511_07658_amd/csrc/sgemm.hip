@@ -1,0 +1,306 @@
+// SGEMM C = A B (Table 3 "MM", single precision) for the GVM on gfx950:
+// FP32 MFMA (v_mfma_f32_32x32x2_f32) on LDS-staged, double-buffered tiles,
+// as one grouped persistent launch over the tiles of every request of the
+// group.  The unit -> request map is a search over the per-request first tile
+// held in the kernel arguments; a tile is always computed by the same code in
+// the same order, whatever else is in the group, so a rank's C is
+// bit-identical alone and in the mix.
+#include "group_device.hpp"
+
+#include <algorithm>
+#include <cstdlib>
+
+namespace gvm {
+
+namespace {
+
+// ---------------------------------------------------------------- SGEMM
+//
+// Workgroup tile BM x BN, k-step BK, WM x WN waves; each wave owns a
+// (BM/WM) x (BN/WN) block of C as (BM/WM/32) x (BN/WN/32) accumulators of
+// one 32x32 MFMA each.  v_mfma_f32_32x32x2_f32 multiplies a 32x2 slice of A
+// by a 2x32 slice of B; lane l supplies A[l%32][k(l)] and B[k(l)][l%32] and
+// lane group g = l/32 selects which of the two k values it carries.  Within
+// a BK tile, MFMA step s takes k = s for g = 0 and k = BK/2 + s for g = 1.
+//
+// Both operands sit in LDS k-contiguous: As[m][k] and Bs[n][k] (B
+// transposed on the way in; each thread fetches four k-rows of one column,
+// so the global reads stay coalesced along n), rows padded by 4 floats.  A
+// lane's fragments of the whole tile are then contiguous and are read with
+// 16-byte LDS reads before the MFMA sequence starts.  Double buffering: the
+// next tile is fetched into registers at the start of a k-step and written
+// to the other LDS buffer half-way through the MFMAs, so one barrier per
+// k-step remains.  Interior tiles take unchecked loads and stores; edge
+// tiles check every element and read zeros outside the matrix.
+//
+// Persistent grid, XCD-aware: the units (tiles, requests in order, tiles of a
+// request row-major) are dealt to the 8 XCDs in contiguous blocks, so that
+// tiles sharing rows of A and columns of B share an L2.
+
+template <int BM, int BN, int BK, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) {
+  constexpr int NT = WM * WN * 64;
+  constexpr int TM = BM / WM, TN = BN / WN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int KH = BK / 2;
+  constexpr int ST = BK + 4;               // LDS row stride (floats) of As and Bs
+  constexpr int A4 = BM * BK / 4 / NT;     // float4 of A per thread per tile
+  constexpr int B4 = BK * BN / 4 / NT;     // 4-row column pieces of B per thread per tile
+  static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile must be a multiple of 32");
+  static_assert(KH % 4 == 0, "BK must be a multiple of 8");
+  static_assert(A4 >= 1 && B4 >= 1 && A4 * NT * 4 == BM * BK && B4 * NT * 4 == BK * BN, "tile/threads mismatch");
+
+  __shared__ __attribute__((aligned(16))) float As[2][BM * ST];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN * ST];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int li = lane & 31, lg = lane >> 5;
+
+  // XCD-aware order: with G a multiple of 8, workgroup w runs on XCD w % 8;
+  // renumbering it v = (w % 8) * (G / 8) + w / 8 gives each XCD a contiguous
+  // block of units in every round of the stride loop below.
+  const uint32_t G = gridDim.x;
+  const uint32_t U = g.total_units;
+  uint32_t v = blockIdx.x;
+  if (G % kXcds == 0) v = (blockIdx.x % kXcds) * (G / kXcds) + blockIdx.x / kXcds;
+
+  for (uint32_t u = v; u < U; u += G) {
+    const int q = find_request(g, u);
+    const GemmDesc& d = g.d[q];
+    const int n = static_cast<int>(d.n);
+    const uint32_t local = u - d.unit_begin;
+    const int row0 = static_cast<int>(local / d.tiles_n) * BM;
+    const int col0 = static_cast<int>(local % d.tiles_n) * BN;
+    const float* __restrict__ A = d.A;
+    const float* __restrict__ B = d.B;
+    const bool rows_in = row0 + BM <= n, cols_in = col0 + BN <= n;
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{0};
+
+    f32x4 ra[A4], rb[B4];
+    auto load_tile = [&](int k0) {
+      const bool k_in = k0 + BK <= n;
+      if (rows_in && k_in) {
+#pragma unroll
+        for (int i = 0; i < A4; ++i) {
+          const int f = tid + i * NT;
+          const int r = f / (BK / 4), c = (f % (BK / 4)) * 4;
+          const float* p = A + static_cast<size_t>(row0 + r) * n + (k0 + c);
+          if (VEC) ra[i] = *reinterpret_cast<const f32x4*>(p);
+          else ra[i] = f32x4{p[0], p[1], p[2], p[3]};
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < A4; ++i) {
+          const int f = tid + i * NT;
+          const int r = f / (BK / 4), c = (f % (BK / 4)) * 4;
+          const int gr = row0 + r, gc = k0 + c;
+          f32x4 x = f32x4{0};
+          if (gr < n) {
+            const float* p = A + static_cast<size_t>(gr) * n;
+            if (gc + 0 < n) x.x = p[gc + 0];
+            if (gc + 1 < n) x.y = p[gc + 1];
+            if (gc + 2 < n) x.z = p[gc + 2];
+            if (gc + 3 < n) x.w = p[gc + 3];
+          }
+          ra[i] = x;
+        }
+      }
+      if (cols_in && k_in) {
+#pragma unroll
+        for (int i = 0; i < B4; ++i) {
+          const int f = tid + i * NT;
+          const int c = f % BN, kq = f / BN;
+          const float* p = B + static_cast<size_t>(k0 + 4 * kq) * n + (col0 + c);
+          rb[i] = f32x4{p[0], p[n], p[2 * n], p[3 * n]};
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < B4; ++i) {
+          const int f = tid + i * NT;
+          const int c = f % BN, kq = f / BN;
+          const int gr = k0 + 4 * kq, gc = col0 + c;
+          f32x4 x = f32x4{0};
+          if (gc < n) {
+            const float* p = B + gc;
+            if (gr + 0 < n) x.x = p[static_cast<size_t>(gr + 0) * n];
+            if (gr + 1 < n) x.y = p[static_cast<size_t>(gr + 1) * n];
+            if (gr + 2 < n) x.z = p[static_cast<size_t>(gr + 2) * n];
+            if (gr + 3 < n) x.w = p[static_cast<size_t>(gr + 3) * n];
+          }
+          rb[i] = x;
+        }
+      }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < A4; ++i) {
+        const int f = tid + i * NT;
+        const int r = f / (BK / 4), c = (f % (BK / 4)) * 4;
+        *reinterpret_cast<f32x4*>(&As[buf][r * ST + c]) = ra[i];
+      }
+#pragma unroll
+      for (int i = 0; i < B4; ++i) {
+        const int f = tid + i * NT;
+        const int c = f % BN, kq = f / BN;
+        *reinterpret_cast<f32x4*>(&Bs[buf][c * ST + 4 * kq]) = rb[i];
+      }
+    };
+
+    const int ktiles = (n + BK - 1) / BK;
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+    for (int kt = 0; kt < ktiles; ++kt) {
+      const int buf = kt & 1;
+      const bool more = kt + 1 < ktiles;
+      if (more) load_tile((kt + 1) * BK);
+      float af[FM][KH], bf[FN][KH];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const float* src = &As[buf][(wm * TM + i * 32 + li) * ST + lg * KH];
+#pragma unroll
+        for (int j = 0; j < KH; j += 4) {
+          const f32x4 x = *reinterpret_cast<const f32x4*>(src + j);
+          af[i][j] = x.x; af[i][j + 1] = x.y; af[i][j + 2] = x.z; af[i][j + 3] = x.w;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < FN; ++i) {
+        const float* src = &Bs[buf][(wn * TN + i * 32 + li) * ST + lg * KH];
+#pragma unroll
+        for (int j = 0; j < KH; j += 4) {
+          const f32x4 x = *reinterpret_cast<const f32x4*>(src + j);
+          bf[i][j] = x.x; bf[i][j + 1] = x.y; bf[i][j + 2] = x.z; bf[i][j + 3] = x.w;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < KH; ++s) {
+        // The other buffer was last read before the previous barrier.
+        if (s == KH / 2 && more) store_tile(buf ^ 1);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+
+    float* __restrict__ C = d.C;
+    if (rows_in && cols_in) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int col = col0 + wn * TN + j * 32 + li;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = row0 + wm * TM + i * 32 + 8 * (r / 4) + 4 * lg + (r % 4);
+            C[static_cast<size_t>(row) * n + col] = acc[i][j][r];
+          }
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int col = col0 + wn * TN + j * 32 + li;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = row0 + wm * TM + i * 32 + 8 * (r / 4) + 4 * lg + (r % 4);
+            if (row < n && col < n) C[static_cast<size_t>(row) * n + col] = acc[i][j][r];
+          }
+        }
+    }
+  }
+}
+
+// Tile configurations.  Index order is part of the tuner table format.
+const GemmConfig kGemmConfigs[] = {
+    {0, 64, 64, 16, 2, 2},
+    {1, 128, 64, 16, 2, 2},
+    {2, 128, 128, 16, 2, 2},
+    {3, 128, 128, 32, 2, 2},
+    {4, 256, 128, 16, 4, 2},
+    {5, 128, 256, 16, 2, 4},
+    {6, 256, 128, 32, 4, 2},
+    {7, 64, 128, 16, 2, 2},
+};
+constexpr int kNumGemmConfigs = sizeof(kGemmConfigs) / sizeof(kGemmConfigs[0]);
+
+int g_forced_config = -1;
+
+#include "gemm_tiles.inc"   // kTileTable: (n_max, config index) rows written by the tuner
+
+template <int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap) {
+  constexpr int NT = WM * WN * 64;
+  int cap = grid_cap > 0 ? grid_cap : 256 * 2;
+  int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
+  if (grid <= 0) return hipSuccess;
+  if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
+  if (vec)
+    hipLaunchKernelGGL((sgemm_group_kernel<BM, BN, BK, WM, WN, true>), dim3(grid), dim3(NT), 0, s, g);
+  else
+    hipLaunchKernelGGL((sgemm_group_kernel<BM, BN, BK, WM, WN, false>), dim3(grid), dim3(NT), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int gemm_config_count() { return kNumGemmConfigs; }
+const GemmConfig& gemm_config(int idx) { return kGemmConfigs[idx]; }
+void gemm_config_force(int idx) { g_forced_config = (idx >= 0 && idx < kNumGemmConfigs) ? idx : -1; }
+
+int gemm_config_for(uint64_t n) {
+  if (g_forced_config >= 0) return g_forced_config;
+  // tuning and tests only: force one configuration for every size
+  if (const char* env = getenv("GVM_SGEMM_CONFIG")) {
+    const int c = atoi(env);
+    if (c >= 0 && c < kNumGemmConfigs) return c;
+  }
+  for (const auto& row : kTileTable)
+    if (n <= row[0]) return static_cast<int>(row[1]);
+  return kTileTable[sizeof(kTileTable) / sizeof(kTileTable[0]) - 1][1];
+}
+void finalize_gemm_group(GemmGroup& g, int config_idx) {
+  const GemmConfig& c = kGemmConfigs[config_idx];
+  uint32_t u = 0;
+  for (uint32_t i = 0; i < g.count; ++i) {
+    const uint32_t n = g.d[i].n;
+    const uint32_t tm = (n + c.bm - 1) / c.bm, tn = (n + c.bn - 1) / c.bn;
+    g.d[i].tiles_n = tn;
+    g.d[i].unit_begin = u;
+    g.d[i].units = tm * tn;
+    u += tm * tn;
+  }
+  g.total_units = u;
+}
+hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap) {
+  bool vec = true;
+  for (uint32_t i = 0; i < g.count; ++i)
+    if ((g.d[i].n % 4) != 0 || (reinterpret_cast<uintptr_t>(g.d[i].A) & 15) ||
+        (reinterpret_cast<uintptr_t>(g.d[i].B) & 15))
+      vec = false;
+  switch (config_idx) {
+    case 0: return launch_cfg<64, 64, 16, 2, 2>(g, vec, s, grid_cap);
+    case 1: return launch_cfg<128, 64, 16, 2, 2>(g, vec, s, grid_cap);
+    case 2: return launch_cfg<128, 128, 16, 2, 2>(g, vec, s, grid_cap);
+    case 3: return launch_cfg<128, 128, 32, 2, 2>(g, vec, s, grid_cap);
+    case 4: return launch_cfg<256, 128, 16, 4, 2>(g, vec, s, grid_cap);
+    case 5: return launch_cfg<128, 256, 16, 2, 4>(g, vec, s, grid_cap);
+    case 6: return launch_cfg<256, 128, 32, 4, 2>(g, vec, s, grid_cap);
+    case 7: return launch_cfg<64, 128, 16, 2, 2>(g, vec, s, grid_cap);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace gvm

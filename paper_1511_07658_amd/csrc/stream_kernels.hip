@@ -1,0 +1,228 @@
+// Streaming per-rank kernels of the GVM, written for gfx950 (CDNA4, wave64):
+//
+//  * vector add / multiply (Table 3 "VecAdd", "VecMul"): HBM-bound;
+//  * Black-Scholes call + put (Table 3 "BlackScholes"): HBM-bound with a
+//    transcendental-heavy body.
+//
+// Both are grouped persistent launches: one grid walks the work units (vector
+// chunks) of every request of the group; the unit -> request map is a search
+// over the per-request first unit held in the kernel arguments.  A unit is
+// always computed by the same code in the same order, whatever else is in the
+// group, so a rank's output is bit-identical alone and in the mix.
+#include "group_device.hpp"
+
+#include <algorithm>
+#include <cstdlib>
+
+namespace gvm {
+
+namespace {
+
+constexpr int kStreamGrid = 1024;           // persistent grid of the streaming kernels
+constexpr bool kStreamNonTemporal = true;   // non-temporal loads/stores in them
+
+// ---------------------------------------------------------------- vectors
+
+struct AddOp { __device__ __forceinline__ float operator()(float x, float y) const { return x + y; } };
+struct MulOp { __device__ __forceinline__ float operator()(float x, float y) const { return x * y; } };
+
+template <class T, bool NT>
+__device__ __forceinline__ T stream_load(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <class T, bool NT>
+__device__ __forceinline__ void stream_store(T v, T* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <class Op, bool NT>
+__global__ __launch_bounds__(kThreads) void vec_group_kernel(VecGroup g) {
+  constexpr int kV4 = kVecUnit / 4 / kThreads;  // float4 per thread per unit
+  Op op;
+  for (uint64_t u = blockIdx.x; u < g.total_units; u += gridDim.x) {
+    const int r = find_request(g, u);
+    const VecDesc& d = g.d[r];
+    const uint64_t e0 = (u - d.unit_begin) * kVecUnit;
+    const uint64_t e1 = min(e0 + kVecUnit, d.n);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(d.a) | reinterpret_cast<uintptr_t>(d.b) |
+                           reinterpret_cast<uintptr_t>(d.c)) & 15) == 0;
+    if (aligned && e1 - e0 == kVecUnit) {
+      const f32x4* a4 = reinterpret_cast<const f32x4*>(d.a + e0);
+      const f32x4* b4 = reinterpret_cast<const f32x4*>(d.b + e0);
+      f32x4* c4 = reinterpret_cast<f32x4*>(d.c + e0);
+      f32x4 va[kV4], vb[kV4];
+#pragma unroll
+      for (int j = 0; j < kV4; ++j) {
+        va[j] = stream_load<f32x4, NT>(a4 + threadIdx.x + j * kThreads);
+        vb[j] = stream_load<f32x4, NT>(b4 + threadIdx.x + j * kThreads);
+      }
+#pragma unroll
+      for (int j = 0; j < kV4; ++j) {
+        f32x4 c;
+        c.x = op(va[j].x, vb[j].x);
+        c.y = op(va[j].y, vb[j].y);
+        c.z = op(va[j].z, vb[j].z);
+        c.w = op(va[j].w, vb[j].w);
+        stream_store<f32x4, NT>(c, c4 + threadIdx.x + j * kThreads);
+      }
+    } else {
+      for (uint64_t e = e0 + threadIdx.x; e < e1; e += kThreads) d.c[e] = op(d.a[e], d.b[e]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Black-Scholes
+//
+// Standard normal distribution function from the polynomial approximation of
+// Abramowitz and Stegun, Handbook of Mathematical Functions, formula 26.2.17
+// (absolute error below 7.5e-8):
+//   N(x) = 1 - phi(x) (b1 t + b2 t^2 + b3 t^3 + b4 t^4 + b5 t^5),  t = 1/(1 + p x),  x >= 0
+// and N(x) = 1 - N(-x) for x < 0.  The pricing formula itself is the
+// Black-Scholes (1973) one of the reference:
+//   d1 = (ln(S/K) + (r + sigma^2/2) T) / (sigma sqrt T),  d2 = d1 - sigma sqrt T
+//   call = S N(d1) - K e^{-rT} N(d2),  put = K e^{-rT} (1 - N(d2)) - S (1 - N(d1))
+
+__device__ __forceinline__ float norm_cdf_as(float x) {
+  constexpr float p = 0.2316419f;
+  constexpr float b1 = 0.319381530f, b2 = -0.356563782f, b3 = 1.781477937f, b4 = -1.821255978f,
+                  b5 = 1.330274429f;
+  constexpr float inv_sqrt_2pi = 0.39894228040143267794f;
+  const float ax = fabsf(x);
+  const float t = __frcp_rn(fmaf(p, ax, 1.0f));
+  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, b5, b4), b3), b2), b1);
+  const float phi = inv_sqrt_2pi * __expf(-0.5f * ax * ax);
+  const float upper = phi * poly;          // 1 - N(|x|)
+  return x >= 0.0f ? 1.0f - upper : upper;
+}
+
+__device__ __forceinline__ void bs_price(float S, float K, float T, float r, float v, float half_v2,
+                                         float& call, float& put) {
+  const float rs = __frsqrt_rn(T);
+  const float sqrt_t = T * rs;
+  const float vs = v * sqrt_t;
+  const float d1 = (__logf(__fdividef(S, K)) + (r + half_v2) * T) * __fdividef(rs, v);
+  const float d2 = d1 - vs;
+  const float kd = K * __expf(-r * T);
+  const float n1 = norm_cdf_as(d1);
+  const float n2 = norm_cdf_as(d2);
+  call = S * n1 - kd * n2;
+  put = kd * (1.0f - n2) - S * (1.0f - n1);
+}
+
+template <bool NT>
+__global__ __launch_bounds__(kThreads) void bs_group_kernel(BsGroup g) {
+  constexpr int kV4 = kBsUnit / 4 / kThreads;
+  const float r = g.rate, v = g.volatility, half_v2 = 0.5f * g.volatility * g.volatility;
+  for (uint64_t u = blockIdx.x; u < g.total_units; u += gridDim.x) {
+    const int q = find_request(g, u);
+    const BsDesc& d = g.d[q];
+    const uint64_t e0 = (u - d.unit_begin) * kBsUnit;
+    const uint64_t e1 = min(e0 + kBsUnit, d.n);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(d.S) | reinterpret_cast<uintptr_t>(d.K) |
+                           reinterpret_cast<uintptr_t>(d.T) | reinterpret_cast<uintptr_t>(d.call) |
+                           reinterpret_cast<uintptr_t>(d.put)) & 15) == 0;
+    if (aligned && e1 - e0 == kBsUnit) {
+      const f32x4* S4 = reinterpret_cast<const f32x4*>(d.S + e0);
+      const f32x4* K4 = reinterpret_cast<const f32x4*>(d.K + e0);
+      const f32x4* T4 = reinterpret_cast<const f32x4*>(d.T + e0);
+      f32x4* C4 = reinterpret_cast<f32x4*>(d.call + e0);
+      f32x4* P4 = reinterpret_cast<f32x4*>(d.put + e0);
+      f32x4 s[kV4], k[kV4], t[kV4];
+#pragma unroll
+      for (int j = 0; j < kV4; ++j) {
+        s[j] = stream_load<f32x4, NT>(S4 + threadIdx.x + j * kThreads);
+        k[j] = stream_load<f32x4, NT>(K4 + threadIdx.x + j * kThreads);
+        t[j] = stream_load<f32x4, NT>(T4 + threadIdx.x + j * kThreads);
+      }
+#pragma unroll
+      for (int j = 0; j < kV4; ++j) {
+        float c0, c1, c2, c3, p0, p1, p2, p3;
+        bs_price(s[j].x, k[j].x, t[j].x, r, v, half_v2, c0, p0);
+        bs_price(s[j].y, k[j].y, t[j].y, r, v, half_v2, c1, p1);
+        bs_price(s[j].z, k[j].z, t[j].z, r, v, half_v2, c2, p2);
+        bs_price(s[j].w, k[j].w, t[j].w, r, v, half_v2, c3, p3);
+        const f32x4 c = {c0, c1, c2, c3};
+        const f32x4 p = {p0, p1, p2, p3};
+        stream_store<f32x4, NT>(c, C4 + threadIdx.x + j * kThreads);
+        stream_store<f32x4, NT>(p, P4 + threadIdx.x + j * kThreads);
+      }
+    } else {
+      for (uint64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+        float c, p;
+        bs_price(d.S[e], d.K[e], d.T[e], r, v, half_v2, c, p);
+        d.call[e] = c;
+        d.put[e] = p;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void finalize_vec_group(VecGroup& g) {
+  uint64_t u = 0;
+  for (uint32_t i = 0; i < g.count; ++i) {
+    g.d[i].unit_begin = u;
+    u += (g.d[i].n + kVecUnit - 1) / kVecUnit;
+  }
+  g.total_units = u;
+}
+
+void finalize_bs_group(BsGroup& g) {
+  uint64_t u = 0;
+  for (uint32_t i = 0; i < g.count; ++i) {
+    g.d[i].unit_begin = u;
+    u += (g.d[i].n + kBsUnit - 1) / kBsUnit;
+  }
+  g.total_units = u;
+}
+
+// Streaming launch shape: persistent grid of kStreamGrid workgroups with
+// non-temporal memory operations; GVM_STREAM_GRID / GVM_STREAM_NT override
+// them for tuning (read once per process).
+int stream_grid(int grid_cap) {
+  static const int env = [] {
+    const char* e = getenv("GVM_STREAM_GRID");
+    return e ? atoi(e) : 0;
+  }();
+  if (grid_cap > 0) return grid_cap;
+  return env > 0 ? env : kStreamGrid;
+}
+
+bool stream_nt() {
+  static const bool nt = [] {
+    const char* e = getenv("GVM_STREAM_NT");
+    return e ? atoi(e) != 0 : kStreamNonTemporal;
+  }();
+  return nt;
+}
+
+template <class Op>
+hipError_t launch_vec(const VecGroup& g, hipStream_t s, int grid_cap) {
+  int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap))));
+  if (grid <= 0) return hipSuccess;
+  if (stream_nt())
+    hipLaunchKernelGGL((vec_group_kernel<Op, true>), dim3(grid), dim3(kThreads), 0, s, g);
+  else
+    hipLaunchKernelGGL((vec_group_kernel<Op, false>), dim3(grid), dim3(kThreads), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap) { return launch_vec<AddOp>(g, s, grid_cap); }
+
+hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap) { return launch_vec<MulOp>(g, s, grid_cap); }
+
+hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap) {
+  int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap))));
+  if (grid <= 0) return hipSuccess;
+  if (stream_nt())
+    hipLaunchKernelGGL(bs_group_kernel<true>, dim3(grid), dim3(kThreads), 0, s, g);
+  else
+    hipLaunchKernelGGL(bs_group_kernel<false>, dim3(grid), dim3(kThreads), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace gvm

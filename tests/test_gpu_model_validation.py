@@ -28,9 +28,11 @@ from paper_1511_07658_amd import spmd
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("vecadd", G.GVM_K_VECADD, 1 << 22), ("sgemm", G.GVM_K_SGEMM, 1024)]
+# vecadd 4M, VecMul of Table 3 (16M floats; its 15 iterations are the
+# repeated batches), SGEMM 1024
+CASES = [("vecadd", G.GVM_K_VECADD, 1 << 22, 5), ("vecmul", G.GVM_K_VECMUL, 1 << 24, 15),
+         ("sgemm", G.GVM_K_SGEMM, 1024, 5)]
 NS_LIST = [1, 2, 4, 8]
-REPS = 5
 
 
 def _run(ns, kernel_id, n, nranks, reps):
@@ -63,16 +65,16 @@ def _run(ns, kernel_id, n, nranks, reps):
 
 def test_execution_model_on_mi355x(ns_name):
     rows = []
-    for name, kid, n in CASES:
+    for name, kid, n, reps in CASES:
         for policy, pname in ((G.GVM_POLICY_PS1, "PS1"), (G.GVM_POLICY_PS2, "PS2")):
             ns = f"{ns_name}.{name}.{pname}"
-            cfg = G.gvm_config_default(nranks=8, shm_bytes_per_rank=64 << 20, hbm_budget_bytes=2 << 30,
+            cfg = G.gvm_config_default(nranks=8, shm_bytes_per_rank=(3 << 26) + (1 << 20), hbm_budget_bytes=4 << 30,
                                        policy=policy, batch_timing=1, batch_window_us=10_000_000, name=ns)
             G.check(G.gvm_init(cfg), "gvm_init")
             try:
                 # profile one rank: T_in, T_out from the timed copies, T_comp from the kernel events
                 G.gvm_stats_reset()
-                st = _run(ns, kid, n, 1, REPS)
+                st = _run(ns, kid, n, 1, reps)
                 tm = st["timing"]
                 t_in = tm["h2d"]["ms"] / tm["h2d"]["count"] * 1e-3
                 t_out = tm["d2h"]["ms"] / tm["d2h"]["count"] * 1e-3
@@ -80,9 +82,9 @@ def test_execution_model_on_mi355x(ns_name):
                 t_comp = ks["device_ms"] / ks["launches"] * 1e-3
                 for N in NS_LIST:
                     G.gvm_stats_reset()
-                    st = _run(ns, kid, n, N, REPS)
+                    st = _run(ns, kid, n, N, reps)
                     spans = st["timing"]["batch_device_us"]
-                    assert len(spans) == REPS, (N, spans)
+                    assert len(spans) == reps, (N, spans)
                     meas = statistics.median(spans) * 1e-6
                     closed = model.modelled_total(pname, N, t_in, t_comp, t_out)
                     des_paper = des.simulate(pname, N, t_in, t_comp, t_out, "paper")

@@ -147,6 +147,36 @@ def test_batch_barrier_holds_until_all_ranks_submit(ns_name):
         G.gvm_detach(1)
 
 
+def test_batch_timing_enqueues_whole_batches(ns_name):
+    # PS-2 with copies starts each rank's chain as its input lands; with
+    # batch_timing a batch goes to the device as one launch (one span)
+    reps, nranks = 3, 4
+    with Manager(ns_name, nranks=nranks, policy=G.GVM_POLICY_PS2, batch_timing=1, batch_window_us=10_000_000):
+        G.gvm_stats_reset()
+        bar = threading.Barrier(nranks)
+        errs = []
+
+        def rank(r):
+            assert G.gvm_attach_ns(ns_name, r) == 0
+            bar.wait()
+            for i in range(reps):
+                inp = np.full(2 * 4096, float(r * 10 + i), np.float32)
+                out = np.zeros(4096, np.float32)
+                t = G.gvm_submit(r, G.GVM_K_VECADD, inp, out, 4096)
+                if t < 0 or G.gvm_wait(r, t, 5_000_000_000) != 0 or not np.all(out == float(r * 10 + i)):
+                    errs.append((r, i, G.gvm_last_error()))
+                bar.wait()
+            assert G.gvm_detach(r) == 0
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(nranks)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+        st = G.gvm_stats_json()
+        assert st["requests_done"] == reps * nranks
+        assert st["batches"] == reps, st["batches"]
+
+
 def test_invalid_requests(ns_name):
     with Manager(ns_name, nranks=1, shm_bytes_per_rank=1 << 20):
         x = np.zeros(16, np.float32)
