@@ -37,6 +37,14 @@ from paper_1511_07658_amd import workloads as wl  # noqa: E402
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBPS = 8000.0
+# EP-like kernel: ALU issue bound.  The compiled unit loop issues, per
+# Philox block (two pairs, both accepted), 109 integer multiplies and 6
+# binary64 reciprocal / square-root estimates (quarter rate: 16 cycles per
+# wave64 instruction) and about 500 other VALU instructions (4 cycles):
+# 3840 SIMD cycles per 128 pairs = 30 cycles per pair; 256 CUs x 4 SIMDs x
+# 2.4 GHz / 30 = 81.9 Gpairs/s.
+EP_SIMD_CYCLES_PER_PAIR = 30.0
+PEAK_EP_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
@@ -75,6 +83,8 @@ WORKLOADS = {
     "bs16": "16 ranks via GVM, FP32 Black-Scholes 4M options each, one fused launch, inputs resident in HBM",
     "mixed32": "32 ranks via GVM with uneven sizes: 16 vector adds n=floor(2^U[16,24]) and 16 SGEMMs "
                "n in {256..2048 step 64}, tuned tiles, one grouped launch per kernel per step, inputs resident in HBM",
+    "ep8": "8 ranks via GVM, EP-like Gaussian-pair tally of 2^24 pairs each (the size of the paper's EP(M24)), "
+           "one grouped launch plus a per-request reduction, keys and results resident in HBM",
 }
 
 
@@ -86,6 +96,8 @@ def rank_specs(workload):
         return [(G.GVM_K_VECADD, 1 << 20, 0)] * 4
     if workload == "bs16":
         return [(G.GVM_K_BLACKSCHOLES, 4 << 20, 2)] * 16
+    if workload == "ep8":
+        return [(G.GVM_K_EP, 1 << 24, 4)] * 8
     if workload == "mixed32":
         return ([(G.GVM_K_VECADD, n, 3) for n in wl.uneven_vecadd_sizes(3, 16)] +
                 [(G.GVM_K_SGEMM, n, 3) for n in wl.uneven_sgemm_sizes(3, 16)])
@@ -102,6 +114,8 @@ def work_of(kernel_id, n):
         return 2.0 * n ** 3, 12.0 * n * n
     if kernel_id == G.GVM_K_BLACKSCHOLES:
         return 0.0, 20.0 * n
+    if kernel_id == G.GVM_K_EP:
+        return 0.0, 112.0   # the work is its n pairs (ALU), not bytes
     return float(n), 12.0 * n
 
 
@@ -182,6 +196,7 @@ def plain_rank(kernel_id, n, cfg_idx, rank, barrier):
 def cpu_baseline(kernel_id, nranks, n, cfg_idx, budget_s=10.0):
     """The oracle as it stands, on this host's cores, over a bounded sample of
     the same workload (whole passes over the ranks' requests, ~budget_s)."""
+    from oracle import ep as oe
     from oracle import kernels as ok
 
     try:
@@ -190,6 +205,17 @@ def cpu_baseline(kernel_id, nranks, n, cfg_idx, budget_s=10.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = 1
+    if kernel_id == G.GVM_K_EP:
+        sample = min(n, 1 << 20)   # a bounded slice of each rank's pair stream
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            oe.ep_reference(wl.ep_key(cfg_idx, done % nranks), sample)
+            done += 1
+        el = time.perf_counter() - t0
+        return {"value": round(done * sample / el / 1e9, 6), "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
+                "sample": f"{done} slices of {sample} pairs through oracle.ep.ep_reference in {el:.1f} s "
+                          f"(the first {sample} pairs of the ranks' keys, cycled)"}
     inputs = []
     for r in range(min(nranks, 4)):
         if kernel_id == G.GVM_K_SGEMM:
@@ -270,7 +296,9 @@ def main(argv=None):
         turn = (max(r["t1"] for r in res) - min(r["t0"] for r in res)) * 1e-9
         stages = np.array([r["stages"] for r in res])
         plain = {"turnaround_s": round(turn, 6),
-                 "value": round((flop_total if main_kernel == G.GVM_K_SGEMM else bytes_total) / turn / 1e9, 3),
+                 "value": round((flop_total if main_kernel == G.GVM_K_SGEMM else
+                                 sum(n for _, n, _ in specs) if main_kernel == G.GVM_K_EP else bytes_total)
+                                / turn / 1e9, 3),
                  "mean_stage_s": dict(zip(["init", "alloc", "copy_in", "kernel", "copy_out", "free"],
                                           [round(float(v), 6) for v in stages.mean(axis=0)])),
                  "digests": [r["digest"] for r in res]}
@@ -321,7 +349,7 @@ def main(argv=None):
         G.gvm_shutdown()
     elapsed = (max(r["t1"] for r in rr) - min(r["t0"] for r in rr)) * 1e-9
     e2e = (max(r["e1"] for r in rr) - min(r["e0"] for r in rr)) * 1e-9
-    knames = {0: "mixed_graph", 1: "vecadd", 2: "blackscholes", 3: "sgemm", 4: "vecmul"}
+    knames = {0: "mixed_graph", 1: "vecadd", 2: "blackscholes", 3: "sgemm", 4: "vecmul", 5: "ep"}
     kname = "mixed_graph" if (mixed and a.graphs and "mixed_graph" in stats["kernels"]) else knames[main_kernel]
     ks = stats["kernels"][kname]
     launches = max(ks["launches"], 1)
@@ -339,6 +367,14 @@ def main(argv=None):
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": measured_traffic(a.workload)}
         e2e_value = a.e2e_steps * main_flop / e2e / 1e9
+    elif main_kernel == G.GVM_K_EP:
+        pairs = sum(n for k, n in main_specs)
+        value = a.steps * pairs / elapsed / 1e9
+        unit = "Gpairs/s"
+        achieved = ks["requests"] / len(main_specs) * pairs / dev_s / 1e9
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_EP_GPAIRS, 1), "unit": "Gpairs/s",
+                "frac": round(achieved / PEAK_EP_GPAIRS, 4), "traffic": None}
+        e2e_value = a.e2e_steps * pairs / e2e / 1e9
     else:
         value = a.steps * main_bytes / elapsed / 1e9
         unit = "GB/s"

@@ -65,12 +65,23 @@ enum gvm_status {
  *                       (rate r, volatility sigma from gvm_config)
  *   GVM_K_SGEMM         C = A B, n x n row-major     in [A(n*n) | B(n*n)]        out [C(n*n)]
  *   GVM_K_VECMUL        c = a * b (element-wise)     in [a(n) | b(n)]            out [c(n)]
+ * and the compute-intensive EP-like kernel (the paper's NPB EP, Table 3 and
+ * Section 6), n = number of pairs (1 .. 2^40), 64-bit words:
+ *   GVM_K_EP            Gaussian-pair tally          in [k0 | k1] (uint64 key)
+ *                       out [sx | sy (binary64) | q[0..9] (uint64)]
+ *     pair j of the request takes the words 2j, 2j+1 of the Philox4x64-10
+ *     stream of key (k0, k1) (block b = counter (b, 0, 0, 0) gives words
+ *     4b .. 4b+3); u = (w >> 11) 2^-53, x = 2u - 1, y likewise; accepted when
+ *     0 < t = x*x + y*y <= 1 (binary64, no fused multiply-add); then
+ *     X = x sqrt(-2 ln t / t), Y = y sqrt(-2 ln t / t); sx, sy = sums of X, Y;
+ *     q[l] = number of accepted pairs with l <= max(|X|, |Y|) < l + 1.
  */
 enum gvm_kernel {
   GVM_K_VECADD = 1,
   GVM_K_BLACKSCHOLES = 2,
   GVM_K_SGEMM = 3,
-  GVM_K_VECMUL = 4
+  GVM_K_VECMUL = 4,
+  GVM_K_EP = 5
 };
 
 /* ------------------------------------------------------------ manager modes */

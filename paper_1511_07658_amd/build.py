@@ -40,6 +40,7 @@ HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__", f
 LIB_SOURCES = [
     ("stream_kernels.hip", "hip"),
     ("sgemm.hip", "hip"),
+    ("ep_kernels.hip", "hip"),
     ("device_hip.cpp", "hip"),
     ("plain.cpp", "hip"),
     ("device_loopback.cpp", "host"),

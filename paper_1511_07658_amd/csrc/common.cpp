@@ -55,6 +55,12 @@ bool request_layout(int kernel_id, uint64_t n, Layout* out) {
       out->in_bytes = 2 * n * n * f;
       out->out_bytes = n * n * f;
       return true;
+    case GVM_K_EP:
+      if (n > (1ull << 40)) return false;
+      out->in_bytes = 2 * sizeof(uint64_t);
+      out->out_bytes = kEpWords * sizeof(uint64_t);
+      out->scratch_bytes = ((n + kEpUnit - 1) / kEpUnit) * kEpWords * sizeof(uint64_t);  // one partial per unit
+      return true;
     default:
       return false;
   }

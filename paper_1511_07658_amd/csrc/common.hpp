@@ -25,12 +25,24 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 struct Layout {
   uint64_t in_bytes = 0;
   uint64_t out_bytes = 0;
+  uint64_t scratch_bytes = 0;  // device-only working space after the output (never copied)
 };
+
+constexpr int kNumKernelIds = 6;  // kernel ids 1..5; index 0 collects mixed graph launches
+
+// EP-like kernel: pairs per work unit, and the 64-bit words of one result
+// record (sx, sy, q[0..9]), the request's output and each unit's partial.
+constexpr uint64_t kEpUnit = 1ull << 15;
+constexpr uint64_t kEpWords = 12;
 // false if the kernel id is unknown, n == 0 or the size overflows.
 bool request_layout(int kernel_id, uint64_t n, Layout* out);
-// Device slot bytes for a request: input, then output at the next aligned offset.
-inline uint64_t slot_bytes(const Layout& l) { return align_up(l.in_bytes, kAlign) + align_up(l.out_bytes, kAlign); }
+// Device slot of a request: input, then output at the next aligned offset,
+// then the device-only scratch at the next aligned offset.
+inline uint64_t slot_bytes(const Layout& l) {
+  return align_up(l.in_bytes, kAlign) + align_up(l.out_bytes, kAlign) + align_up(l.scratch_bytes, kAlign);
+}
 inline uint64_t slot_out_offset(const Layout& l) { return align_up(l.in_bytes, kAlign); }
+inline uint64_t slot_scratch_offset(const Layout& l) { return align_up(l.in_bytes, kAlign) + align_up(l.out_bytes, kAlign); }
 
 // Futex on a 32-bit word that lives in shared memory (process-shared).
 // Returns 0 when woken or the value differed, GVM_ETIMEDOUT on timeout.
@@ -48,6 +60,7 @@ inline const char* kernel_name(int k) {
     case GVM_K_BLACKSCHOLES: return "blackscholes";
     case GVM_K_SGEMM: return "sgemm";
     case GVM_K_VECMUL: return "vecmul";
+    case GVM_K_EP: return "ep";
     default: return "unknown";
   }
 }

@@ -48,7 +48,8 @@ struct KernelStats {
 };
 
 // Algorithmic work of one request (the per-unit figures: 12 B per vector
-// element, 20 B per option, 2 n^3 FLOP and 12 n^2 compulsory bytes per GEMM).
+// element, 20 B per option, 2 n^3 FLOP and 12 n^2 compulsory bytes per GEMM,
+// the 112 input and output bytes of an EP request, whose work is its n pairs).
 void request_work(int kernel_id, uint64_t n, double* flop, double* bytes);
 
 class Device {
@@ -69,7 +70,7 @@ class Device {
   virtual void finish(Job* j) = 0;
   virtual void drain() = 0;
   virtual void close() = 0;
-  virtual const KernelStats* kernel_stats() const = 0;  // indexed by kernel id (0..4)
+  virtual const KernelStats* kernel_stats() const = 0;  // indexed by kernel id (kNumKernelIds entries)
   virtual void reset_stats() = 0;
   virtual std::string describe() const = 0;
   // Batch device phases and copy timings (batch_timing), as a JSON object.

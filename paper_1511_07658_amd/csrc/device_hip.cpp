@@ -1,10 +1,12 @@
 // HIP device of the manager: the single context of device 0, per-rank
-// streams, compute streams, one device arena, per-rank pinned staging, and
-// the three enqueue policies (PS-1, PS-2 of Section 4.2.1, and the grouped
-// persistent launch).
+// kernel streams, two compute streams for grouped launches, one copy stream
+// per direction (FIFO, in the role of the copy engines of the execution
+// model), one device arena, per-rank pinned staging, and the three enqueue
+// policies (PS-1, PS-2 of Section 4.2.1, and the grouped persistent launch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -81,6 +83,8 @@ class HipDevice final : public Device {
       HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
       compute_streams_.push_back(s);
     }
+    HIPCHK(hipStreamCreateWithFlags(&h2d_, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&d2h_, hipStreamNonBlocking));
     HIPCHK(hipMalloc(reinterpret_cast<void**>(&arena_), cfg.hbm_budget_bytes));
     staging_.assign(cfg.nranks, nullptr);
     staging_bytes_ = cfg.staging_bytes ? cfg.staging_bytes : cfg.shm_bytes_per_rank;
@@ -140,11 +144,23 @@ class HipDevice final : public Device {
     std::vector<hipStream_t> span_streams;
     const bool span = cfg_.batch_timing && !cfg_.use_graphs;
     if (span) {
+      // only the streams that carry work of this batch (each extra stream
+      // costs a cross-queue wait at both ends of the span)
       hipStream_t c0 = compute_streams_[0];
-      span_streams = {compute_streams_[1]};
+      bool any_in = false, any_out = false;
       for (Job* j : jobs) {
-        hipStream_t s = rank_stream(j->rank);
-        if (std::find(span_streams.begin(), span_streams.end(), s) == span_streams.end()) span_streams.push_back(s);
+        any_in |= j->copy_in;
+        any_out |= j->copy_out;
+      }
+      if (any_in) span_streams.push_back(h2d_);
+      if (any_out) span_streams.push_back(d2h_);
+      if (policy == GVM_POLICY_PS1 || policy == GVM_POLICY_PS2) {
+        for (Job* j : jobs) {
+          hipStream_t s = rank_stream(j->rank);
+          if (std::find(span_streams.begin(), span_streams.end(), s) == span_streams.end()) span_streams.push_back(s);
+        }
+      } else if (grouped_launches(jobs) > 1) {
+        span_streams.push_back(compute_streams_[1]);
       }
       b->span0 = timed_event();
       b->span1 = timed_event();
@@ -155,25 +171,54 @@ class HipDevice final : public Device {
     }
     if (rc != GVM_OK) {
     } else if (policy == GVM_POLICY_PS2) {
+      // Per rank: copy-in (host-to-device FIFO) -> kernel (rank stream) ->
+      // copy-out (device-to-host FIFO).  The FIFOs play the paper's copy
+      // engines: rank i+1's input streams in while rank i computes and
+      // rank i-1's result streams out.
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         Job* j = jobs[i];
         hipStream_t s = rank_stream(j->rank);
         std::vector<Job*> one{j};
-        rc = enqueue_in(j, s);
+        if (j->copy_in) {
+          rc = enqueue_in(j, h2d_);
+          if (rc == GVM_OK) rc = after(s, h2d_, b);
+        }
         if (rc == GVM_OK) rc = enqueue_kernels(one, {s}, b, true, nullptr);
-        if (rc == GVM_OK) rc = enqueue_out(j, s);
-        if (rc == GVM_OK) rc = record_done(b, i, s);
+        if (rc == GVM_OK && j->copy_out) {
+          rc = after(d2h_, s, b);
+          if (rc == GVM_OK) rc = enqueue_out(j, d2h_);
+          if (rc == GVM_OK) rc = record_done(b, i, d2h_);
+        } else if (rc == GVM_OK) {
+          rc = record_done(b, i, s);
+        }
       }
     } else if (policy == GVM_POLICY_PS1) {
-      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) rc = enqueue_in(jobs[i], rank_stream(jobs[i]->rank));
+      // Phases: every copy-in, then every kernel (concurrently, one per rank
+      // stream), then every copy-out.
+      std::vector<hipStream_t> ks;
+      for (Job* j : jobs)
+        if (std::find(ks.begin(), ks.end(), rank_stream(j->rank)) == ks.end()) ks.push_back(rank_stream(j->rank));
+      bool any_in = false, any_out = false;
+      for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
+        any_in |= jobs[i]->copy_in;
+        any_out |= jobs[i]->copy_out;
+        rc = enqueue_in(jobs[i], h2d_);
+      }
+      if (any_in)
+        for (size_t k = 0; k < ks.size() && rc == GVM_OK; ++k) rc = after(ks[k], h2d_, b);
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         std::vector<Job*> one{jobs[i]};
         rc = enqueue_kernels(one, {rank_stream(jobs[i]->rank)}, b, true, nullptr);
       }
+      if (any_out)
+        for (size_t k = 0; k < ks.size() && rc == GVM_OK; ++k) rc = after(d2h_, ks[k], b);
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
-        hipStream_t s = rank_stream(jobs[i]->rank);
-        rc = enqueue_out(jobs[i], s);
-        if (rc == GVM_OK) rc = record_done(b, i, s);
+        if (jobs[i]->copy_out) {
+          rc = enqueue_out(jobs[i], d2h_);
+          if (rc == GVM_OK) rc = record_done(b, i, d2h_);
+        } else {
+          rc = record_done(b, i, rank_stream(jobs[i]->rank));
+        }
       }
     } else {
       rc = launch_grouped(b);
@@ -275,6 +320,9 @@ class HipDevice final : public Device {
     free_timed_.clear();
     for (hipStream_t s : rank_streams_) (void)hipStreamDestroy(s);
     for (hipStream_t s : compute_streams_) (void)hipStreamDestroy(s);
+    if (h2d_) (void)hipStreamDestroy(h2d_);
+    if (d2h_) (void)hipStreamDestroy(d2h_);
+    h2d_ = d2h_ = nullptr;
     rank_streams_.clear();
     compute_streams_.clear();
     if (arena_) (void)hipFree(arena_);
@@ -337,6 +385,28 @@ class HipDevice final : public Device {
       return nullptr;
     }
     return e;
+  }
+
+  // Number of grouped launches enqueue_kernels makes for `jobs` (one per
+  // kernel id and SGEMM tile configuration, per kMaxGroup requests).
+  static size_t grouped_launches(const std::vector<Job*>& jobs) {
+    std::map<std::pair<int, int>, size_t> groups;
+    for (const Job* j : jobs) {
+      const int k = static_cast<int>(j->req.kernel_id);
+      ++groups[{k, k == GVM_K_SGEMM ? gemm_config_for(j->req.n) : 0}];
+    }
+    size_t n = 0;
+    for (const auto& kv : groups) n += (kv.second + kMaxGroup - 1) / kMaxGroup;
+    return n;
+  }
+
+  // `waiter` continues only after everything enqueued so far on `producer`.
+  int after(hipStream_t waiter, hipStream_t producer, Batch* b) {
+    hipEvent_t e = sync_event(b);
+    if (!e) return GVM_EDEVICE;
+    HIPCHK(hipEventRecord(e, producer));
+    HIPCHK(hipStreamWaitEvent(waiter, e, 0));
+    return GVM_OK;
   }
 
   int record_done(Batch* b, size_t i, hipStream_t s) {
@@ -476,6 +546,18 @@ class HipDevice final : public Device {
           }
           finalize_gemm_group(g, cfgi);
           e = launch_sgemm_group(g, cfgi, s);
+        } else if (k == GVM_K_EP) {
+          EpGroup g{};
+          g.count = static_cast<uint32_t>(cnt);
+          for (size_t i = 0; i < cnt; ++i) {
+            Job* j = v[base + i];
+            g.d[i].key = reinterpret_cast<const uint64_t*>(j->slot);
+            g.d[i].out = reinterpret_cast<uint64_t*>(j->slot + slot_out_offset(j->lay));
+            g.d[i].partial = reinterpret_cast<uint64_t*>(j->slot + slot_scratch_offset(j->lay));
+            g.d[i].n = j->req.n;
+          }
+          finalize_ep_group(g);
+          e = launch_ep_group(g, s);
         } else {
           return fail(GVM_EINVAL, "unknown kernel id %d", k);
         }
@@ -490,9 +572,9 @@ class HipDevice final : public Device {
     return GVM_OK;
   }
 
-  // Grouped policy: copy-ins on the rank streams, one grouped launch per
-  // kernel id spread over the two compute streams, copy-outs on the rank
-  // streams.  With use_graphs the whole batch is captured once per batch
+  // Grouped policy: copy-ins on the host-to-device FIFO, one grouped launch
+  // per kernel id spread over the two compute streams, copy-outs on the
+  // device-to-host FIFO.  With use_graphs the whole batch is captured once per batch
   // template (ranks, kernels, sizes, copies, buffers) and replayed.
   int launch_grouped(Batch* b) {
     std::vector<Job*>& jobs = b->jobs;
@@ -556,27 +638,26 @@ class HipDevice final : public Device {
   int enqueue_grouped(Batch* b, bool capture) {
     std::vector<Job*>& jobs = b->jobs;
     hipStream_t c0 = compute_streams_[0], c1 = compute_streams_[1];
-    std::vector<hipStream_t> used;
-    for (Job* j : jobs) {
-      hipStream_t s = rank_stream(j->rank);
-      if ((j->copy_in || j->copy_out) && std::find(used.begin(), used.end(), s) == used.end()) used.push_back(s);
-    }
+    bool any_in = false;
+    for (Job* j : jobs) any_in |= j->copy_in;
     if (capture) {
       hipEvent_t fork = sync_event(b);
       if (!fork) return GVM_EDEVICE;
       HIPCHK(hipEventRecord(fork, c0));
-      for (hipStream_t s : used) HIPCHK(hipStreamWaitEvent(s, fork, 0));
+      HIPCHK(hipStreamWaitEvent(h2d_, fork, 0));
+      HIPCHK(hipStreamWaitEvent(d2h_, fork, 0));
       HIPCHK(hipStreamWaitEvent(c1, fork, 0));
     }
-    // copy-ins, then both compute streams wait for them
+    // copy-ins in rank order on the host-to-device FIFO, then both compute
+    // streams wait for them
     for (Job* j : jobs) {
-      const int rc0 = enqueue_in(j, rank_stream(j->rank));
+      const int rc0 = enqueue_in(j, h2d_);
       if (rc0 != GVM_OK) return rc0;
     }
-    for (hipStream_t s : used) {
+    if (any_in) {
       hipEvent_t ev = sync_event(b);
       if (!ev) return GVM_EDEVICE;
-      HIPCHK(hipEventRecord(ev, s));
+      HIPCHK(hipEventRecord(ev, h2d_));
       HIPCHK(hipStreamWaitEvent(c0, ev, 0));
       HIPCHK(hipStreamWaitEvent(c1, ev, 0));
     }
@@ -595,6 +676,9 @@ class HipDevice final : public Device {
       if (!k[c]) return GVM_EDEVICE;
       HIPCHK(hipEventRecord(k[c], c == 0 ? c0 : c1));
     }
+    // copy-outs in rank order on the device-to-host FIFO, each after the
+    // launch that computed it
+    int waited = -1;
     for (size_t i = 0; i < jobs.size(); ++i) {
       Job* j = jobs[i];
       hipEvent_t kev = k[stream_of[i]];
@@ -603,17 +687,19 @@ class HipDevice final : public Device {
         if (!capture) track(b, kev, stream_of[i] == 0 ? c0 : c1);
         continue;
       }
-      hipStream_t s = rank_stream(j->rank);
-      HIPCHK(hipStreamWaitEvent(s, kev, 0));
-      rc = enqueue_out(j, s);
+      if (waited != stream_of[i]) {
+        HIPCHK(hipStreamWaitEvent(d2h_, kev, 0));
+        waited = stream_of[i];
+      }
+      rc = enqueue_out(j, d2h_);
       if (rc != GVM_OK) return rc;
       if (!capture) {
-        rc = record_done(b, i, s);
+        rc = record_done(b, i, d2h_);
         if (rc != GVM_OK) return rc;
       }
     }
     if (capture) {  // join
-      for (hipStream_t s : used) {
+      for (hipStream_t s : {h2d_, d2h_}) {
         hipEvent_t ev = sync_event(b);
         if (!ev) return GVM_EDEVICE;
         HIPCHK(hipEventRecord(ev, s));
@@ -653,7 +739,7 @@ class HipDevice final : public Device {
     }
     for (auto& t : b->timed) {
       float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, t.e0, t.e1) == hipSuccess && t.kernel_id >= 0 && t.kernel_id < 5) {
+      if (hipEventElapsedTime(&ms, t.e0, t.e1) == hipSuccess && t.kernel_id >= 0 && t.kernel_id < kNumKernelIds) {
         // kernel id 0 collects graph launches of mixed batches
         KernelStats& ks = stats_[t.kernel_id];
         ks.launches += 1;
@@ -714,6 +800,12 @@ class HipDevice final : public Device {
       finalize_gemm_group(gg, c);
       HIPCHK(launch_sgemm_group(gg, c, s));
     }
+    EpGroup eg{};
+    eg.count = 1;
+    uint64_t* w = reinterpret_cast<uint64_t*>(arena_);
+    eg.d[0] = EpDesc{w, w + 16, w + 64, 64, 0, 0};  // key words are zero (memset above)
+    finalize_ep_group(eg);
+    HIPCHK(launch_ep_group(eg, s));
     HIPCHK(hipStreamSynchronize(s));
     return GVM_OK;
   }
@@ -724,6 +816,7 @@ class HipDevice final : public Device {
   bool closed_ = false;
   std::vector<hipStream_t> rank_streams_;
   std::vector<hipStream_t> compute_streams_;
+  hipStream_t h2d_ = nullptr, d2h_ = nullptr;  // copy FIFOs, one per direction
   size_t next_cs_ = 0;
   struct FifoEntry {
     Batch* b;
@@ -740,7 +833,7 @@ class HipDevice final : public Device {
   std::vector<hipEvent_t> free_sync_;
   std::vector<hipEvent_t> free_timed_;
   std::vector<Batch*> batches_;
-  KernelStats stats_[5];
+  KernelStats stats_[kNumKernelIds];
   struct GraphEntry {
     hipGraph_t graph;
     hipGraphExec_t exec;

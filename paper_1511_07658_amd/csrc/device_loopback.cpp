@@ -31,6 +31,10 @@ void request_work(int kernel_id, uint64_t n, double* flop, double* bytes) {
       *flop = 2.0 * dn * dn * dn;
       *bytes = 12.0 * dn * dn;
       return;
+    case GVM_K_EP:
+      *flop = 0.0;  // integer and transcendental work; counted in pairs by the caller
+      *bytes = 16.0 + 8.0 * kEpWords;
+      return;
     default:
       *flop = 0.0;
       *bytes = 0.0;
@@ -76,7 +80,7 @@ class LoopbackDevice final : public Device {
       memmove(j->slot + o, j->slot, keep);
       memset(j->slot + o + keep, 0, j->lay.out_bytes - keep);
       if (j->copy_out) timed_copy(1, j->pin + o, j->slot + o, j->lay.out_bytes);
-      KernelStats& ks = stats_[j->req.kernel_id < 5 ? j->req.kernel_id : 0];
+      KernelStats& ks = stats_[j->req.kernel_id < kNumKernelIds ? j->req.kernel_id : 0];
       ks.launches += 1;
       ks.requests += 1;
       double f, b;
@@ -147,7 +151,7 @@ class LoopbackDevice final : public Device {
   uint64_t arena_bytes_ = 0;
   std::vector<uint8_t*> staging_;
   uint64_t staging_bytes_ = 0;
-  KernelStats stats_[5];
+  KernelStats stats_[kNumKernelIds];
 };
 
 }  // namespace

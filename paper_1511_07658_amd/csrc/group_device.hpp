@@ -23,4 +23,12 @@ __device__ __forceinline__ int find_request(const G& g, uint64_t u) {
   return lo;
 }
 
+// Launch `kernel(g)` on `s` (nothing for an empty grid).
+template <class G>
+hipError_t launch_group(void (*kernel)(G), int grid, int block, hipStream_t s, const G& g) {
+  if (grid <= 0) return hipSuccess;
+  void* args[] = {const_cast<G*>(&g)};
+  return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block), args, 0, s);
+}
+
 }  // namespace gvm

@@ -64,6 +64,22 @@ struct GemmGroup {
   GemmDesc d[kMaxGroup];
 };
 
+struct EpDesc {
+  const uint64_t* key;   // (k0, k1)
+  uint64_t* out;         // sx, sy (binary64 bit patterns), q[0..9]
+  uint64_t* partial;     // one record of the same layout per work unit
+  uint64_t n;            // pairs
+  uint64_t unit_begin;
+  uint64_t units;
+};
+
+struct EpGroup {
+  uint32_t count;
+  uint32_t pad;
+  uint64_t total_units;
+  EpDesc d[kMaxGroup];
+};
+
 // SGEMM tile configurations available to the tuner.  A configuration is a
 // pure function of n (see gemm_config_for), so a request always runs with the
 // same tiles whatever it is grouped with.
@@ -71,6 +87,7 @@ struct GemmConfig {
   int id;
   int bm, bn, bk;   // macro tile of one workgroup
   int wm, wn;       // waves along M and N (wave tile = bm/wm x bn/wn)
+  bool late;        // next tile written to LDS after the k-step's MFMAs, not half-way
 };
 
 int gemm_config_count();
@@ -89,10 +106,14 @@ hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap = 
 hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap = 0);
 hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap = 0);
 hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap = 0);
+// EP-like tally: one launch over the work units of every request (partials),
+// then one workgroup per request sums its partials.
+hipError_t launch_ep_group(const EpGroup& g, hipStream_t s, int grid_cap = 0);
 
 // Fill the unit bookkeeping of a group (unit_begin, tiles, totals).
 void finalize_vec_group(VecGroup& g);
 void finalize_bs_group(BsGroup& g);
 void finalize_gemm_group(GemmGroup& g, int config_idx);
+void finalize_ep_group(EpGroup& g);
 
 }  // namespace gvm

@@ -282,8 +282,8 @@ void Manager::on_message(int r, const Request& m) {
     q.status = GVM_EINVAL;
   } else if (!(m.flags & GVM_F_OUT_RESIDENT) && (m.off_out > space || lay.out_bytes > space - m.off_out)) {
     q.status = GVM_EINVAL;
-  } else if (slot_bytes(lay) > align_up((cfg_.staging_bytes ? cfg_.staging_bytes : space) + 2 * kAlign, 4096)) {
-    q.status = GVM_ENOMEM;
+  } else if (slot_out_offset(lay) + lay.out_bytes > align_up((cfg_.staging_bytes ? cfg_.staging_bytes : space) + 2 * kAlign, 4096)) {
+    q.status = GVM_ENOMEM;  // the pinned staging mirrors the slot's input and output
   }
   rt.queue.push_back(q);
 }
@@ -311,7 +311,7 @@ void Manager::respond(int r, uint64_t ticket, uint32_t kernel_id, int status, co
   std::atomic_thread_fence(std::memory_order_seq_cst);
   s->resp_bell.fetch_add(1, std::memory_order_seq_cst);
   if (s->rank_sleeping.load(std::memory_order_seq_cst)) futex_wake_all(&s->resp_bell);
-  if (kernel_id >= GVM_K_VECADD && kernel_id <= GVM_K_VECMUL) {
+  if (kernel_id >= GVM_K_VECADD && kernel_id <= GVM_K_EP) {
     std::lock_guard<std::mutex> lk(stats_mu_);
     if (status == GVM_OK) {
       ++n_done_;
@@ -368,36 +368,46 @@ void Manager::check_liveness() {
 bool Manager::complete_jobs() {
   bool any = false;
   dev_->begin_poll();
+  // 1. device work that finished: start the result's copy-out
+  std::vector<Job*> device_done;
+  for (uint32_t r = 0; r < cfg_.nranks; ++r) {
+    Job* j = ranks_[r].running;
+    if (!j || j->stage != kStageDevice) continue;
+    if (dev_->query(j) == 0) continue;
+    device_done.push_back(j);
+    any = true;
+    if (j->status == GVM_OK && j->copy_out)
+      copy_.submit(j->shm + j->req.off_out, j->pin + slot_out_offset(j->lay), j->lay.out_bytes, &j->copies);
+    j->stage = kStageCopyOut;
+  }
+  // 2. answer every rank whose result is in place, before any bookkeeping
+  std::vector<int> answered;
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
     RankRt& rt = ranks_[r];
     Job* j = rt.running;
-    if (!j) continue;
-    if (j->stage == kStageDevice) {
-      if (dev_->query(j) == 0) continue;
-      dev_->finish(j);
-      any = true;
-      if (j->status == GVM_OK && j->copy_out) {
-        copy_.submit(j->shm + j->req.off_out, j->pin + slot_out_offset(j->lay), j->lay.out_bytes, &j->copies);
-        j->stage = kStageCopyOut;
-      } else {
-        j->stage = kStageCopyOut;  // nothing to copy
-      }
-    }
-    if (j->stage != kStageCopyOut || j->copies.load(std::memory_order_acquire) != 0) continue;
+    if (!j || j->stage != kStageCopyOut || j->copies.load(std::memory_order_acquire) != 0) continue;
+    if (rt.attached) respond(static_cast<int>(r), j->req.ticket, j->req.kernel_id, j->status, j, j->req.t_submit_ns);
+    answered.push_back(static_cast<int>(r));
+  }
+  // 3. release the device bookkeeping (event timings of a retired batch)
+  for (Job* j : device_done) dev_->finish(j);
+  // 4. retire the answered jobs
+  for (int r : answered) {
+    RankRt& rt = ranks_[r];
+    Job* j = rt.running;
     const bool alive = rt.attached;
-    if (alive) respond(static_cast<int>(r), j->req.ticket, j->req.kernel_id, j->status, j, j->req.t_submit_ns);
     if (j->status != GVM_OK) rt.res_valid = false;
     rt.running = nullptr;
     rt.last_use_ns = now_ns();
     delete j;
     --inflight_;
     any = true;
-    if (!alive || (rt.attached && !pid_alive(rt.pid) && rt.pid != getpid())) reap_rank(static_cast<int>(r));
+    if (!alive || (rt.attached && !pid_alive(rt.pid) && rt.pid != getpid())) reap_rank(r);
   }
   if (any) {
     std::lock_guard<std::mutex> lk(stats_mu_);
     const KernelStats* ks = dev_->kernel_stats();
-    for (int k = 0; k < 5; ++k) kstats_[k] = ks[k];
+    for (int k = 0; k < kNumKernelIds; ++k) kstats_[k] = ks[k];
     peak_bytes_ = std::max(peak_bytes_, arena_.peak());
     if (cfg_.batch_timing) timing_json_ = dev_->timing_json();
   }
@@ -624,7 +634,7 @@ int Manager::stats_json(std::string* out) {
   s += buf;
   s += ",\"kernels\":{";
   bool first = true;
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < kNumKernelIds; ++k) {
     const KernelStats& ks = kstats_[k];
     if (k == 0 && ks.launches == 0) continue;
     std::vector<double> all = lat_us_[k];

@@ -107,9 +107,9 @@ class Manager {
   // statistics (guarded by stats_mu_)
   std::mutex stats_mu_;
   uint64_t n_done_ = 0, n_err_ = 0, n_batches_ = 0;
-  std::vector<double> lat_us_[5];      // submit -> result posted, per kernel id
+  std::vector<double> lat_us_[kNumKernelIds];      // submit -> result posted, per kernel id
   std::vector<double> wait_us_;        // submit -> admitted
-  KernelStats kstats_[5];
+  KernelStats kstats_[kNumKernelIds];
   uint64_t peak_bytes_ = 0;
   std::string timing_json_ = "{}";
 };

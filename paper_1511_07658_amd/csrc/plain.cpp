@@ -62,6 +62,13 @@ extern "C" int gvm_plain_run(int kernel_id, const void* in, void* out, uint64_t 
     g.d[0] = gvm::BsDesc{fin, fin + n, fin + 2 * n, fout, fout + n, n, 0};
     gvm::finalize_bs_group(g);
     e = gvm::launch_bs_group(g, nullptr);
+  } else if (kernel_id == GVM_K_EP) {
+    gvm::EpGroup g{};
+    g.count = 1;
+    g.d[0] = gvm::EpDesc{reinterpret_cast<const uint64_t*>(dev), reinterpret_cast<uint64_t*>(fout),
+                         reinterpret_cast<uint64_t*>(dev + gvm::slot_scratch_offset(lay)), n, 0, 0};
+    gvm::finalize_ep_group(g);
+    e = gvm::launch_ep_group(g, nullptr);
   } else {
     gvm::GemmGroup g{};
     g.count = 1;

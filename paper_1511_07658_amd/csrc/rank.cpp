@@ -129,13 +129,15 @@ void drain(RankHandle& h) {
 }
 
 // Block until `done()` holds, a response arrives for it, or the deadline.
-// Poll budget before a futex sleep: 200 us when every rank and the manager
-// can have a core of their own, 10 us when the host is oversubscribed (a
-// spinning rank would then steal the core of the one it waits for).
+// Poll budget before a futex sleep: 1 ms when every rank and the manager can
+// have a core of their own (longer than a typical synchronous step, so that
+// the first rank to submit does not fall asleep and then wake last, a
+// futex wake-up later), 10 us when the host is oversubscribed (a spinning
+// rank would then steal the core of the one it waits for).
 uint64_t rank_spin_ns(const CtlHeader* hdr) {
-  if (getenv("GVM_RANK_SPIN_US")) return spin_env_ns("GVM_RANK_SPIN_US", 200);
+  if (getenv("GVM_RANK_SPIN_US")) return spin_env_ns("GVM_RANK_SPIN_US", 1000);
   static const long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
-  return (static_cast<long>(hdr->nranks) + 2 > ncpu) ? 10000ull : 200000ull;
+  return (static_cast<long>(hdr->nranks) + 2 > ncpu) ? 10000ull : 1000000ull;
 }
 
 template <class Pred>
@@ -153,7 +155,7 @@ int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
     }
     const uint64_t now = now_ns();
     if (now >= deadline) return fail(GVM_ETIMEDOUT, "timed out");
-    if (now - t0 < spin) {  // poll before sleeping (GVM_RANK_SPIN_US, default 200 us)
+    if (now - t0 < spin) {  // poll before sleeping (GVM_RANK_SPIN_US)
       for (int i = 0; i < 32; ++i) _mm_pause();
       continue;
     }

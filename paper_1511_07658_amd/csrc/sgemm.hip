@@ -29,15 +29,16 @@ namespace {
 // lane's fragments of the whole tile are then contiguous and are read with
 // 16-byte LDS reads before the MFMA sequence starts.  Double buffering: the
 // next tile is fetched into registers at the start of a k-step and written
-// to the other LDS buffer half-way through the MFMAs, so one barrier per
-// k-step remains.  Interior tiles take unchecked loads and stores; edge
+// to the other LDS buffer half-way through the MFMAs (or, LATE, after them:
+// more time for the global loads to land), so one barrier per k-step
+// remains.  Interior tiles take unchecked loads and stores; edge
 // tiles check every element and read zeros outside the matrix.
 //
 // Persistent grid, XCD-aware: the units (tiles, requests in order, tiles of a
 // request row-major) are dealt to the 8 XCDs in contiguous blocks, so that
 // tiles sharing rows of A and columns of B share an L2.
 
-template <int BM, int BN, int BK, int WM, int WN, bool VEC>
+template <int BM, int BN, int BK, int WM, int WN, bool LATE, bool VEC>
 __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) {
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM, TN = BN / WN;
@@ -184,13 +185,14 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
 #pragma unroll
       for (int s = 0; s < KH; ++s) {
         // The other buffer was last read before the previous barrier.
-        if (s == KH / 2 && more) store_tile(buf ^ 1);
+        if (!LATE && s == KH / 2 && more) store_tile(buf ^ 1);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
       }
+      if (LATE && more) store_tile(buf ^ 1);
       __syncthreads();
     }
 
@@ -225,14 +227,18 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
 
 // Tile configurations.  Index order is part of the tuner table format.
 const GemmConfig kGemmConfigs[] = {
-    {0, 64, 64, 16, 2, 2},
-    {1, 128, 64, 16, 2, 2},
-    {2, 128, 128, 16, 2, 2},
-    {3, 128, 128, 32, 2, 2},
-    {4, 256, 128, 16, 4, 2},
-    {5, 128, 256, 16, 2, 4},
-    {6, 256, 128, 32, 4, 2},
-    {7, 64, 128, 16, 2, 2},
+    {0, 64, 64, 16, 2, 2, false},
+    {1, 128, 64, 16, 2, 2, false},
+    {2, 128, 128, 16, 2, 2, false},
+    {3, 128, 128, 32, 2, 2, false},
+    {4, 256, 128, 16, 4, 2, false},
+    {5, 128, 256, 16, 2, 4, false},
+    {6, 256, 128, 32, 4, 2, false},
+    {7, 64, 128, 16, 2, 2, false},
+    {8, 128, 128, 16, 2, 2, true},
+    {9, 256, 128, 16, 4, 2, true},
+    {10, 128, 256, 16, 2, 4, true},
+    {11, 256, 128, 32, 4, 2, true},
 };
 constexpr int kNumGemmConfigs = sizeof(kGemmConfigs) / sizeof(kGemmConfigs[0]);
 
@@ -240,18 +246,14 @@ int g_forced_config = -1;
 
 #include "gemm_tiles.inc"   // kTileTable: (n_max, config index) rows written by the tuner
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, bool LATE>
 hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap) {
   constexpr int NT = WM * WN * 64;
   int cap = grid_cap > 0 ? grid_cap : 256 * 2;
   int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
-  if (grid <= 0) return hipSuccess;
   if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
-  if (vec)
-    hipLaunchKernelGGL((sgemm_group_kernel<BM, BN, BK, WM, WN, true>), dim3(grid), dim3(NT), 0, s, g);
-  else
-    hipLaunchKernelGGL((sgemm_group_kernel<BM, BN, BK, WM, WN, false>), dim3(grid), dim3(NT), 0, s, g);
-  return hipGetLastError();
+  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, LATE, true>, grid, NT, s, g)
+             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, LATE, false>, grid, NT, s, g);
 }
 
 }  // namespace
@@ -291,14 +293,18 @@ hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s,
         (reinterpret_cast<uintptr_t>(g.d[i].B) & 15))
       vec = false;
   switch (config_idx) {
-    case 0: return launch_cfg<64, 64, 16, 2, 2>(g, vec, s, grid_cap);
-    case 1: return launch_cfg<128, 64, 16, 2, 2>(g, vec, s, grid_cap);
-    case 2: return launch_cfg<128, 128, 16, 2, 2>(g, vec, s, grid_cap);
-    case 3: return launch_cfg<128, 128, 32, 2, 2>(g, vec, s, grid_cap);
-    case 4: return launch_cfg<256, 128, 16, 4, 2>(g, vec, s, grid_cap);
-    case 5: return launch_cfg<128, 256, 16, 2, 4>(g, vec, s, grid_cap);
-    case 6: return launch_cfg<256, 128, 32, 4, 2>(g, vec, s, grid_cap);
-    case 7: return launch_cfg<64, 128, 16, 2, 2>(g, vec, s, grid_cap);
+    case 0: return launch_cfg<64, 64, 16, 2, 2, false>(g, vec, s, grid_cap);
+    case 1: return launch_cfg<128, 64, 16, 2, 2, false>(g, vec, s, grid_cap);
+    case 2: return launch_cfg<128, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
+    case 3: return launch_cfg<128, 128, 32, 2, 2, false>(g, vec, s, grid_cap);
+    case 4: return launch_cfg<256, 128, 16, 4, 2, false>(g, vec, s, grid_cap);
+    case 5: return launch_cfg<128, 256, 16, 2, 4, false>(g, vec, s, grid_cap);
+    case 6: return launch_cfg<256, 128, 32, 4, 2, false>(g, vec, s, grid_cap);
+    case 7: return launch_cfg<64, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
+    case 8: return launch_cfg<128, 128, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 9: return launch_cfg<256, 128, 16, 4, 2, true>(g, vec, s, grid_cap);
+    case 10: return launch_cfg<128, 256, 16, 2, 4, true>(g, vec, s, grid_cap);
+    case 11: return launch_cfg<256, 128, 32, 4, 2, true>(g, vec, s, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }

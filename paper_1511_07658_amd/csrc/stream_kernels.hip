@@ -18,8 +18,14 @@ namespace gvm {
 
 namespace {
 
-constexpr int kStreamGrid = 1024;           // persistent grid of the streaming kernels
-constexpr bool kStreamNonTemporal = true;   // non-temporal loads/stores in them
+// Launch shapes measured on the MI355X (grid x {cached, non-temporal} sweep
+// of the grouped launches): vector ops 1024 workgroups, Black-Scholes 512.
+// A group whose bytes exceed the 256 MB memory-side cache streams through
+// with non-temporal loads and stores; a smaller one stays cacheable, since
+// its inputs come back from that cache on the next request.
+constexpr int kVecGrid = 1024;
+constexpr int kBsGrid = 512;
+constexpr uint64_t kMallBytes = 256ull << 20;
 
 // ---------------------------------------------------------------- vectors
 
@@ -180,35 +186,31 @@ void finalize_bs_group(BsGroup& g) {
   g.total_units = u;
 }
 
-// Streaming launch shape: persistent grid of kStreamGrid workgroups with
-// non-temporal memory operations; GVM_STREAM_GRID / GVM_STREAM_NT override
-// them for tuning (read once per process).
-int stream_grid(int grid_cap) {
+// Tuning overrides (read once per process): GVM_STREAM_GRID replaces the
+// grid, GVM_STREAM_NT = 0 / 1 forces cached / non-temporal access.
+int stream_grid(int grid_cap, int dflt) {
   static const int env = [] {
     const char* e = getenv("GVM_STREAM_GRID");
     return e ? atoi(e) : 0;
   }();
   if (grid_cap > 0) return grid_cap;
-  return env > 0 ? env : kStreamGrid;
+  return env > 0 ? env : dflt;
 }
 
-bool stream_nt() {
-  static const bool nt = [] {
+bool stream_nt(uint64_t group_bytes) {
+  static const int env = [] {
     const char* e = getenv("GVM_STREAM_NT");
-    return e ? atoi(e) != 0 : kStreamNonTemporal;
+    return e ? atoi(e) : -1;
   }();
-  return nt;
+  return env >= 0 ? env != 0 : group_bytes > kMallBytes;
 }
 
 template <class Op>
 hipError_t launch_vec(const VecGroup& g, hipStream_t s, int grid_cap) {
-  int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap))));
-  if (grid <= 0) return hipSuccess;
-  if (stream_nt())
-    hipLaunchKernelGGL((vec_group_kernel<Op, true>), dim3(grid), dim3(kThreads), 0, s, g);
-  else
-    hipLaunchKernelGGL((vec_group_kernel<Op, false>), dim3(grid), dim3(kThreads), 0, s, g);
-  return hipGetLastError();
+  const int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap, kVecGrid))));
+  const uint64_t bytes = g.total_units * kVecUnit * 12;
+  return stream_nt(bytes) ? launch_group(vec_group_kernel<Op, true>, grid, kThreads, s, g)
+                          : launch_group(vec_group_kernel<Op, false>, grid, kThreads, s, g);
 }
 
 hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap) { return launch_vec<AddOp>(g, s, grid_cap); }
@@ -216,13 +218,10 @@ hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap) {
 hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap) { return launch_vec<MulOp>(g, s, grid_cap); }
 
 hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap) {
-  int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap))));
-  if (grid <= 0) return hipSuccess;
-  if (stream_nt())
-    hipLaunchKernelGGL(bs_group_kernel<true>, dim3(grid), dim3(kThreads), 0, s, g);
-  else
-    hipLaunchKernelGGL(bs_group_kernel<false>, dim3(grid), dim3(kThreads), 0, s, g);
-  return hipGetLastError();
+  const int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap, kBsGrid))));
+  const uint64_t bytes = g.total_units * kBsUnit * 20;
+  return stream_nt(bytes) ? launch_group(bs_group_kernel<true>, grid, kThreads, s, g)
+                          : launch_group(bs_group_kernel<false>, grid, kThreads, s, g);
 }
 
 }  // namespace gvm

@@ -36,6 +36,7 @@ GVM_K_VECADD = 1
 GVM_K_BLACKSCHOLES = 2
 GVM_K_SGEMM = 3
 GVM_K_VECMUL = 4
+GVM_K_EP = 5
 
 GVM_MODE_BATCH = 0
 GVM_MODE_SERVING = 1
@@ -249,11 +250,15 @@ def check(rc, what="gvm call"):
 
 
 def in_elems(kernel_id, n):
-    return {GVM_K_VECADD: 2 * n, GVM_K_VECMUL: 2 * n, GVM_K_BLACKSCHOLES: 3 * n, GVM_K_SGEMM: 2 * n * n}[kernel_id]
+    """32-bit elements of a request's input (EP: the two 64-bit key words)."""
+    return {GVM_K_VECADD: 2 * n, GVM_K_VECMUL: 2 * n, GVM_K_BLACKSCHOLES: 3 * n, GVM_K_SGEMM: 2 * n * n,
+            GVM_K_EP: 4}[kernel_id]
 
 
 def out_elems(kernel_id, n):
-    return {GVM_K_VECADD: n, GVM_K_VECMUL: n, GVM_K_BLACKSCHOLES: 2 * n, GVM_K_SGEMM: n * n}[kernel_id]
+    """32-bit elements of a request's output (EP: twelve 64-bit words)."""
+    return {GVM_K_VECADD: n, GVM_K_VECMUL: n, GVM_K_BLACKSCHOLES: 2 * n, GVM_K_SGEMM: n * n,
+            GVM_K_EP: 24}[kernel_id]
 
 
 def header_symbols(header_path=None):

@@ -101,6 +101,9 @@ def run(nranks: int, reps: int, loopback: bool = False):
                                        backend=G.GVM_BACKEND_LOOPBACK if loopback else G.GVM_BACKEND_HIP)
             G.check(G.gvm_init(cfg), "gvm_init")
             try:
+                # one untimed batch over every rank: first copies into fresh
+                # device slots and staging run several times slower
+                _batches(ns, kid, n, nranks, 1, False)
                 if prof is None:  # single-rank profile with copies
                     st = _batches(ns, kid, n, 1, reps, False)
                     tm = st["timing"]

@@ -50,6 +50,8 @@ def make_input(kernel_id: int, config: int, rank: int, n: int, request: int = 0,
     if kernel_id == G.GVM_K_SGEMM:
         gen = wl.sgemm_int_inputs if integer else wl.sgemm_inputs
         return wl.pack_request(kernel_id, *gen(config, rank, n, request))
+    if kernel_id == G.GVM_K_EP:
+        return wl.ep_request(wl.ep_key(config, rank, request))
     raise ValueError(kernel_id)
 
 

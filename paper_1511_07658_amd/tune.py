@@ -29,9 +29,9 @@ from . import workloads as wl
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "gemm_tiles.inc")
-NUM_CONFIGS = 8
+NUM_CONFIGS = 12
 CONFIG_NAMES = ["64x64x16", "128x64x16", "128x128x16", "128x128x32", "256x128x16", "128x256x16", "256x128x32",
-                "64x128x16"]
+                "64x128x16", "128x128x16L", "256x128x16L", "128x256x16L", "256x128x32L"]
 
 
 def _time_size(ns, n, group, reps, configs):

@@ -31,6 +31,7 @@ BS_VOLATILITY = 0.30
 KERNEL_VECADD = 1
 KERNEL_BLACKSCHOLES = 2
 KERNEL_SGEMM = 3
+KERNEL_EP = 5
 
 
 def generator(config: int, rank: int, request: int = 0) -> np.random.Generator:
@@ -66,6 +67,24 @@ def sgemm_int_inputs(config: int, rank: int, n: int, request: int = 0, lo: int =
     return A, B
 
 
+def ep_key(config: int, rank: int, request: int = 0) -> np.ndarray:
+    """The 128-bit generator key (k0, k1) of one EP-like request."""
+    return generator(config, rank, request).integers(0, 2**64, size=2, dtype=np.uint64)
+
+
+def ep_request(key) -> np.ndarray:
+    """The packed input of an EP-like request: the two key words, viewed as
+    the four 32-bit elements the C-ABI transports."""
+    return np.ascontiguousarray(np.asarray(key, dtype=np.uint64)).view(np.float32)
+
+
+def ep_result(out) -> dict:
+    """Decode an EP-like output (24 32-bit elements): sx, sy and q[0..9]."""
+    w = np.ascontiguousarray(out).view(np.uint64)
+    return {"sx": float(w[:1].view(np.float64)[0]), "sy": float(w[1:2].view(np.float64)[0]),
+            "q": w[2:12].astype(np.int64)}
+
+
 def pack_request(kernel_id: int, *arrays) -> np.ndarray:
     """Concatenate the input arrays of one request into the packed binary32
     layout the C-ABI expects (``[a|b]``, ``[S|K|T]`` or ``[A|B]``)."""
@@ -79,6 +98,8 @@ def in_elems(kernel_id: int, n: int) -> int:
         return 3 * n
     if kernel_id == KERNEL_SGEMM:
         return 2 * n * n
+    if kernel_id == KERNEL_EP:
+        return 4
     raise ValueError(f"unknown kernel id {kernel_id}")
 
 
@@ -89,6 +110,8 @@ def out_elems(kernel_id: int, n: int) -> int:
         return 2 * n
     if kernel_id == KERNEL_SGEMM:
         return n * n
+    if kernel_id == KERNEL_EP:
+        return 24
     raise ValueError(f"unknown kernel id {kernel_id}")
 
 

@@ -4,7 +4,10 @@ Bars: vector add / multiply bit-exact; Black-Scholes relative L2 error of
 each output vector <= 1e-5 (plus a per-element diagnostic and put-call
 parity on the GPU output); SGEMM relative Frobenius error <= 1e-4 against
 the float64 oracle, and bit-exact on small-integer inputs (every partial sum
-is an exactly representable integer).  Virtualisation must not change a
+is an exactly representable integer); EP-like: the ten annulus counts exact
+(both sides decide them in binary64), the two sums within
+256 eps sum|X| of the exactly rounded sum (a worst-case bound for the
+kernel's summation depth plus a few ulp per term from the binary64 log).  Virtualisation must not change a
 rank's bytes: alone, in the mix, under every policy and in the plain
 per-process path the outputs are identical.
 """
@@ -16,10 +19,12 @@ import threading
 import numpy as np
 import pytest
 
+from oracle import ep as oe
 from oracle import kernels as ok
 from paper_1511_07658_amd import gvm as G
 from paper_1511_07658_amd import spmd
 from paper_1511_07658_amd import workloads as wl
+from paper_1511_07658_amd.tune import NUM_CONFIGS
 
 pytestmark = pytest.mark.gpu
 
@@ -98,6 +103,19 @@ def assert_sgemm(out, cfg, rank, n, req=0, integer=False):
 
 # ------------------------------------------------------------------ tests
 
+EP_TOL_ULPS = 256
+
+
+def assert_ep(out, cfg, rank, n, req=0):
+    ref = oe.ep_reference(wl.ep_key(cfg, rank, req), n)
+    got = wl.ep_result(out)
+    assert np.array_equal(got["q"], ref["q"]), f"rank {rank} n {n}: counts {got['q']} vs {ref['q']}"
+    eps = np.finfo(np.float64).eps
+    for s, a in (("sx", "abs_x"), ("sy", "abs_y")):
+        tol = EP_TOL_ULPS * eps * ref[a]
+        assert abs(got[s] - ref[s]) <= tol, f"rank {rank} n {n} {s}: {got[s]!r} vs {ref[s]!r} (tol {tol:.3e})"
+
+
 def test_vecadd_bitexact_ragged(ns_name):
     sizes = [1, 3, 4, 4095, 4097, 65537, (1 << 20) + 3]
     with hip_manager(ns_name, nranks=len(sizes)):
@@ -142,7 +160,7 @@ def test_every_tile_configuration(ns_name):
         A, B = wl.sgemm_inputs(15, 0, n)
         x = wl.pack_request(3, A, B)
         outs = []
-        for cfg_idx in range(8):
+        for cfg_idx in range(NUM_CONFIGS):
             os.environ["GVM_SGEMM_CONFIG"] = str(cfg_idx)
             try:
                 o = np.empty(n * n, np.float32)
@@ -190,8 +208,8 @@ def test_config3_sixteen_ranks_blackscholes_4m(ns_name):
 
 
 def _jobs_mix(r):
-    k = [1, 2, 3, 4][r % 4]
-    n = {1: 300001 + r, 2: 70001 + r, 3: 96 + 64 * (r % 3) + r, 4: 5000 + r}[k]
+    k = [1, 2, 3, 4, 5][r % 5]
+    n = {1: 300001 + r, 2: 70001 + r, 3: 96 + 64 * (r % 3) + r, 4: 5000 + r, 5: 100003 + r}[k]
     return [(k, 21, n, 0, False)]
 
 
@@ -215,6 +233,30 @@ def test_alone_equals_mix_equals_plain(ns_name, policy):
         rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
         assert rc == 0, G.gvm_last_error()
         assert spmd.digest(o) == mixed[r]["digest"], f"rank {r} differs plain vs GVM"
+
+
+EP_SIZES = [1, 2, 3, 1001, (1 << 15) - 1, 1 << 15, (1 << 15) + 1, 3 * (1 << 15) + 5, 1 << 20]
+
+
+def test_ep_matches_oracle_ragged(ns_name):
+    # sizes around the 2^15-pair work unit: partial units, one, several
+    with hip_manager(ns_name, nranks=1):
+        jobs = [(G.GVM_K_EP, 31, n, i, False) for i, n in enumerate(EP_SIZES)]
+        outs = check_ok(run_ranks(ns_name, [jobs])[0])
+        for (k, cfg, n, req, _), o in zip(jobs, outs):
+            assert_ep(o, cfg, 0, n, req)
+
+
+def test_ep_four_ranks_grouped_match_oracle(ns_name):
+    # one grouped launch over four ranks' requests of 2^22 pairs
+    n = 1 << 22
+    with hip_manager(ns_name, nranks=4, policy=G.GVM_POLICY_GROUPED):
+        res = run_ranks(ns_name, [[(G.GVM_K_EP, 32, n, 0, False)] for _ in range(4)])
+        for r in range(4):
+            (o,) = check_ok(res[r])
+            assert_ep(o, 32, r, n)
+        st = G.gvm_stats_json()
+        assert st["kernels"]["ep"]["launches"] == 1 and st["kernels"]["ep"]["requests"] == 4
 
 
 def test_resident_buffers(ns_name):

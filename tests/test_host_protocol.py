@@ -76,7 +76,7 @@ def test_threads_get_their_own_data_back(ns_name):
 
         def rank(r):
             assert G.gvm_attach_ns(ns_name, r) == 0
-            for i, (k, n) in enumerate([(1, 1), (1, 4097), (2, 333), (3, 17), (4, 5)]):
+            for i, (k, n) in enumerate([(1, 1), (1, 4097), (2, 333), (3, 17), (4, 5), (5, 7), (5, 1 << 20)]):
                 inp = (np.arange(G.in_elems(k, n), dtype=np.float32) + 1000 * r + 10 * i)
                 out = np.full(G.out_elems(k, n), -1, np.float32)
                 t = G.gvm_submit(r, k, inp, out, n)
