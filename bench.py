@@ -37,13 +37,13 @@ from paper_1511_07658_amd import workloads as wl  # noqa: E402
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBPS = 8000.0
-# EP-like kernel: ALU issue bound.  The compiled unit loop issues, per
-# Philox block (two pairs, both accepted), 109 integer multiplies and 6
-# binary64 reciprocal / square-root estimates (quarter rate: 16 cycles per
-# wave64 instruction) and about 500 other VALU instructions (4 cycles):
-# 3840 SIMD cycles per 128 pairs = 30 cycles per pair; 256 CUs x 4 SIMDs x
-# 2.4 GHz / 30 = 81.9 Gpairs/s.
-EP_SIMD_CYCLES_PER_PAIR = 30.0
+# EP-like kernel: VALU issue bound.  A SIMD issues one wave64 VALU
+# instruction per 4 cycles (16 lanes); the compiled unit loop of
+# csrc/ep_kernels.hip issues 602 VALU instructions per Philox block, i.e.
+# per 2 pairs of each of the 64 lanes (both pairs accepted; the rejected path
+# is a subset): 4 * 602 / 128 = 18.8 SIMD cycles per pair, and 256 CUs x 4
+# SIMDs x 2.4 GHz / 18.8 = 130.6 Gpairs/s.
+EP_SIMD_CYCLES_PER_PAIR = 4.0 * 602 / 128
 PEAK_EP_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE /
@@ -145,6 +145,7 @@ def bench_rank(ns, rank, kernel_id, n, cfg_idx, warmup, steps, e2e_steps, barrie
     submit_ex, wait_timed = lib.gvm_submit_ex, lib.gvm_wait_timed
     ts = (ctypes.c_uint64 * 5)()
     parts = [0, 0, 0, 0, 0, 0]
+    stamps = []                          # per step: submit, admit, posted, seen (ns)
     t0 = clock(mono)
     seen = t0
     for _ in range(steps):
@@ -162,6 +163,7 @@ def bench_rank(ns, rank, kernel_id, n, cfg_idx, warmup, steps, e2e_steps, barrie
         parts[3] += ts[4] - ts[3]
         parts[4] += now - ts[4]
         parts[5] += ts[0] - seen
+        stamps.append((ts[0], ts[1], ts[4], now))
         seen = now
     t1 = clock(mono)
     barrier.wait()                       # 4: timed steps done
@@ -175,7 +177,24 @@ def bench_rank(ns, rank, kernel_id, n, cfg_idx, warmup, steps, e2e_steps, barrie
     same = spmd.digest(out) == first
     G.gvm_detach(rank)
     return {"t0": t0, "t1": t1, "e0": e0, "e1": e1, "same_bytes": same, "digest": first,
-            "parts_ns": [x / max(steps, 1) for x in parts]}
+            "parts_ns": [x / max(steps, 1) for x in parts], "stamps": stamps}
+
+
+def step_detail(rr):
+    """Across ranks, per timed step: spread of the submit times, spread of
+    the completion posts, and the gap from the previous step's last post to
+    this step's first submit (means, us), plus how often each rank submitted
+    last (the one the request barrier waits for)."""
+    st = np.array([r["stamps"] for r in rr], dtype=np.float64)   # ranks x steps x 4
+    if st.ndim != 3 or st.shape[1] < 2:
+        return None
+    sub, post = st[:, :, 0], st[:, :, 2]
+    last = np.bincount(np.argmax(sub, axis=0), minlength=st.shape[0])
+    return {"submit_spread": round(float(np.mean(sub.max(0) - sub.min(0))) * 1e-3, 2),
+            "post_spread": round(float(np.mean(post.max(0) - post.min(0))) * 1e-3, 2),
+            "last_post_to_first_submit": round(float(np.mean(sub.min(0)[1:] - post.max(0)[:-1])) * 1e-3, 2),
+            "last_post_to_last_submit": round(float(np.mean(sub.max(0)[1:] - post.max(0)[:-1])) * 1e-3, 2),
+            "last_submitter_counts": last.tolist()}
 
 
 def plain_rank(kernel_id, n, cfg_idx, rank, barrier):
@@ -422,6 +441,7 @@ def main(argv=None):
             ["barrier_and_drain", "admit_to_launch", "launch_to_device_done", "device_done_to_posted",
              "posted_to_seen", "rank_loop"],
             [round(float(x) * 1e-3, 2) for x in np.mean([r["parts_ns"] for r in rr], axis=0)])),
+        "step_detail_us": step_detail(rr),
         "e2e_pcie": {"value": round(e2e_value, 3), "unit": unit, "steps": a.e2e_steps,
                      "ms_per_step": round(e2e / max(a.e2e_steps, 1) * 1e3, 3)},
         "plain": None if plain is None else {k: v for k, v in plain.items() if k != "digests"},

@@ -30,6 +30,12 @@ struct Layout {
 
 constexpr int kNumKernelIds = 6;  // kernel ids 1..5; index 0 collects mixed graph launches
 
+// Requests move between the ranks' shared memory, the pinned staging and the
+// device in pieces of this size (unless batch_timing asks for whole copies):
+// each piece's next hop starts as soon as it lands.
+constexpr uint64_t kPieceBytes = 4ull << 20;   // one host copy chunk: each piece lands on one worker
+inline uint32_t piece_count(uint64_t bytes) { return static_cast<uint32_t>((bytes + kPieceBytes - 1) / kPieceBytes); }
+
 // EP-like kernel: pairs per work unit, and the 64-bit words of one result
 // record (sx, sy, q[0..9]), the request's output and each unit's partial.
 constexpr uint64_t kEpUnit = 1ull << 15;

@@ -37,6 +37,13 @@ struct Job {
   int done_index = -1;
   int stage = kStageCopyIn;
   std::atomic<int> copies{0};   // host copy chunks still in flight
+  // Piecewise copies (kPieceBytes): the input's pieces go to the device as
+  // each lands in the pinned staging, the output's pieces come back to shared
+  // memory as each leaves the device.
+  bool pieces = false;
+  uint32_t in_pieces = 0, in_sent = 0;                 // input pieces; those whose H2D is queued
+  std::unique_ptr<std::atomic<int>[]> in_pending;      // host copy chunks in flight per input piece
+  uint32_t out_pieces = 0, out_taken = 0;              // output pieces; those handed to the host copy
 };
 
 struct KernelStats {
@@ -58,8 +65,15 @@ class Device {
   virtual int open(const gvm_config& cfg) = 0;
   virtual uint8_t* arena() = 0;                 // hbm_budget_bytes of device memory
   virtual uint8_t* staging(int rank) = 0;       // pinned staging of a rank (nullptr on failure)
-  // Enqueue the device work of the admitted jobs under `policy`.
+  // Queue the host-to-device copy of input bytes [off, off + bytes) of a
+  // piecewise job (in order, before launch()).
+  virtual int stream_in(Job* j, uint64_t off, uint64_t bytes) = 0;
+  // Enqueue the device work of the admitted jobs under `policy` (a piecewise
+  // job's copy-in is already queued; its copy-out is queued piece by piece).
   virtual int launch(std::vector<Job*>& jobs, int policy) = 0;
+  // Leading output pieces of a piecewise job that have reached the pinned
+  // staging (< 0 on a device error).
+  virtual int out_pieces_done(Job* j) = 0;
   // 1 when the job's device work has finished, 0 if not yet, < 0 on a device error.
   virtual int query(Job* j) = 0;
   // Start a polling round: query() may then ask the runtime about each

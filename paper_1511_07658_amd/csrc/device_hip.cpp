@@ -43,6 +43,7 @@ struct TimedCopy {
   int dir;  // 0 host->device, 1 device->host
   hipEvent_t e0, e1;
   uint64_t bytes;
+  bool first;  // first piece of a request's copy (copies are counted per request)
 };
 
 struct Batch {
@@ -53,6 +54,8 @@ struct Batch {
   std::vector<hipEvent_t> done;   // per job (several jobs may share one event)
   std::vector<hipEvent_t> sync;   // events owned by the batch, recycled at the end
   std::vector<TimedLaunch> timed;
+  std::vector<std::vector<hipEvent_t>> out_ev;  // per job: one event after each output piece
+  std::vector<uint32_t> out_done;               // per job: leading output pieces seen complete
   size_t remaining = 0;
 };
 
@@ -125,6 +128,27 @@ class HipDevice final : public Device {
     return staging_[rank];
   }
 
+  int stream_in(Job* j, uint64_t off, uint64_t bytes) override {
+    // timing records wait in pre_copies_ until the job's batch exists
+    return timed_copy(j->slot + off, j->pin + off, bytes, hipMemcpyHostToDevice, h2d_,
+                      cfg_.batch_timing ? &pre_copies_[j] : nullptr, off == 0);
+  }
+
+  int out_pieces_done(Job* j) override {
+    auto* b = static_cast<Batch*>(j->batch);
+    if (!b) return static_cast<int>(j->out_pieces);
+    const size_t i = static_cast<size_t>(j->done_index);
+    const auto& evs = b->out_ev[i];
+    uint32_t& done = b->out_done[i];
+    while (done < evs.size()) {
+      const hipError_t e = hipEventQuery(evs[done]);
+      if (e == hipErrorNotReady) break;
+      if (e != hipSuccess) return fail(GVM_EDEVICE, "device-to-host copy failed: %s", hipGetErrorString(e));
+      ++done;
+    }
+    return static_cast<int>(done);
+  }
+
   int launch(std::vector<Job*>& jobs, int policy) override {
     if (jobs.empty()) return GVM_OK;
     if (policy != GVM_POLICY_PS1 && policy != GVM_POLICY_PS2)
@@ -132,11 +156,18 @@ class HipDevice final : public Device {
     auto* b = new Batch;
     b->jobs = jobs;
     b->done.assign(jobs.size(), nullptr);
+    b->out_ev.resize(jobs.size());
+    b->out_done.assign(jobs.size(), 0);
     b->remaining = jobs.size();
     for (size_t i = 0; i < jobs.size(); ++i) {
       jobs[i]->batch = b;
       jobs[i]->done_index = static_cast<int>(i);
       jobs[i]->t_launch_ns = now_ns();
+      auto pre = pre_copies_.find(jobs[i]);
+      if (pre != pre_copies_.end()) {
+        b->copies.insert(b->copies.end(), pre->second.begin(), pre->second.end());
+        pre_copies_.erase(pre);
+      }
     }
     int rc = GVM_OK;
     // device phase of the batch: every stream it uses starts after span0 and
@@ -314,6 +345,12 @@ class HipDevice final : public Device {
       (void)hipGraphDestroy(kv.second.graph);
     }
     graphs_.clear();
+    for (auto& kv : pre_copies_)
+      for (auto& t : kv.second) {
+        (void)hipEventDestroy(t.e0);
+        (void)hipEventDestroy(t.e1);
+      }
+    pre_copies_.clear();
     for (hipEvent_t e : free_sync_) (void)hipEventDestroy(e);
     for (hipEvent_t e : free_timed_) (void)hipEventDestroy(e);
     free_sync_.clear();
@@ -429,9 +466,12 @@ class HipDevice final : public Device {
 
   // One copy of a job between its pinned staging and its device slot; with
   // batch_timing (and outside a capture) bracketed by timing events.
-  int timed_copy(void* dst, const void* src, uint64_t bytes, hipMemcpyKind kind, hipStream_t s, Batch* b) {
-    TimedCopy t{kind == hipMemcpyHostToDevice ? 0 : 1, nullptr, nullptr, bytes};
-    const bool timed = cfg_.batch_timing && !capturing_ && b;
+  // `into` receives the timing record (a batch's list, or the pre-launch
+  // list of a piecewise input); `first` marks a request's first piece.
+  int timed_copy(void* dst, const void* src, uint64_t bytes, hipMemcpyKind kind, hipStream_t s,
+                 std::vector<TimedCopy>* into, bool first = true) {
+    TimedCopy t{kind == hipMemcpyHostToDevice ? 0 : 1, nullptr, nullptr, bytes, first};
+    const bool timed = cfg_.batch_timing && !capturing_ && into;
     if (timed) {
       t.e0 = timed_event();
       t.e1 = timed_event();
@@ -441,21 +481,36 @@ class HipDevice final : public Device {
     HIPCHK(hipMemcpyAsync(dst, src, bytes, kind, s));
     if (timed) {
       HIPCHK(hipEventRecord(t.e1, s));
-      b->copies.push_back(t);
+      into->push_back(t);
     }
     return GVM_OK;
   }
 
   int enqueue_in(Job* j, hipStream_t s) {
-    if (!j->copy_in) return GVM_OK;
-    return timed_copy(j->slot, j->pin, j->lay.in_bytes, hipMemcpyHostToDevice, s, static_cast<Batch*>(j->batch));
+    if (!j->copy_in || j->pieces) return GVM_OK;  // a piecewise input is queued as it lands
+    return timed_copy(j->slot, j->pin, j->lay.in_bytes, hipMemcpyHostToDevice, s, &static_cast<Batch*>(j->batch)->copies);
   }
 
   int enqueue_out(Job* j, hipStream_t s) {
     if (!j->copy_out) return GVM_OK;
     const uint64_t o = slot_out_offset(j->lay);
-    return timed_copy(j->pin + o, j->slot + o, j->lay.out_bytes, hipMemcpyDeviceToHost, s,
-                      static_cast<Batch*>(j->batch));
+    auto* b = static_cast<Batch*>(j->batch);
+    if (!j->out_pieces)
+      return timed_copy(j->pin + o, j->slot + o, j->lay.out_bytes, hipMemcpyDeviceToHost, s, &b->copies);
+    // piecewise: an event after each piece lets the host copy of the
+    // leading pieces start while the rest is still on the link
+    auto& evs = b->out_ev[static_cast<size_t>(j->done_index)];
+    for (uint32_t i = 0; i < j->out_pieces; ++i) {
+      const uint64_t off = static_cast<uint64_t>(i) * kPieceBytes;
+      const int rc = timed_copy(j->pin + o + off, j->slot + o + off, std::min<uint64_t>(kPieceBytes, j->lay.out_bytes - off),
+                                hipMemcpyDeviceToHost, s, &b->copies, i == 0);
+      if (rc != GVM_OK) return rc;
+      hipEvent_t e = sync_event(b);
+      if (!e) return GVM_EDEVICE;
+      HIPCHK(hipEventRecord(e, s));
+      evs.push_back(e);
+    }
+    return GVM_OK;
   }
 
   // One grouped launch per kernel id (per tile configuration for SGEMM), at
@@ -763,7 +818,7 @@ class HipDevice final : public Device {
       if (hipEventElapsedTime(&ms, c.e0, c.e1) == hipSuccess) {
         copy_ms_[c.dir] += ms;
         copy_bytes_[c.dir] += static_cast<double>(c.bytes);
-        copy_n_[c.dir] += 1;
+        copy_n_[c.dir] += c.first ? 1 : 0;
       }
       free_timed_.push_back(c.e0);
       free_timed_.push_back(c.e1);
@@ -817,6 +872,7 @@ class HipDevice final : public Device {
   std::vector<hipStream_t> rank_streams_;
   std::vector<hipStream_t> compute_streams_;
   hipStream_t h2d_ = nullptr, d2h_ = nullptr;  // copy FIFOs, one per direction
+  std::map<const Job*, std::vector<TimedCopy>> pre_copies_;  // timed input pieces of jobs not yet launched
   size_t next_cs_ = 0;
   struct FifoEntry {
     Batch* b;

@@ -74,7 +74,7 @@ class LoopbackDevice final : public Device {
     const uint64_t t_batch = now_ns();
     for (Job* j : jobs) {
       j->t_launch_ns = now_ns();
-      if (j->copy_in) timed_copy(0, j->slot, j->pin, j->lay.in_bytes);
+      if (j->copy_in && !j->pieces) timed_copy(0, j->slot, j->pin, j->lay.in_bytes);
       const uint64_t o = slot_out_offset(j->lay);
       const uint64_t keep = j->lay.in_bytes < j->lay.out_bytes ? j->lay.in_bytes : j->lay.out_bytes;
       memmove(j->slot + o, j->slot, keep);
@@ -91,6 +91,13 @@ class LoopbackDevice final : public Device {
     if (cfg_.batch_timing) batch_us_.push_back((now_ns() - t_batch) * 1e-3);
     return GVM_OK;
   }
+
+  int stream_in(Job* j, uint64_t off, uint64_t bytes) override {
+    memcpy(j->slot + off, j->pin + off, bytes);
+    return GVM_OK;
+  }
+
+  int out_pieces_done(Job* j) override { return static_cast<int>(j->out_pieces); }
 
   int query(Job* j) override {
     if (!j->t_device_ns) j->t_device_ns = now_ns();

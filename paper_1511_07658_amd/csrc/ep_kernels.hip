@@ -22,6 +22,7 @@ namespace {
 
 constexpr int kEpThreads = 256;
 constexpr int kEpGrid = 1024;   // persistent grid of the unit launch
+static_assert(kEpUnit / kEpThreads <= 255, "per-thread 8-bit annulus counts of a unit would overflow");
 
 // Philox4x64 multipliers and Weyl key increments (Salmon et al., 2011).
 constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull, kPhiloxM1 = 0xCA5A826395121157ull;
@@ -52,9 +53,24 @@ __device__ __forceinline__ void philox_block(uint64_t b, uint64_t k0, uint64_t k
   w[3] = c3;
 }
 
+// A thread's annulus counts within one work unit, 8 bits each: counts 0..7
+// in `lo`, 8..9 in `hi` (a thread tallies at most 2 * kEpUnit / (2 *
+// kEpThreads) = 128 pairs of a unit, so no field overflows).
+struct Tally {
+  uint64_t lo = 0, hi = 0;
+  __device__ __forceinline__ void add(int l) {  // l in 0..9, or >= 10: not counted
+    const uint64_t one = 1ull << (8 * (l & 7));
+    lo += l < 8 ? one : 0;
+    hi += (l >= 8 && l < 10) ? one : 0;
+  }
+  __device__ __forceinline__ uint32_t get(int l) const {
+    return static_cast<uint32_t>(((l < 8 ? lo : hi) >> (8 * (l & 7))) & 0xFF);
+  }
+};
+
 // One pair from two generator words: accept it when 0 < t <= 1 and add its
 // Gaussian pair to the running sums and annulus counts.
-__device__ __forceinline__ void ep_pair(uint64_t wx, uint64_t wy, double& sx, double& sy, uint32_t q[10]) {
+__device__ __forceinline__ void ep_pair(uint64_t wx, uint64_t wy, double& sx, double& sy, Tally& q) {
 #pragma clang fp contract(off)
   const double x = 2.0 * (static_cast<double>(wx >> 11) * 0x1.0p-53) - 1.0;
   const double y = 2.0 * (static_cast<double>(wy >> 11) * 0x1.0p-53) - 1.0;
@@ -65,9 +81,7 @@ __device__ __forceinline__ void ep_pair(uint64_t wx, uint64_t wy, double& sx, do
     sx += X;
     sy += Y;
     const double m = fmax(fabs(X), fabs(Y));
-    const int l = m < 10.0 ? static_cast<int>(m) : 10;  // floor for m >= 0
-#pragma unroll
-    for (int i = 0; i < 10; ++i) q[i] += (l == i);      // no dynamic register indexing
+    q.add(m < 10.0 ? static_cast<int>(m) : 10);  // floor for m >= 0
   }
 }
 
@@ -97,7 +111,7 @@ __global__ __launch_bounds__(kEpThreads) void ep_units_kernel(EpGroup g) {
     const uint64_t p1 = min(p0 + kEpUnit, d.n);              // end of pairs
     const uint64_t k0 = d.key[0], k1 = d.key[1];
     double sx = 0.0, sy = 0.0;
-    uint32_t q[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Tally q;
     if (threadIdx.x < 10) cnt[threadIdx.x] = 0;
     for (uint64_t b = p0 / 2 + threadIdx.x; 2 * b < p1; b += kEpThreads) {
       uint64_t w[4];
@@ -108,7 +122,7 @@ __global__ __launch_bounds__(kEpThreads) void ep_units_kernel(EpGroup g) {
     __syncthreads();  // cnt cleared
 #pragma unroll
     for (int l = 0; l < 10; ++l)
-      if (q[l]) atomicAdd(&cnt[l], q[l]);
+      if (q.get(l)) atomicAdd(&cnt[l], q.get(l));
     sx = tree_sum(sx, red);
     sy = tree_sum(sy, red);
     if (threadIdx.x == 0) {

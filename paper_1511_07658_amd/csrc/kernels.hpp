@@ -87,7 +87,7 @@ struct GemmConfig {
   int id;
   int bm, bn, bk;   // macro tile of one workgroup
   int wm, wn;       // waves along M and N (wave tile = bm/wm x bn/wn)
-  bool late;        // next tile written to LDS after the k-step's MFMAs, not half-way
+  bool bt;          // B staged k-contiguous in LDS (transposed), else row-major
 };
 
 int gemm_config_count();

@@ -373,11 +373,27 @@ bool Manager::complete_jobs() {
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
     Job* j = ranks_[r].running;
     if (!j || j->stage != kStageDevice) continue;
+    const uint64_t out_off = slot_out_offset(j->lay);
+    if (j->out_pieces && j->status == GVM_OK) {
+      // hand each output piece to the host copy as soon as it is staged
+      const int n = dev_->out_pieces_done(j);
+      if (n < 0) {
+        j->status = n;
+      } else {
+        for (; j->out_taken < static_cast<uint32_t>(n); ++j->out_taken) {
+          const uint64_t off = static_cast<uint64_t>(j->out_taken) * kPieceBytes;
+          copy_.submit(j->shm + j->req.off_out + off, j->pin + out_off + off,
+                       std::min<uint64_t>(kPieceBytes, j->lay.out_bytes - off), &j->copies);
+          any = true;
+        }
+        if (j->out_taken < j->out_pieces) continue;
+      }
+    }
     if (dev_->query(j) == 0) continue;
     device_done.push_back(j);
     any = true;
-    if (j->status == GVM_OK && j->copy_out)
-      copy_.submit(j->shm + j->req.off_out, j->pin + slot_out_offset(j->lay), j->lay.out_bytes, &j->copies);
+    if (j->status == GVM_OK && j->copy_out && !j->out_pieces)
+      copy_.submit(j->shm + j->req.off_out, j->pin + out_off, j->lay.out_bytes, &j->copies);
     j->stage = kStageCopyOut;
   }
   // 2. answer every rank whose result is in place, before any bookkeeping
@@ -422,7 +438,20 @@ bool Manager::launch_ready() {
   if (staged_.empty()) return false;
   bool all = true;
   for (Job* j : staged_) {
-    if (j->stage == kStageCopyIn && j->copies.load(std::memory_order_acquire) == 0) j->stage = kStageReady;
+    if (j->stage == kStageCopyIn) {
+      if (j->pieces) {
+        // each input piece goes to the device as soon as it is staged
+        while (j->in_sent < j->in_pieces && j->in_pending[j->in_sent].load(std::memory_order_acquire) == 0) {
+          const uint64_t off = static_cast<uint64_t>(j->in_sent) * kPieceBytes;
+          const int rc = dev_->stream_in(j, off, std::min<uint64_t>(kPieceBytes, j->lay.in_bytes - off));
+          if (rc != GVM_OK && j->status == GVM_OK) j->status = rc;
+          ++j->in_sent;
+        }
+        if (j->in_sent == j->in_pieces) j->stage = kStageReady;
+      } else if (j->copies.load(std::memory_order_acquire) == 0) {
+        j->stage = kStageReady;
+      }
+    }
     all &= (j->stage == kStageReady);
   }
   // A batch of kernels that run as one grouped launch waits for all of its
@@ -504,9 +533,23 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   j->copy_in = copy_in;
   j->copy_out = copy_out;
   j->t_admit_ns = now_ns();
+  // whole copies only where a batch's device phase is timed as one span
+  j->pieces = !(cfg_.batch_timing && cfg_.mode == GVM_MODE_BATCH);
+  if (j->pieces && copy_out) j->out_pieces = piece_count(lay.out_bytes);
   if (copy_in) {
     j->stage = kStageCopyIn;
-    copy_.submit(j->pin, j->shm + m.off_in, lay.in_bytes, &j->copies);
+    if (j->pieces) {
+      j->in_pieces = piece_count(lay.in_bytes);
+      j->in_pending.reset(new std::atomic<int>[j->in_pieces]());
+      for (uint32_t i = 0; i < j->in_pieces; ++i) {
+        const uint64_t off = static_cast<uint64_t>(i) * kPieceBytes;
+        const uint64_t len = std::min<uint64_t>(kPieceBytes, lay.in_bytes - off);
+        j->in_pending[i].store(0, std::memory_order_relaxed);
+        copy_.submit(j->pin + off, j->shm + m.off_in + off, len, &j->in_pending[i]);
+      }
+    } else {
+      copy_.submit(j->pin, j->shm + m.off_in, lay.in_bytes, &j->copies);
+    }
   } else {
     j->stage = kStageReady;
   }

@@ -4,11 +4,14 @@
 #include <sched.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <cstring>
 #include <deque>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
+#include <vector>
 
 #include "common.hpp"
 #include "rank.hpp"
@@ -17,6 +20,30 @@
 namespace gvm {
 
 namespace {
+
+// Copy between the caller's memory and its shared-memory space.  A large
+// copy is split over a few threads when the host has cores to spare: one
+// thread moves about 10 GB/s, the PCIe link behind the manager ~57 GB/s.
+// Threads per copy: the cores per rank (online CPUs / (ranks + 2)), 1..8.
+void rank_copy(void* dst, const void* src, uint64_t bytes, uint32_t nranks) {
+  constexpr uint64_t kSplit = 8ull << 20;
+  static const long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
+  const long spare = ncpu / (static_cast<long>(nranks) + 2);
+  const int nt = static_cast<int>(std::min<long>(std::min<long>(spare, 8), static_cast<long>(bytes / kSplit)));
+  if (nt <= 1) {
+    memcpy(dst, src, bytes);
+    return;
+  }
+  const uint64_t part = (bytes / nt + 4095) & ~4095ull;
+  std::vector<std::thread> ts;
+  for (int i = 1; i < nt; ++i) {
+    const uint64_t off = part * i;
+    if (off >= bytes) break;
+    ts.emplace_back([=] { memcpy(static_cast<uint8_t*>(dst) + off, static_cast<const uint8_t*>(src) + off, std::min(part, bytes - off)); });
+  }
+  memcpy(dst, src, std::min(part, bytes));
+  for (auto& t : ts) t.join();
+}
 
 struct Alloc {
   uint64_t start, end;
@@ -118,7 +145,7 @@ void drain(RankHandle& h) {
     for (auto it = h.pending.begin(); it != h.pending.end(); ++it) {
       if (it->ticket != r.ticket) continue;
       if (r.status == GVM_OK && it->copy_out)
-        memcpy(it->out, static_cast<uint8_t*>(h.data.addr) + it->off_out, it->out_bytes);
+        rank_copy(it->out, static_cast<uint8_t*>(h.data.addr) + it->off_out, it->out_bytes, g_ns.hdr ? g_ns.hdr->nranks : 1);
       release(h, it->ticket);
       h.pending.erase(it);
       break;
@@ -348,7 +375,7 @@ int64_t rank_submit(int rank, int kernel_id, const void* in, void* out, uint64_t
   m.out_bytes = lay.out_bytes;
   m.off_in = in_res ? 0 : (in_zero ? static_cast<uint64_t>(static_cast<const uint8_t*>(in) - base) : off);
   m.off_out = out_res ? 0 : (out_zero ? static_cast<uint64_t>(static_cast<uint8_t*>(out) - base) : off + need_in);
-  if (need_in) memcpy(base + m.off_in, in, lay.in_bytes);
+  if (need_in) rank_copy(base + m.off_in, in, lay.in_bytes, g_ns.hdr ? g_ns.hdr->nranks : 1);
   m.t_submit_ns = now_ns();
   int rc = push_message(h, hdr, m);
   if (rc != GVM_OK) {

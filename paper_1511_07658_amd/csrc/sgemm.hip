@@ -23,36 +23,40 @@ namespace {
 // lane group g = l/32 selects which of the two k values it carries.  Within
 // a BK tile, MFMA step s takes k = s for g = 0 and k = BK/2 + s for g = 1.
 //
-// Both operands sit in LDS k-contiguous: As[m][k] and Bs[n][k] (B
-// transposed on the way in; each thread fetches four k-rows of one column,
-// so the global reads stay coalesced along n), rows padded by 4 floats.  A
-// lane's fragments of the whole tile are then contiguous and are read with
-// 16-byte LDS reads before the MFMA sequence starts.  Double buffering: the
-// next tile is fetched into registers at the start of a k-step and written
-// to the other LDS buffer half-way through the MFMAs (or, LATE, after them:
-// more time for the global loads to land), so one barrier per k-step
-// remains.  Interior tiles take unchecked loads and stores; edge
+// A sits in LDS as As[m][k] (rows padded by 4 floats), so a lane's A
+// fragments of a whole tile are contiguous and read with 16-byte LDS reads.
+// B has two stagings, chosen per tile configuration by the tuner:
+//  * BT: Bs[n][k], B transposed on the way in (each thread fetches four
+//    k-rows of one column, coalesced along n); B fragments are then 16-byte
+//    reads like A's;
+//  * row-major: Bs[k][n] from float4 loads along n; B fragments are 4-byte
+//    reads (one per MFMA step and column block).
+// All fragments of a k-step are read before its MFMAs.  Double buffering:
+// the next tile is fetched into registers at the start of a k-step and
+// written to the other LDS buffer half-way through the MFMAs, so one barrier
+// per k-step remains.  Interior tiles take unchecked loads and stores; edge
 // tiles check every element and read zeros outside the matrix.
 //
 // Persistent grid, XCD-aware: the units (tiles, requests in order, tiles of a
 // request row-major) are dealt to the 8 XCDs in contiguous blocks, so that
 // tiles sharing rows of A and columns of B share an L2.
 
-template <int BM, int BN, int BK, int WM, int WN, bool LATE, bool VEC>
+template <int BM, int BN, int BK, int WM, int WN, bool BT, bool VEC>
 __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) {
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 32, FN = TN / 32;
   constexpr int KH = BK / 2;
-  constexpr int ST = BK + 4;               // LDS row stride (floats) of As and Bs
-  constexpr int A4 = BM * BK / 4 / NT;     // float4 of A per thread per tile
-  constexpr int B4 = BK * BN / 4 / NT;     // 4-row column pieces of B per thread per tile
+  constexpr int AST = BK + 4;                      // LDS row stride of As
+  constexpr int BST = BT ? BK + 4 : BN + 4;        // LDS row stride of Bs
+  constexpr int A4 = BM * BK / 4 / NT;             // float4 of A per thread per tile
+  constexpr int B4 = BK * BN / 4 / NT;             // float4 of B per thread per tile
   static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile must be a multiple of 32");
   static_assert(KH % 4 == 0, "BK must be a multiple of 8");
   static_assert(A4 >= 1 && B4 >= 1 && A4 * NT * 4 == BM * BK && B4 * NT * 4 == BK * BN, "tile/threads mismatch");
 
-  __shared__ __attribute__((aligned(16))) float As[2][BM * ST];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BN * ST];
+  __shared__ __attribute__((aligned(16))) float As[2][BM * AST];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BT ? BN * BST : BK * BST];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -85,58 +89,56 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{0};
 
+    // 4 consecutive floats of row r from column c, or zeros outside n x n
+    auto row4 = [&](const float* M, int r, int c, bool fast) -> f32x4 {
+      const float* p = M + static_cast<size_t>(r) * n + c;
+      if (fast) {
+        if (VEC) return *reinterpret_cast<const f32x4*>(p);
+        return f32x4{p[0], p[1], p[2], p[3]};
+      }
+      f32x4 x = f32x4{0};
+      if (r < n) {
+        if (c + 0 < n) x.x = p[0];
+        if (c + 1 < n) x.y = p[1];
+        if (c + 2 < n) x.z = p[2];
+        if (c + 3 < n) x.w = p[3];
+      }
+      return x;
+    };
+
     f32x4 ra[A4], rb[B4];
     auto load_tile = [&](int k0) {
       const bool k_in = k0 + BK <= n;
-      if (rows_in && k_in) {
 #pragma unroll
-        for (int i = 0; i < A4; ++i) {
-          const int f = tid + i * NT;
-          const int r = f / (BK / 4), c = (f % (BK / 4)) * 4;
-          const float* p = A + static_cast<size_t>(row0 + r) * n + (k0 + c);
-          if (VEC) ra[i] = *reinterpret_cast<const f32x4*>(p);
-          else ra[i] = f32x4{p[0], p[1], p[2], p[3]};
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < A4; ++i) {
-          const int f = tid + i * NT;
-          const int r = f / (BK / 4), c = (f % (BK / 4)) * 4;
-          const int gr = row0 + r, gc = k0 + c;
-          f32x4 x = f32x4{0};
-          if (gr < n) {
-            const float* p = A + static_cast<size_t>(gr) * n;
-            if (gc + 0 < n) x.x = p[gc + 0];
-            if (gc + 1 < n) x.y = p[gc + 1];
-            if (gc + 2 < n) x.z = p[gc + 2];
-            if (gc + 3 < n) x.w = p[gc + 3];
-          }
-          ra[i] = x;
-        }
+      for (int i = 0; i < A4; ++i) {
+        const int f = tid + i * NT;
+        ra[i] = row4(A, row0 + f / (BK / 4), k0 + (f % (BK / 4)) * 4, rows_in && k_in);
       }
-      if (cols_in && k_in) {
+      if (BT) {
 #pragma unroll
-        for (int i = 0; i < B4; ++i) {
-          const int f = tid + i * NT;
-          const int c = f % BN, kq = f / BN;
-          const float* p = B + static_cast<size_t>(k0 + 4 * kq) * n + (col0 + c);
-          rb[i] = f32x4{p[0], p[n], p[2 * n], p[3 * n]};
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < B4; ++i) {
+        for (int i = 0; i < B4; ++i) {  // four k-rows of one column
           const int f = tid + i * NT;
           const int c = f % BN, kq = f / BN;
           const int gr = k0 + 4 * kq, gc = col0 + c;
-          f32x4 x = f32x4{0};
-          if (gc < n) {
-            const float* p = B + gc;
-            if (gr + 0 < n) x.x = p[static_cast<size_t>(gr + 0) * n];
-            if (gr + 1 < n) x.y = p[static_cast<size_t>(gr + 1) * n];
-            if (gr + 2 < n) x.z = p[static_cast<size_t>(gr + 2) * n];
-            if (gr + 3 < n) x.w = p[static_cast<size_t>(gr + 3) * n];
+          const float* p = B + static_cast<size_t>(gr) * n + gc;
+          if (cols_in && k_in) {
+            rb[i] = f32x4{p[0], p[n], p[2 * n], p[3 * n]};
+          } else {
+            f32x4 x = f32x4{0};
+            if (gc < n) {
+              if (gr + 0 < n) x.x = p[0];
+              if (gr + 1 < n) x.y = p[n];
+              if (gr + 2 < n) x.z = p[2 * static_cast<size_t>(n)];
+              if (gr + 3 < n) x.w = p[3 * static_cast<size_t>(n)];
+            }
+            rb[i] = x;
           }
-          rb[i] = x;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < B4; ++i) {  // four columns of one k-row
+          const int f = tid + i * NT;
+          rb[i] = row4(B, k0 + f / (BN / 4), col0 + (f % (BN / 4)) * 4, cols_in && k_in);
         }
       }
     };
@@ -145,13 +147,18 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
       for (int i = 0; i < A4; ++i) {
         const int f = tid + i * NT;
         const int r = f / (BK / 4), c = (f % (BK / 4)) * 4;
-        *reinterpret_cast<f32x4*>(&As[buf][r * ST + c]) = ra[i];
+        *reinterpret_cast<f32x4*>(&As[buf][r * AST + c]) = ra[i];
       }
 #pragma unroll
       for (int i = 0; i < B4; ++i) {
         const int f = tid + i * NT;
-        const int c = f % BN, kq = f / BN;
-        *reinterpret_cast<f32x4*>(&Bs[buf][c * ST + 4 * kq]) = rb[i];
+        if (BT) {
+          const int c = f % BN, kq = f / BN;
+          *reinterpret_cast<f32x4*>(&Bs[buf][c * BST + 4 * kq]) = rb[i];
+        } else {
+          const int r = f / (BN / 4), c = (f % (BN / 4)) * 4;
+          *reinterpret_cast<f32x4*>(&Bs[buf][r * BST + c]) = rb[i];
+        }
       }
     };
 
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
       float af[FM][KH], bf[FN][KH];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        const float* src = &As[buf][(wm * TM + i * 32 + li) * ST + lg * KH];
+        const float* src = &As[buf][(wm * TM + i * 32 + li) * AST + lg * KH];
 #pragma unroll
         for (int j = 0; j < KH; j += 4) {
           const f32x4 x = *reinterpret_cast<const f32x4*>(src + j);
@@ -175,24 +182,29 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
       }
 #pragma unroll
       for (int i = 0; i < FN; ++i) {
-        const float* src = &Bs[buf][(wn * TN + i * 32 + li) * ST + lg * KH];
+        if (BT) {
+          const float* src = &Bs[buf][(wn * TN + i * 32 + li) * BST + lg * KH];
 #pragma unroll
-        for (int j = 0; j < KH; j += 4) {
-          const f32x4 x = *reinterpret_cast<const f32x4*>(src + j);
-          bf[i][j] = x.x; bf[i][j + 1] = x.y; bf[i][j + 2] = x.z; bf[i][j + 3] = x.w;
+          for (int j = 0; j < KH; j += 4) {
+            const f32x4 x = *reinterpret_cast<const f32x4*>(src + j);
+            bf[i][j] = x.x; bf[i][j + 1] = x.y; bf[i][j + 2] = x.z; bf[i][j + 3] = x.w;
+          }
+        } else {
+          const float* src = &Bs[buf][(lg * KH) * BST + wn * TN + i * 32 + li];
+#pragma unroll
+          for (int j = 0; j < KH; ++j) bf[i][j] = src[j * BST];
         }
       }
 #pragma unroll
       for (int s = 0; s < KH; ++s) {
         // The other buffer was last read before the previous barrier.
-        if (!LATE && s == KH / 2 && more) store_tile(buf ^ 1);
+        if (s == KH / 2 && more) store_tile(buf ^ 1);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
       }
-      if (LATE && more) store_tile(buf ^ 1);
       __syncthreads();
     }
 
@@ -227,18 +239,20 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
 
 // Tile configurations.  Index order is part of the tuner table format.
 const GemmConfig kGemmConfigs[] = {
-    {0, 64, 64, 16, 2, 2, false},
-    {1, 128, 64, 16, 2, 2, false},
-    {2, 128, 128, 16, 2, 2, false},
-    {3, 128, 128, 32, 2, 2, false},
-    {4, 256, 128, 16, 4, 2, false},
-    {5, 128, 256, 16, 2, 4, false},
-    {6, 256, 128, 32, 4, 2, false},
-    {7, 64, 128, 16, 2, 2, false},
-    {8, 128, 128, 16, 2, 2, true},
-    {9, 256, 128, 16, 4, 2, true},
-    {10, 128, 256, 16, 2, 4, true},
-    {11, 256, 128, 32, 4, 2, true},
+    {0, 64, 64, 16, 2, 2, true},
+    {1, 128, 64, 16, 2, 2, true},
+    {2, 128, 128, 16, 2, 2, true},
+    {3, 128, 128, 32, 2, 2, true},
+    {4, 256, 128, 16, 4, 2, true},
+    {5, 128, 256, 16, 2, 4, true},
+    {6, 256, 128, 32, 4, 2, true},
+    {7, 64, 128, 16, 2, 2, true},
+    {8, 128, 128, 16, 2, 2, false},
+    {9, 256, 128, 16, 4, 2, false},
+    {10, 128, 256, 16, 2, 4, false},
+    {11, 256, 128, 32, 4, 2, false},
+    {12, 128, 128, 32, 2, 2, false},
+    {13, 64, 128, 16, 2, 2, false},
 };
 constexpr int kNumGemmConfigs = sizeof(kGemmConfigs) / sizeof(kGemmConfigs[0]);
 
@@ -246,14 +260,14 @@ int g_forced_config = -1;
 
 #include "gemm_tiles.inc"   // kTileTable: (n_max, config index) rows written by the tuner
 
-template <int BM, int BN, int BK, int WM, int WN, bool LATE>
+template <int BM, int BN, int BK, int WM, int WN, bool BT>
 hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap) {
   constexpr int NT = WM * WN * 64;
   int cap = grid_cap > 0 ? grid_cap : 256 * 2;
   int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
   if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
-  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, LATE, true>, grid, NT, s, g)
-             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, LATE, false>, grid, NT, s, g);
+  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, true>, grid, NT, s, g)
+             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, false>, grid, NT, s, g);
 }
 
 }  // namespace
@@ -293,18 +307,20 @@ hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s,
         (reinterpret_cast<uintptr_t>(g.d[i].B) & 15))
       vec = false;
   switch (config_idx) {
-    case 0: return launch_cfg<64, 64, 16, 2, 2, false>(g, vec, s, grid_cap);
-    case 1: return launch_cfg<128, 64, 16, 2, 2, false>(g, vec, s, grid_cap);
-    case 2: return launch_cfg<128, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
-    case 3: return launch_cfg<128, 128, 32, 2, 2, false>(g, vec, s, grid_cap);
-    case 4: return launch_cfg<256, 128, 16, 4, 2, false>(g, vec, s, grid_cap);
-    case 5: return launch_cfg<128, 256, 16, 2, 4, false>(g, vec, s, grid_cap);
-    case 6: return launch_cfg<256, 128, 32, 4, 2, false>(g, vec, s, grid_cap);
-    case 7: return launch_cfg<64, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
-    case 8: return launch_cfg<128, 128, 16, 2, 2, true>(g, vec, s, grid_cap);
-    case 9: return launch_cfg<256, 128, 16, 4, 2, true>(g, vec, s, grid_cap);
-    case 10: return launch_cfg<128, 256, 16, 2, 4, true>(g, vec, s, grid_cap);
-    case 11: return launch_cfg<256, 128, 32, 4, 2, true>(g, vec, s, grid_cap);
+    case 0: return launch_cfg<64, 64, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 1: return launch_cfg<128, 64, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 2: return launch_cfg<128, 128, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 3: return launch_cfg<128, 128, 32, 2, 2, true>(g, vec, s, grid_cap);
+    case 4: return launch_cfg<256, 128, 16, 4, 2, true>(g, vec, s, grid_cap);
+    case 5: return launch_cfg<128, 256, 16, 2, 4, true>(g, vec, s, grid_cap);
+    case 6: return launch_cfg<256, 128, 32, 4, 2, true>(g, vec, s, grid_cap);
+    case 7: return launch_cfg<64, 128, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 8: return launch_cfg<128, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
+    case 9: return launch_cfg<256, 128, 16, 4, 2, false>(g, vec, s, grid_cap);
+    case 10: return launch_cfg<128, 256, 16, 2, 4, false>(g, vec, s, grid_cap);
+    case 11: return launch_cfg<256, 128, 32, 4, 2, false>(g, vec, s, grid_cap);
+    case 12: return launch_cfg<128, 128, 32, 2, 2, false>(g, vec, s, grid_cap);
+    case 13: return launch_cfg<64, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }

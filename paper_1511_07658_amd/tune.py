@@ -9,9 +9,10 @@ compiled-in table ``csrc/gemm_tiles.inc`` (rows of {largest n, config}),
 so the tile choice stays a pure function of n: a rank's SGEMM result does
 not depend on what it is grouped with.
 
-    python -m paper_1511_07658_amd.tune [--sizes 256,512,...] [--group 8] [--reps 10] [--write]
+    python -m paper_1511_07658_amd.tune [--sizes 256,512,...] [--group 8] [--reps 10] [--write] [--json out.json]
+    python -m paper_1511_07658_amd.tune --from-json out.json     # table from a saved sweep
 
-Needs the GPU; rebuild the library after --write.
+Timing needs the GPU; rebuild the library after writing the table.
 """
 
 from __future__ import annotations
@@ -29,9 +30,11 @@ from . import workloads as wl
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "gemm_tiles.inc")
-NUM_CONFIGS = 12
-CONFIG_NAMES = ["64x64x16", "128x64x16", "128x128x16", "128x128x32", "256x128x16", "128x256x16", "256x128x32",
-                "64x128x16", "128x128x16L", "256x128x16L", "128x256x16L", "256x128x32L"]
+NUM_CONFIGS = 14
+# "T": B staged k-contiguous (transposed) in LDS; "R": B row-major in LDS
+CONFIG_NAMES = ["64x64x16T", "128x64x16T", "128x128x16T", "128x128x32T", "256x128x16T", "128x256x16T",
+                "256x128x32T", "64x128x16T", "128x128x16R", "256x128x16R", "128x256x16R", "256x128x32R",
+                "128x128x32R", "64x128x16R"]
 
 
 def _time_size(ns, n, group, reps, configs):
@@ -138,7 +141,15 @@ def main(argv=None):
     ap.add_argument("--configs", default=None)
     ap.add_argument("--write", action="store_true")
     ap.add_argument("--json", default=None)
+    ap.add_argument("--from-json", default=None,
+                    help="write the table from a saved sweep (the --json output of a run on the GPU) without timing")
     a = ap.parse_args(argv)
+    if a.from_json:
+        with open(a.from_json) as f:
+            saved = json.load(f)
+        write_table({int(n): r for n, r in saved.items()})
+        print(f"wrote {TABLE} from {a.from_json}; rebuild the library", file=sys.stderr)
+        return 0
     sizes = [int(s) for s in a.sizes.split(",")] if a.sizes else [64, 128, 192] + list(range(256, 2049, 64))
     configs = [int(c) for c in a.configs.split(",")] if a.configs else None
     res = tune(sizes, a.group, a.reps, configs)

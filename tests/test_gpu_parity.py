@@ -44,12 +44,13 @@ def hip_manager(name, **kw):
         G.gvm_shutdown()
 
 
-def run_ranks(ns, jobs_by_rank, zero_copy=False):
-    """Each rank (a thread) runs its job list; returns the per-rank results."""
+def run_ranks(ns, jobs_by_rank, zero_copy=False, barrier=None):
+    """Each rank (a thread) runs its job list; returns the per-rank results.
+    With `barrier`, every rank attaches before any submits."""
     out = [None] * len(jobs_by_rank)
 
     def body(r):
-        out[r] = spmd.rank_program(ns, r, jobs_by_rank[r], True, zero_copy)
+        out[r] = spmd.rank_program(ns, r, jobs_by_rank[r], True, zero_copy, barrier=barrier)
 
     ths = [threading.Thread(target=body, args=(r,)) for r in range(len(jobs_by_rank)) if jobs_by_rank[r]]
     for t in ths:
@@ -251,7 +252,8 @@ def test_ep_four_ranks_grouped_match_oracle(ns_name):
     # one grouped launch over four ranks' requests of 2^22 pairs
     n = 1 << 22
     with hip_manager(ns_name, nranks=4, policy=G.GVM_POLICY_GROUPED):
-        res = run_ranks(ns_name, [[(G.GVM_K_EP, 32, n, 0, False)] for _ in range(4)])
+        # all four attach before any submits, so the request barrier sees one batch
+        res = run_ranks(ns_name, [[(G.GVM_K_EP, 32, n, 0, False)] for _ in range(4)], barrier=threading.Barrier(4))
         for r in range(4):
             (o,) = check_ok(res[r])
             assert_ep(o, 32, r, n)

@@ -147,6 +147,35 @@ def test_batch_barrier_holds_until_all_ranks_submit(ns_name):
         G.gvm_detach(1)
 
 
+@pytest.mark.parametrize("timing", [0, 1])
+def test_large_requests_move_in_pieces(ns_name, timing):
+    # inputs of 10 and 18 pieces (4 MiB each, the last one short), outputs
+    # of 5 and 9; with batch_timing the copies are whole instead
+    sizes = [5_000_003, 9_000_001]
+    with Manager(ns_name, nranks=2, mode=G.GVM_MODE_SERVING, batch_timing=timing,
+                 shm_bytes_per_rank=(3 * max(sizes) + 8) * 4 + (1 << 20), hbm_budget_bytes=1 << 30):
+        errs = []
+
+        def rank(r):
+            assert G.gvm_attach_ns(ns_name, r) == 0
+            n = sizes[r]
+            inp = np.arange(2 * n, dtype=np.float32) * (r + 1)
+            out = np.zeros(n, np.float32)
+            for rep in range(2):
+                t = G.gvm_submit(r, G.GVM_K_VECADD, inp, out, n)
+                if t < 0 or G.gvm_wait(r, t, 20_000_000_000) != 0:
+                    errs.append((r, G.gvm_last_error()))
+                elif not np.array_equal(out, inp[:n]):
+                    errs.append((r, rep, "wrong bytes"))
+                out[:] = 0
+            assert G.gvm_detach(r) == 0
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(2)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+
+
 def test_batch_timing_enqueues_whole_batches(ns_name):
     # PS-2 with copies starts each rank's chain as its input lands; with
     # batch_timing a batch goes to the device as one launch (one span)
