@@ -442,6 +442,7 @@ def main(argv=None):
              "posted_to_seen", "rank_loop"],
             [round(float(x) * 1e-3, 2) for x in np.mean([r["parts_ns"] for r in rr], axis=0)])),
         "step_detail_us": step_detail(rr),
+        "manager_us": {"ring": stats.get("ring_us"), "batch_admit_lag": stats.get("batch_admit_lag_us")},
         "e2e_pcie": {"value": round(e2e_value, 3), "unit": unit, "steps": a.e2e_steps,
                      "ms_per_step": round(e2e / max(a.e2e_steps, 1) * 1e3, 3)},
         "plain": None if plain is None else {k: v for k, v in plain.items() if k != "digests"},

@@ -36,6 +36,12 @@ constexpr int kNumKernelIds = 6;  // kernel ids 1..5; index 0 collects mixed gra
 constexpr uint64_t kPieceBytes = 4ull << 20;   // one host copy chunk: each piece lands on one worker
 inline uint32_t piece_count(uint64_t bytes) { return static_cast<uint32_t>((bytes + kPieceBytes - 1) / kPieceBytes); }
 
+// A request whose copies total at most this many bytes keeps them on the
+// stream that runs its kernel: such a copy takes ~18 us on the link, less
+// than a dependency between two hardware queues costs (~15-20 us), and it
+// gains nothing from the copy FIFOs.
+constexpr uint64_t kLocalCopyBytes = 1ull << 20;
+
 // EP-like kernel: pairs per work unit, and the 64-bit words of one result
 // record (sx, sy, q[0..9]), the request's output and each unit's partial.
 constexpr uint64_t kEpUnit = 1ull << 15;

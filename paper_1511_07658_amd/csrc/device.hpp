@@ -40,6 +40,7 @@ struct Job {
   // Piecewise copies (kPieceBytes): the input's pieces go to the device as
   // each lands in the pinned staging, the output's pieces come back to shared
   // memory as each leaves the device.
+  bool local = false;            // small copies: on the kernel's own stream, whole
   bool pieces = false;
   uint32_t in_pieces = 0, in_sent = 0;                 // input pieces; those whose H2D is queued
   std::unique_ptr<std::atomic<int>[]> in_pending;      // host copy chunks in flight per input piece

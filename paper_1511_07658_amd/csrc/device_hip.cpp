@@ -180,8 +180,8 @@ class HipDevice final : public Device {
       hipStream_t c0 = compute_streams_[0];
       bool any_in = false, any_out = false;
       for (Job* j : jobs) {
-        any_in |= j->copy_in;
-        any_out |= j->copy_out;
+        any_in |= j->copy_in && (!j->local || policy == GVM_POLICY_PS1);
+        any_out |= j->copy_out && (!j->local || policy == GVM_POLICY_PS1);
       }
       if (any_in) span_streams.push_back(h2d_);
       if (any_out) span_streams.push_back(d2h_);
@@ -210,6 +210,13 @@ class HipDevice final : public Device {
         Job* j = jobs[i];
         hipStream_t s = rank_stream(j->rank);
         std::vector<Job*> one{j};
+        if (j->local) {  // small: the whole chain on the rank stream
+          rc = enqueue_in(j, s);
+          if (rc == GVM_OK) rc = enqueue_kernels(one, {s}, b, true, nullptr);
+          if (rc == GVM_OK) rc = enqueue_out(j, s);
+          if (rc == GVM_OK) rc = record_done(b, i, s);
+          continue;
+        }
         if (j->copy_in) {
           rc = enqueue_in(j, h2d_);
           if (rc == GVM_OK) rc = after(s, h2d_, b);
@@ -693,8 +700,6 @@ class HipDevice final : public Device {
   int enqueue_grouped(Batch* b, bool capture) {
     std::vector<Job*>& jobs = b->jobs;
     hipStream_t c0 = compute_streams_[0], c1 = compute_streams_[1];
-    bool any_in = false;
-    for (Job* j : jobs) any_in |= j->copy_in;
     if (capture) {
       hipEvent_t fork = sync_event(b);
       if (!fork) return GVM_EDEVICE;
@@ -703,13 +708,23 @@ class HipDevice final : public Device {
       HIPCHK(hipStreamWaitEvent(d2h_, fork, 0));
       HIPCHK(hipStreamWaitEvent(c1, fork, 0));
     }
-    // copy-ins in rank order on the host-to-device FIFO, then both compute
-    // streams wait for them
+    // copy-ins in rank order on the host-to-device FIFO (small ones on
+    // compute stream 0, ahead of its kernels), then both compute streams
+    // wait for the FIFO
+    bool fifo_in = false, local_in = false;
     for (Job* j : jobs) {
-      const int rc0 = enqueue_in(j, h2d_);
+      const int rc0 = enqueue_in(j, j->local ? c0 : h2d_);
       if (rc0 != GVM_OK) return rc0;
+      fifo_in |= j->copy_in && !j->local;
+      local_in |= j->copy_in && j->local;
     }
-    if (any_in) {
+    if (local_in && grouped_launches(jobs) > 1) {  // c1's kernels may need c0's local copies
+      hipEvent_t ev = sync_event(b);
+      if (!ev) return GVM_EDEVICE;
+      HIPCHK(hipEventRecord(ev, c0));
+      HIPCHK(hipStreamWaitEvent(c1, ev, 0));
+    }
+    if (fifo_in) {
       hipEvent_t ev = sync_event(b);
       if (!ev) return GVM_EDEVICE;
       HIPCHK(hipEventRecord(ev, h2d_));
@@ -732,14 +747,21 @@ class HipDevice final : public Device {
       HIPCHK(hipEventRecord(k[c], c == 0 ? c0 : c1));
     }
     // copy-outs in rank order on the device-to-host FIFO, each after the
-    // launch that computed it
+    // launch that computed it (small ones on that launch's own stream)
     int waited = -1;
     for (size_t i = 0; i < jobs.size(); ++i) {
       Job* j = jobs[i];
       hipEvent_t kev = k[stream_of[i]];
+      hipStream_t ks = stream_of[i] == 0 ? c0 : c1;
       if (!j->copy_out) {
         b->done[i] = kev;
-        if (!capture) track(b, kev, stream_of[i] == 0 ? c0 : c1);
+        if (!capture) track(b, kev, ks);
+        continue;
+      }
+      if (j->local) {
+        rc = enqueue_out(j, ks);
+        if (rc == GVM_OK && !capture) rc = record_done(b, i, ks);
+        if (rc != GVM_OK) return rc;
         continue;
       }
       if (waited != stream_of[i]) {

@@ -271,6 +271,10 @@ void Manager::on_message(int r, const Request& m) {
     return;
   }
   Queued q{seq_++, now_ns(), GVM_OK, m};
+  if (m.t_submit_ns && q.t_arrive_ns >= m.t_submit_ns) {
+    std::lock_guard<std::mutex> lk(stats_mu_);
+    if (ring_us_.size() < (1u << 20)) ring_us_.push_back((q.t_arrive_ns - m.t_submit_ns) * 1e-3);
+  }
   Layout lay;
   const uint64_t space = cfg_.shm_bytes_per_rank;
   if (!request_layout(static_cast<int>(m.kernel_id), m.n, &lay) || lay.in_bytes != m.in_bytes ||
@@ -533,8 +537,10 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   j->copy_in = copy_in;
   j->copy_out = copy_out;
   j->t_admit_ns = now_ns();
-  // whole copies only where a batch's device phase is timed as one span
-  j->pieces = !(cfg_.batch_timing && cfg_.mode == GVM_MODE_BATCH);
+  // small copies stay with the kernel; whole copies where a batch's device
+  // phase is timed as one span; pieces otherwise
+  j->local = (copy_in ? lay.in_bytes : 0) + (copy_out ? lay.out_bytes : 0) <= kLocalCopyBytes;
+  j->pieces = !j->local && !(cfg_.batch_timing && cfg_.mode == GVM_MODE_BATCH);
   if (j->pieces && copy_out) j->out_pieces = piece_count(lay.out_bytes);
   if (copy_in) {
     j->stage = kStageCopyIn;
@@ -597,7 +603,7 @@ bool Manager::schedule() {
   // Candidate heads in global arrival order.
   std::vector<std::pair<uint64_t, int>> heads;
   size_t live = 0;
-  uint64_t oldest = UINT64_MAX;
+  uint64_t oldest = UINT64_MAX, newest = 0;
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
     const RankRt& rt = ranks_[r];
     if (!rt.attached) continue;
@@ -605,6 +611,7 @@ bool Manager::schedule() {
     if (rt.running || rt.queue.empty()) continue;
     heads.emplace_back(rt.queue.front().seq, static_cast<int>(r));
     oldest = std::min(oldest, rt.queue.front().t_arrive_ns);
+    newest = std::max(newest, rt.queue.front().t_arrive_ns);
   }
   if (heads.empty()) return any;
   std::sort(heads.begin(), heads.end());
@@ -617,6 +624,10 @@ bool Manager::schedule() {
     const bool all = heads.size() >= live;
     const bool expired = now_ns() - oldest >= static_cast<uint64_t>(cfg_.batch_window_us) * 1000ull;
     if (!all && !expired) return any;
+    {
+      std::lock_guard<std::mutex> lk(stats_mu_);
+      if (batch_lag_us_.size() < (1u << 20)) batch_lag_us_.push_back((now_ns() - newest) * 1e-3);
+    }
     for (auto& h : heads) {
       Admit a = admit(h.second, jobs);
       if (a == kRejected) any = true;
@@ -690,8 +701,13 @@ int Manager::stats_json(std::string* out) {
     first = false;
   }
   s += "}";
-  snprintf(buf, sizeof(buf), ",\"admit_wait_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f,\"max\":%.3f}}", wait_us_.size(),
+  snprintf(buf, sizeof(buf), ",\"admit_wait_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f,\"max\":%.3f}", wait_us_.size(),
            pct(wait_us_, 50), pct(wait_us_, 99), pct(wait_us_, 100));
+  s += buf;
+  // submit -> drained from the ring; last request of a batch drained -> batch admitted
+  snprintf(buf, sizeof(buf), ",\"ring_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f},\"batch_admit_lag_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f}}",
+           ring_us_.size(), pct(ring_us_, 50), pct(ring_us_, 99), batch_lag_us_.size(), pct(batch_lag_us_, 50),
+           pct(batch_lag_us_, 99));
   s += buf;
   *out = s;
   return GVM_OK;
@@ -702,6 +718,8 @@ void Manager::reset_stats() {
   n_done_ = n_err_ = n_batches_ = 0;
   for (auto& v : lat_us_) v.clear();
   wait_us_.clear();
+  ring_us_.clear();
+  batch_lag_us_.clear();
   for (auto& k : kstats_) k = KernelStats{};
   peak_bytes_ = 0;
   timing_json_ = "{}";

@@ -109,6 +109,8 @@ class Manager {
   uint64_t n_done_ = 0, n_err_ = 0, n_batches_ = 0;
   std::vector<double> lat_us_[kNumKernelIds];      // submit -> result posted, per kernel id
   std::vector<double> wait_us_;        // submit -> admitted
+  std::vector<double> ring_us_;        // submit -> drained from the rank's ring
+  std::vector<double> batch_lag_us_;   // batch mode: last request drained -> batch admitted
   KernelStats kstats_[kNumKernelIds];
   uint64_t peak_bytes_ = 0;
   std::string timing_json_ = "{}";

@@ -27,6 +27,7 @@ import json
 import os
 import statistics
 import sys
+import threading
 import time
 
 import numpy as np
@@ -36,8 +37,10 @@ from . import spmd
 from . import workloads as wl
 
 
-def _rank(ns: str, n: int, reps: int, zero_copy: bool):
-    """Rank program: `reps` vector adds of length n; per-request turnaround (ns)."""
+def _rank(ns: str, n: int, warmup: int, reps: int, zero_copy: bool, barrier):
+    """Rank program: `warmup` untimed then `reps` timed vector adds of length
+    n (the manager's statistics are reset at the barrier in between);
+    per-request turnaround (ns) of the timed ones."""
     G.check(G.gvm_attach_ns(ns, 0), "attach")
     a, b = wl.vecadd_inputs(61, 0, n, 0)
     if zero_copy:
@@ -48,6 +51,11 @@ def _rank(ns: str, n: int, reps: int, zero_copy: bool):
     else:
         inb = np.concatenate([a, b])
         outb = np.empty(n, np.float32)
+    for _ in range(warmup):
+        t = G.check(G.gvm_submit(0, G.GVM_K_VECADD, inb, outb, n), "warm-up submit")
+        G.check(G.gvm_wait(0, t, 60_000_000_000), "warm-up wait")
+    barrier.wait()   # warm-up done
+    barrier.wait()   # statistics reset
     times = []
     for _ in range(reps):
         t0 = time.perf_counter_ns()
@@ -75,14 +83,21 @@ def run(sizes_mb, reps: int, warmup: int = 2, loopback: bool = False):
             n -= n % 4
             for mode in ("copy", "zero-copy"):
                 zc = mode == "zero-copy"
+                bar = spmd.context().Barrier(2)
+                box = {}
+                th = threading.Thread(target=lambda: box.update(r=spmd.run_processes(_rank, [(ns, n, warmup, reps, zc, bar)])[0]))
+                th.start()
+                bar.wait()
                 G.gvm_stats_reset()
-                res = spmd.run_processes(_rank, [(ns, n, warmup + reps, zc)])[0]
+                bar.wait()
+                th.join()
+                res = box["r"]
                 st = G.gvm_stats_json()
-                tt = [x / 1e3 for x in res["turnaround_ns"][warmup:]]
+                tt = [x / 1e3 for x in res["turnaround_ns"]]
                 tm = st["timing"]
                 ks = st["kernels"]["vecadd"]
                 turn = statistics.median(tt)
-                # means over all requests (the statistics include the warm-up)
+                # means over the timed requests
                 h2d = tm["h2d"]["ms"] * 1e3 / max(tm["h2d"]["count"], 1)
                 kern = ks["device_ms"] * 1e3 / max(ks["launches"], 1)
                 d2h = tm["d2h"]["ms"] * 1e3 / max(tm["d2h"]["count"], 1)
