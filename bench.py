@@ -50,12 +50,14 @@ PEAK_EP_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # plain 1 GiB copy (fetch x2.000, write x1.000); valid only for the kernel
 # sources they were taken on (sha256 over `sources` in csrc/, in order;
-# profiles/sgemm_grouped_8x1024.md).
+# profiles/sgemm_grouped_8x1024.md, profiles/blackscholes_grouped_16x4M.md).
 SGEMM_SOURCES = ("sgemm.hip", "group_device.hpp", "kernels.hpp", "gemm_tiles.inc")
 STREAM_SOURCES = ("stream_kernels.hip", "group_device.hpp", "kernels.hpp")
 MEASURED_TRAFFIC = {
-    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "",
-               "fetch_kib": 0.0, "fetch_factor": 2.000, "write_kib": 0.0, "write_factor": 1.000},
+    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "c0fed2cf09dea93cfa44c300047a25c4e21385462f7f721f563aec42d8314ae0",
+               "fetch_kib": 32831.4, "fetch_factor": 2.000, "write_kib": 32768.0, "write_factor": 1.000},
+    "bs16": {"sources": STREAM_SOURCES, "kernels_sha256": "df0b567041278f6cf6db25ae3edfbc52b6cdec68be8d0251b1de4a330e18b50b",
+             "fetch_kib": 393286.6, "fetch_factor": 2.000, "write_kib": 524288.5, "write_factor": 1.000},
 }
 
 
@@ -167,14 +169,20 @@ def bench_rank(ns, rank, kernel_id, n, cfg_idx, warmup, steps, e2e_steps, barrie
         seen = now
     t1 = clock(mono)
     barrier.wait()                       # 4: timed steps done
-    # PCIe-inclusive steps: copy-in from the rank's shared memory, copy-out back
+    # PCIe-inclusive steps: the input sits in the rank's shared memory
+    # (zero-copy region), the manager moves it to HBM and the result back
+    view = G.gvm_rank_buffer(rank, (x.size + out.size) * 4)
+    if view is None:
+        raise RuntimeError(f"rank {rank}: no zero-copy space: {G.gvm_last_error()}")
+    xin, oview = view[:x.size], view[x.size:x.size + out.size]
+    xin[:] = x
     barrier.wait()                       # 5: statistics read, go
     e0 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
     for _ in range(e2e_steps):
-        t = G.check(G.gvm_submit(rank, kernel_id, x, out, n), "e2e step")
+        t = G.check(G.gvm_submit(rank, kernel_id, xin, oview, n), "e2e step")
         G.check(G.gvm_wait(rank, t, 120_000_000_000), "e2e wait")
     e1 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
-    same = spmd.digest(out) == first
+    same = spmd.digest(oview if e2e_steps else out) == first
     G.gvm_detach(rank)
     return {"t0": t0, "t1": t1, "e0": e0, "e1": e1, "same_bytes": same, "digest": first,
             "parts_ns": [x / max(steps, 1) for x in parts], "stamps": stamps}
@@ -442,7 +450,8 @@ def main(argv=None):
              "posted_to_seen", "rank_loop"],
             [round(float(x) * 1e-3, 2) for x in np.mean([r["parts_ns"] for r in rr], axis=0)])),
         "step_detail_us": step_detail(rr),
-        "manager_us": {"ring": stats.get("ring_us"), "batch_admit_lag": stats.get("batch_admit_lag_us")},
+        "manager_us": {"ring": stats.get("ring_us"), "batch_admit_lag": stats.get("batch_admit_lag_us"),
+                       "busy_iteration": stats.get("busy_iteration_us")},
         "e2e_pcie": {"value": round(e2e_value, 3), "unit": unit, "steps": a.e2e_steps,
                      "ms_per_step": round(e2e / max(a.e2e_steps, 1) * 1e3, 3)},
         "plain": None if plain is None else {k: v for k, v in plain.items() if k != "digests"},

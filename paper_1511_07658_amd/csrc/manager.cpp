@@ -163,12 +163,26 @@ void Manager::service(std::promise<int>* ready) {
       dev_->reset_stats();
       arena_.reset_peak();
     }
+    const uint64_t t_it = now_ns();
     bool progress = drain_rings();
-    progress |= complete_jobs();
+    const bool done = complete_jobs();
+    const uint64_t t_done = now_ns();
+    progress |= done;
     check_liveness();
     progress |= schedule();
-    progress |= launch_ready();
+    const bool launched = launch_ready();
+    progress |= launched;
     if (progress) {
+      // time of service iterations that retired or launched work (the ring
+      // is not drained while they run)
+      if (done || launched) {
+        const uint64_t t_end = now_ns();
+        std::lock_guard<std::mutex> lk(stats_mu_);
+        if (iter_us_.size() < (1u << 20)) {
+          iter_us_.push_back((t_end - t_it) * 1e-3);
+          iter_done_us_.push_back((t_done - t_it) * 1e-3);
+        }
+      }
       spins = 0;
       idle_since = 0;
       continue;
@@ -705,9 +719,14 @@ int Manager::stats_json(std::string* out) {
            pct(wait_us_, 50), pct(wait_us_, 99), pct(wait_us_, 100));
   s += buf;
   // submit -> drained from the ring; last request of a batch drained -> batch admitted
-  snprintf(buf, sizeof(buf), ",\"ring_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f},\"batch_admit_lag_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f}}",
+  snprintf(buf, sizeof(buf), ",\"ring_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f},\"batch_admit_lag_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f}",
            ring_us_.size(), pct(ring_us_, 50), pct(ring_us_, 99), batch_lag_us_.size(), pct(batch_lag_us_, 50),
            pct(batch_lag_us_, 99));
+  s += buf;
+  // service iterations that retired or launched work: whole, and their completion part
+  snprintf(buf, sizeof(buf), ",\"busy_iteration_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f,\"max\":%.3f,\"completion_p50\":%.3f,\"completion_p99\":%.3f}}",
+           iter_us_.size(), pct(iter_us_, 50), pct(iter_us_, 99), pct(iter_us_, 100), pct(iter_done_us_, 50),
+           pct(iter_done_us_, 99));
   s += buf;
   *out = s;
   return GVM_OK;
@@ -720,6 +739,8 @@ void Manager::reset_stats() {
   wait_us_.clear();
   ring_us_.clear();
   batch_lag_us_.clear();
+  iter_us_.clear();
+  iter_done_us_.clear();
   for (auto& k : kstats_) k = KernelStats{};
   peak_bytes_ = 0;
   timing_json_ = "{}";

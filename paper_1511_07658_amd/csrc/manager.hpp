@@ -111,6 +111,8 @@ class Manager {
   std::vector<double> wait_us_;        // submit -> admitted
   std::vector<double> ring_us_;        // submit -> drained from the rank's ring
   std::vector<double> batch_lag_us_;   // batch mode: last request drained -> batch admitted
+  std::vector<double> iter_us_;        // service iterations that retired or launched work
+  std::vector<double> iter_done_us_;   // their complete_jobs part
   KernelStats kstats_[kNumKernelIds];
   uint64_t peak_bytes_ = 0;
   std::string timing_json_ = "{}";
