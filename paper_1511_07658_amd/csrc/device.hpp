@@ -81,8 +81,14 @@ class Device {
   // completion event at most once until the next round.
   virtual void begin_poll() {}
   // After query() == 1: release the device bookkeeping of the job (the
-  // result is in the pinned staging).
+  // result is in the pinned staging).  A batch whose last job finished is
+  // retired later, by flush_retired().
   virtual void finish(Job* j) = 0;
+  // Retire finished batches: read their device timings into the counters
+  // and recycle their events.  Returns true if any batch was retired.  The
+  // manager calls it while the device is busy or it is idle, so that this
+  // work never delays answering the ranks.
+  virtual bool flush_retired() { return false; }
   virtual void drain() = 0;
   virtual void close() = 0;
   virtual const KernelStats* kernel_stats() const = 0;  // indexed by kernel id (kNumKernelIds entries)

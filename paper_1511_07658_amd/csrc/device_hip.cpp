@@ -140,10 +140,13 @@ class HipDevice final : public Device {
     const size_t i = static_cast<size_t>(j->done_index);
     const auto& evs = b->out_ev[i];
     uint32_t& done = b->out_done[i];
+    // the events were tracked: their state is what the last polling round
+    // (begin_poll) saw, so no runtime call per job here
     while (done < evs.size()) {
-      const hipError_t e = hipEventQuery(evs[done]);
-      if (e == hipErrorNotReady) break;
-      if (e != hipSuccess) return fail(GVM_EDEVICE, "device-to-host copy failed: %s", hipGetErrorString(e));
+      auto it = b->state.find(evs[done]);
+      if (it == b->state.end() || (!it->second.done && it->second.err == hipErrorNotReady)) break;
+      if (!it->second.done)
+        return fail(GVM_EDEVICE, "device-to-host copy failed: %s", hipGetErrorString(it->second.err));
       ++done;
     }
     return static_cast<int>(done);
@@ -323,7 +326,14 @@ class HipDevice final : public Device {
   void finish(Job* j) override {
     auto* b = static_cast<Batch*>(j->batch);
     j->batch = nullptr;
-    if (b && --b->remaining == 0) retire(b);
+    if (b && --b->remaining == 0) retire_q_.push_back(b);
+  }
+
+  bool flush_retired() override {
+    if (retire_q_.empty()) return false;
+    for (Batch* b : retire_q_) retire(b);
+    retire_q_.clear();
+    return true;
   }
 
   void drain() override { (void)hipDeviceSynchronize(); }
@@ -347,6 +357,7 @@ class HipDevice final : public Device {
       delete b;
     }
     batches_.clear();
+    retire_q_.clear();
     for (auto& kv : graphs_) {
       (void)hipGraphExecDestroy(kv.second.exec);
       (void)hipGraphDestroy(kv.second.graph);
@@ -516,6 +527,7 @@ class HipDevice final : public Device {
       if (!e) return GVM_EDEVICE;
       HIPCHK(hipEventRecord(e, s));
       evs.push_back(e);
+      if (!capturing_) track(b, e, s);  // settled by the per-stream polling rounds
     }
     return GVM_OK;
   }
@@ -895,6 +907,7 @@ class HipDevice final : public Device {
   std::vector<hipStream_t> compute_streams_;
   hipStream_t h2d_ = nullptr, d2h_ = nullptr;  // copy FIFOs, one per direction
   std::map<const Job*, std::vector<TimedCopy>> pre_copies_;  // timed input pieces of jobs not yet launched
+  std::vector<Batch*> retire_q_;                              // finished batches not yet retired
   size_t next_cs_ = 0;
   struct FifoEntry {
     Batch* b;

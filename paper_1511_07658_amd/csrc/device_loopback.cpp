@@ -89,7 +89,15 @@ class LoopbackDevice final : public Device {
       ks.work_bytes += b;
     }
     if (cfg_.batch_timing) batch_us_.push_back((now_ns() - t_batch) * 1e-3);
+    counted_ = true;
     return GVM_OK;
+  }
+
+  // Counters are updated at launch; report them at the next flush.
+  bool flush_retired() override {
+    const bool c = counted_;
+    counted_ = false;
+    return c;
   }
 
   int stream_in(Job* j, uint64_t off, uint64_t bytes) override {
@@ -151,6 +159,7 @@ class LoopbackDevice final : public Device {
   }
 
   gvm_config cfg_{};
+  bool counted_ = false;            // counters changed since the last flush
   std::vector<double> batch_us_;
   double copy_ms_[2] = {0, 0}, copy_bytes_[2] = {0, 0};
   uint64_t copy_n_[2] = {0, 0};

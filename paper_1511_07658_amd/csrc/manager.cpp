@@ -5,6 +5,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <future>
@@ -160,8 +161,17 @@ void Manager::service(std::promise<int>* ready) {
   while (!stop_.load(std::memory_order_acquire)) {
     ctl_->heartbeat_ns.store(now_ns(), std::memory_order_relaxed);
     if (reset_pending_.exchange(false)) {
+      dev_->flush_retired();  // work before the reset stays out of the counters
       dev_->reset_stats();
       arena_.reset_peak();
+    }
+    if (flush_req_.exchange(false)) {
+      flush_deferred();
+      {
+        std::lock_guard<std::mutex> lk(flush_mu_);
+        ++flush_done_;
+      }
+      flush_cv_.notify_all();
     }
     const uint64_t t_it = now_ns();
     bool progress = drain_rings();
@@ -188,7 +198,9 @@ void Manager::service(std::promise<int>* ready) {
       continue;
     }
     if (inflight_ > 0) {
-      // device work outstanding: poll its events, yielding the core politely
+      // device work outstanding: retire finished batches meanwhile, then
+      // poll its events, yielding the core politely
+      flush_deferred();
       if (++spins < 64) _mm_pause(); else sched_yield();
       idle_since = 0;
       continue;
@@ -197,10 +209,13 @@ void Manager::service(std::promise<int>* ready) {
     // next request of a synchronous SPMD step is seen without a futex wake-up
     if (idle_since == 0) idle_since = now_ns();
     if (now_ns() - idle_since < spin_ns_) {
+      if (now_ns() - idle_since > 50000) flush_deferred();  // nothing arrived for 50 us
       _mm_pause();
       continue;
     }
-    // idle: sleep on the doorbell until a rank rings it (or a deadline)
+    // idle: retire what finished, then sleep on the doorbell until a rank
+    // rings it (or a deadline)
+    flush_deferred();
     int64_t timeout = 2000000;  // 2 ms: liveness checks and batch windows
     const uint32_t v = ctl_->bell.load(std::memory_order_acquire);
     ctl_->manager_sleeping.store(1, std::memory_order_seq_cst);
@@ -436,17 +451,19 @@ bool Manager::complete_jobs() {
     delete j;
     --inflight_;
     any = true;
-    if (!alive || (rt.attached && !pid_alive(rt.pid) && rt.pid != getpid())) reap_rank(r);
-  }
-  if (any) {
-    std::lock_guard<std::mutex> lk(stats_mu_);
-    const KernelStats* ks = dev_->kernel_stats();
-    for (int k = 0; k < kNumKernelIds; ++k) kstats_[k] = ks[k];
-    peak_bytes_ = std::max(peak_bytes_, arena_.peak());
-    if (cfg_.batch_timing) timing_json_ = dev_->timing_json();
+    if (!alive) reap_rank(r);  // a dead rank process is found by check_liveness()
   }
   if (cfg_.mode == GVM_MODE_BATCH && batch_open_ && inflight_ == 0) batch_open_ = false;
   return any;
+}
+
+void Manager::flush_deferred() {
+  if (!dev_->flush_retired()) return;
+  std::lock_guard<std::mutex> lk(stats_mu_);
+  const KernelStats* ks = dev_->kernel_stats();
+  for (int k = 0; k < kNumKernelIds; ++k) kstats_[k] = ks[k];
+  peak_bytes_ = std::max(peak_bytes_, arena_.peak());
+  if (cfg_.batch_timing) timing_json_ = dev_->timing_json();
 }
 
 // Launch admitted jobs whose inputs have reached the pinned staging.  A
@@ -692,6 +709,17 @@ double pct(std::vector<double> v, double p) {
 
 int Manager::stats_json(std::string* out) {
   if (!started_) return fail(GVM_ESTATE, "no manager runs in this process");
+  if (std::this_thread::get_id() != thread_.get_id()) {
+    // let the service thread retire finished batches first, so that the
+    // counters cover every request answered so far
+    std::unique_lock<std::mutex> fl(flush_mu_);
+    const uint64_t gen = flush_done_;
+    flush_req_.store(true, std::memory_order_release);
+    ctl_->bell.fetch_add(1, std::memory_order_seq_cst);
+    futex_wake_all(&ctl_->bell);
+    flush_cv_.wait_for(fl, std::chrono::milliseconds(200),
+                       [&] { return flush_done_ != gen || stop_.load(std::memory_order_acquire); });
+  }
   std::lock_guard<std::mutex> lk(stats_mu_);
   char buf[512];
   std::string s = "{";

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <atomic>
+#include <condition_variable>
 #include <cstdint>
 #include <deque>
 #include <future>
@@ -73,6 +74,7 @@ class Manager {
   bool drain_rings();
   void on_message(int r, const Request& m);
   bool complete_jobs();
+  void flush_deferred();           // retire finished batches, refresh the statistics
   bool schedule();
   bool launch_ready();
   Admit admit(int r, std::vector<Job*>& jobs);
@@ -101,6 +103,11 @@ class Manager {
   bool batch_open_ = false;        // batch mode: a batch is on the device
   uint64_t last_liveness_ns_ = 0;
   std::atomic<bool> reset_pending_{false};
+  // stats_json() asks the service thread to retire finished batches first
+  std::atomic<bool> flush_req_{false};
+  std::mutex flush_mu_;
+  std::condition_variable flush_cv_;
+  uint64_t flush_done_ = 0;        // guarded by flush_mu_
   std::string open_error_;
   uint64_t spin_ns_ = 200000;      // poll before sleeping once idle
 

@@ -216,6 +216,7 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--plain-procs", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-threads", type=int, default=8, help="manager threads for shm <-> pinned staging copies")
     ap.add_argument("--copy-api", action="store_true",
                     help="ranks pass private buffers (the API copies them) instead of building in shared memory")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
@@ -227,7 +228,7 @@ def main(argv=None):
     ctx = spmd.context()
     r32, v32 = float(np.float32(wl.BS_RATE)), float(np.float32(wl.BS_VOLATILITY))
     result = {"config": {"ranks": a.ranks, "rank_buffers": "copied by the API" if a.copy_api else "zero-copy in shm", "rate_req_s": a.rate, "duration_s": a.duration, "warmup_s": a.warmup,
-                         "budget_GiB": a.budget_gib, "kernels": "vecadd n<=2^24, Black-Scholes n<=4M, SGEMM n<=2048",
+                         "budget_GiB": a.budget_gib, "copy_threads": a.copy_threads, "kernels": "vecadd n<=2^24, Black-Scholes n<=4M, SGEMM n<=2048",
                          "requests_in_trace": sum(len(t) for t in traces)}}
 
     # plain first: this process must not touch the GPU before forking them
@@ -258,7 +259,7 @@ def main(argv=None):
     space = slot * 2 + (1 << 20)                          # two requests in flight per rank
     cfg = G.gvm_config_default(nranks=a.ranks, shm_bytes_per_rank=space, staging_bytes=(3 * MAX_VEC) * 4 + (1 << 20),
                                hbm_budget_bytes=int(a.budget_gib * (1 << 30)), mode=G.GVM_MODE_SERVING,
-                               policy=G.GVM_POLICY_AUTO, max_inflight=a.ranks, copy_threads=8, name=ns,
+                               policy=G.GVM_POLICY_AUTO, max_inflight=a.ranks, copy_threads=a.copy_threads, name=ns,
                                backend=G.GVM_BACKEND_LOOPBACK if a.loopback else G.GVM_BACKEND_HIP)
     start = ctx.Value("q", 0)
     bar = ctx.Barrier(a.ranks + 1)
