@@ -1,12 +1,71 @@
 #include "copy_pool.hpp"
 
+#include <emmintrin.h>
+#include <sys/resource.h>
+#include <sys/syscall.h>
+#include <unistd.h>
+
+#include <chrono>
+#include <cstdlib>
 #include <cstring>
 
 namespace gvm {
 
 namespace {
 constexpr size_t kChunk = size_t(4) << 20;
+constexpr size_t kStreamMin = size_t(256) << 10;  // smaller copies may stay in cache
+constexpr int kWorkerNice = 4;
+
+uint64_t mono_ns() {
+  return static_cast<uint64_t>(
+      std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch()).count());
+}
+
+// Copy with non-temporal 16-byte stores: the destination (pinned staging
+// read next by a DMA engine, or a rank's result area) is not read back by
+// this core, so the stores skip the read-for-ownership of every line and
+// leave the caches to the ranks.  Head and tail up to 16-byte alignment of
+// the destination go through memcpy.
+void stream_copy(char* dst, const char* src, size_t bytes) {
+  size_t head = (16 - (reinterpret_cast<uintptr_t>(dst) & 15)) & 15;
+  if (head > bytes) head = bytes;
+  memcpy(dst, src, head);
+  dst += head;
+  src += head;
+  bytes -= head;
+  const size_t body = bytes & ~size_t(63);
+  for (size_t i = 0; i < body; i += 64) {
+    const __m128i a = _mm_loadu_si128(reinterpret_cast<const __m128i*>(src + i));
+    const __m128i b = _mm_loadu_si128(reinterpret_cast<const __m128i*>(src + i + 16));
+    const __m128i c = _mm_loadu_si128(reinterpret_cast<const __m128i*>(src + i + 32));
+    const __m128i d = _mm_loadu_si128(reinterpret_cast<const __m128i*>(src + i + 48));
+    _mm_stream_si128(reinterpret_cast<__m128i*>(dst + i), a);
+    _mm_stream_si128(reinterpret_cast<__m128i*>(dst + i + 16), b);
+    _mm_stream_si128(reinterpret_cast<__m128i*>(dst + i + 32), c);
+    _mm_stream_si128(reinterpret_cast<__m128i*>(dst + i + 48), d);
+  }
+  _mm_sfence();  // the streamed lines are globally visible before the chunk is reported done
+  memcpy(dst + body, src + body, bytes - body);
+}
+
+bool stream_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("GVM_COPY_NT");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
 }  // namespace
+
+void CopyEngine::copy(char* dst, const char* src, size_t bytes) {
+  const uint64_t t0 = mono_ns();
+  if (bytes >= kStreamMin && stream_enabled())
+    stream_copy(dst, src, bytes);
+  else
+    memcpy(dst, src, bytes);
+  busy_ns_.fetch_add(mono_ns() - t0, std::memory_order_relaxed);
+  bytes_.fetch_add(bytes, std::memory_order_relaxed);
+}
 
 void CopyEngine::start(int nthreads) {
   stop();
@@ -27,13 +86,17 @@ void CopyEngine::stop() {
   threads_.clear();
   // anything still queued is copied here so that no waiter is left behind
   for (Chunk& c : queue_) {
-    memcpy(c.dst, c.src, c.bytes);
+    copy(c.dst, c.src, c.bytes);
     c.pending->fetch_sub(1, std::memory_order_acq_rel);
   }
   queue_.clear();
 }
 
 void CopyEngine::worker() {
+  // A lower scheduling weight than the service thread: when the host is
+  // oversubscribed the copies give way to the thread that drains the rings
+  // and launches work (raising a thread's nice value needs no privilege).
+  (void)setpriority(PRIO_PROCESS, static_cast<id_t>(syscall(SYS_gettid)), kWorkerNice);
   for (;;) {
     Chunk c;
     {
@@ -43,7 +106,7 @@ void CopyEngine::worker() {
       c = queue_.front();
       queue_.pop_front();
     }
-    memcpy(c.dst, c.src, c.bytes);
+    copy(c.dst, c.src, c.bytes);
     c.pending->fetch_sub(1, std::memory_order_acq_rel);
   }
 }
@@ -51,7 +114,7 @@ void CopyEngine::worker() {
 void CopyEngine::submit(void* dst, const void* src, size_t bytes, std::atomic<int>* pending) {
   if (bytes == 0) return;
   if (threads_.empty()) {
-    memcpy(dst, src, bytes);
+    copy(static_cast<char*>(dst), static_cast<const char*>(src), bytes);
     return;
   }
   const size_t n = (bytes + kChunk - 1) / kChunk;
@@ -63,8 +126,25 @@ void CopyEngine::submit(void* dst, const void* src, size_t bytes, std::atomic<in
       const size_t len = (off + kChunk <= bytes) ? kChunk : bytes - off;
       queue_.push_back(Chunk{static_cast<char*>(dst) + off, static_cast<const char*>(src) + off, len, pending});
     }
+    if (queue_.size() > max_queue_) max_queue_ = queue_.size();
   }
   if (n == 1) cv_.notify_one(); else cv_.notify_all();
+}
+
+CopyEngine::Stats CopyEngine::stats() {
+  Stats s;
+  s.bytes = bytes_.load(std::memory_order_relaxed);
+  s.busy_ns = busy_ns_.load(std::memory_order_relaxed);
+  std::lock_guard<std::mutex> lk(mu_);
+  s.max_queue = max_queue_;
+  return s;
+}
+
+void CopyEngine::reset_stats() {
+  bytes_.store(0, std::memory_order_relaxed);
+  busy_ns_.store(0, std::memory_order_relaxed);
+  std::lock_guard<std::mutex> lk(mu_);
+  max_queue_ = 0;
 }
 
 }  // namespace gvm

@@ -27,6 +27,15 @@ class CopyEngine {
   void submit(void* dst, const void* src, size_t bytes, std::atomic<int>* pending);
   int threads() const { return static_cast<int>(threads_.size()); }
 
+  // Bytes moved, summed time the workers spent copying, and the deepest
+  // the chunk queue has been, since the start or the last reset.
+  struct Stats {
+    uint64_t bytes = 0, busy_ns = 0;
+    size_t max_queue = 0;
+  };
+  Stats stats();
+  void reset_stats();
+
  private:
   struct Chunk {
     char* dst;
@@ -35,12 +44,15 @@ class CopyEngine {
     std::atomic<int>* pending;
   };
   void worker();
+  void copy(char* dst, const char* src, size_t bytes);
 
   std::vector<std::thread> threads_;
   std::mutex mu_;
   std::condition_variable cv_;
   std::deque<Chunk> queue_;
   bool stopping_ = false;
+  size_t max_queue_ = 0;
+  std::atomic<uint64_t> bytes_{0}, busy_ns_{0};
 };
 
 }  // namespace gvm

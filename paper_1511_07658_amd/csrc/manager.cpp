@@ -2,6 +2,8 @@
 
 #include <immintrin.h>
 #include <sched.h>
+#include <pthread.h>
+#include <time.h>
 #include <unistd.h>
 
 #include <algorithm>
@@ -141,6 +143,8 @@ int Manager::init(const gvm_config& cfg_in) {
     return rc;
   }
   started_ = true;
+  stats_t0_ns_ = now_ns();
+  stats_cpu0_ns_ = service_cpu_ns();
   return GVM_OK;
 }
 
@@ -752,12 +756,29 @@ int Manager::stats_json(std::string* out) {
            pct(batch_lag_us_, 99));
   s += buf;
   // service iterations that retired or launched work: whole, and their completion part
-  snprintf(buf, sizeof(buf), ",\"busy_iteration_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f,\"max\":%.3f,\"completion_p50\":%.3f,\"completion_p99\":%.3f}}",
+  snprintf(buf, sizeof(buf), ",\"busy_iteration_us\":{\"count\":%zu,\"p50\":%.3f,\"p99\":%.3f,\"max\":%.3f,\"completion_p50\":%.3f,\"completion_p99\":%.3f}",
            iter_us_.size(), pct(iter_us_, 50), pct(iter_us_, 99), pct(iter_us_, 100), pct(iter_done_us_, 50),
            pct(iter_done_us_, 99));
   s += buf;
+  // host side since the last reset: staging copies and the service thread's CPU time
+  const CopyEngine::Stats cs = copy_.stats();
+  const double wall = (now_ns() - stats_t0_ns_) * 1e-9;
+  snprintf(buf, sizeof(buf),
+           ",\"host\":{\"wall_s\":%.4f,\"copy_threads\":%d,\"copy_bytes\":%llu,\"copy_busy_s\":%.4f,\"copy_max_queue\":%zu,"
+           "\"service_cpu_s\":%.4f}}",
+           wall, copy_.threads(), (unsigned long long)cs.bytes, cs.busy_ns * 1e-9, cs.max_queue, (service_cpu_ns() - stats_cpu0_ns_) * 1e-9);
+  s += buf;
   *out = s;
   return GVM_OK;
+}
+
+uint64_t Manager::service_cpu_ns() const {
+  clockid_t cid;
+  timespec ts{};
+  if (!started_ || pthread_getcpuclockid(const_cast<std::thread&>(thread_).native_handle(), &cid) != 0 ||
+      clock_gettime(cid, &ts) != 0)
+    return 0;
+  return static_cast<uint64_t>(ts.tv_sec) * 1000000000ull + static_cast<uint64_t>(ts.tv_nsec);
 }
 
 void Manager::reset_stats() {
@@ -772,6 +793,9 @@ void Manager::reset_stats() {
   for (auto& k : kstats_) k = KernelStats{};
   peak_bytes_ = 0;
   timing_json_ = "{}";
+  copy_.reset_stats();
+  stats_t0_ns_ = now_ns();
+  stats_cpu0_ns_ = service_cpu_ns();
   // the device counters are reset on the service thread's next completion
   reset_pending_.store(true);
 }

@@ -110,9 +110,11 @@ class Manager {
   uint64_t flush_done_ = 0;        // guarded by flush_mu_
   std::string open_error_;
   uint64_t spin_ns_ = 200000;      // poll before sleeping once idle
+  uint64_t service_cpu_ns() const;  // CPU time of the service thread so far
 
   // statistics (guarded by stats_mu_)
   std::mutex stats_mu_;
+  uint64_t stats_t0_ns_ = 0, stats_cpu0_ns_ = 0;  // wall clock and service CPU time at the last reset
   uint64_t n_done_ = 0, n_err_ = 0, n_batches_ = 0;
   std::vector<double> lat_us_[kNumKernelIds];      // submit -> result posted, per kernel id
   std::vector<double> wait_us_;        // submit -> admitted

@@ -135,8 +135,13 @@ def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot
         if not pending:
             time.sleep(max(0.0, (t0 + int(trace[i][0] * 1e9) - now) * 1e-9))
             continue
-        # all slots busy: the arrival waits in the rank (its latency counts)
-        wait_ns = (t0 + int(trace[i][0] * 1e9) - now) if i < len(trace) else 60_000_000_000
+        # wait for a result; with a free slot only until the next arrival.
+        # With every slot busy a due arrival waits in the rank (its latency
+        # counts) and the rank blocks until a result frees a slot.
+        if i < len(trace) and (free_slots or not zero_copy):
+            wait_ns = t0 + int(trace[i][0] * 1e9) - now
+        else:
+            wait_ns = 60_000_000_000
         rc, t, ts = G.gvm_wait_any_timed(rank, max(wait_ns, 0))
         if rc == G.GVM_ETIMEDOUT:
             continue
@@ -216,7 +221,7 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--plain-procs", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--copy-threads", type=int, default=8, help="manager threads for shm <-> pinned staging copies")
+    ap.add_argument("--copy-threads", type=int, default=16, help="manager threads for shm <-> pinned staging copies")
     ap.add_argument("--copy-api", action="store_true",
                     help="ranks pass private buffers (the API copies them) instead of building in shared memory")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
@@ -276,9 +281,11 @@ def main(argv=None):
         th.start()
         bar.wait()
         G.gvm_stats_reset()
+        cpu0 = os.times()
         start.value = _now() + 200_000_000
         bar.wait()
         th.join()
+        cpu1 = os.times()
         stats = G.gvm_stats_json()
     finally:
         G.gvm_shutdown()
@@ -286,7 +293,11 @@ def main(argv=None):
     result["gvm"] = {**summarize(recs, a.warmup, a.duration), "peak_device_bytes": stats["peak_device_bytes"],
                      "admit_wait_us": stats["admit_wait_us"],
                      "device_ms": {k: v["device_ms"] for k, v in stats["kernels"].items()},
-                     "launches": {k: v["launches"] for k, v in stats["kernels"].items()}}
+                     "launches": {k: v["launches"] for k, v in stats["kernels"].items()},
+                     "ring_us": stats["ring_us"], "busy_iteration_us": stats["busy_iteration_us"],
+                     # CPU time of the manager's process (service thread, copy workers), whole run
+                     "host": {**stats["host"],
+                              "manager_process_cpu_s": round(cpu1.user + cpu1.system - cpu0.user - cpu0.system, 3)}}
     if "plain" in result and result["plain"]["p99_ms"] and result["gvm"]["p99_ms"]:
         result["p99_plain_over_gvm"] = round(result["plain"]["p99_ms"] / result["gvm"]["p99_ms"], 3)
         result["throughput_gvm_over_plain"] = round(result["gvm"]["throughput_req_s"] /
