@@ -97,6 +97,7 @@ int Manager::init(const gvm_config& cfg_in) {
   ctl_->generation.store(static_cast<uint32_t>(now_ns() & 0xffffffffu));
   ctl_->bell.store(0);
   ctl_->manager_sleeping.store(0);
+  ctl_->group_bell.store(0);
   ctl_->cfg = cfg;
   for (uint32_t r = 0; r < cfg.nranks; ++r) {
     RankSlot* s = new (ctl_slot(ctl_, r)) RankSlot();
@@ -180,12 +181,14 @@ void Manager::service(std::promise<int>* ready) {
     const uint64_t t_it = now_ns();
     bool progress = drain_rings();
     const bool done = complete_jobs();
+    wake_group();
     const uint64_t t_done = now_ns();
     progress |= done;
     check_liveness();
     progress |= schedule();
     const bool launched = launch_ready();
     progress |= launched;
+    wake_group();  // answers given while scheduling or launching
     if (progress) {
       // time of service iterations that retired or launched work (the ring
       // is not drained while they run)
@@ -260,6 +263,17 @@ void Manager::service(std::promise<int>* ready) {
     s->resp_bell.fetch_add(1);
     futex_wake_all(&s->resp_bell);
   }
+  ctl_->group_bell.fetch_add(1);
+  futex_wake_all(&ctl_->group_bell);
+}
+
+// One wake-up call for every rank that fell asleep on the group doorbell
+// since the last call (respond() only marks them).
+void Manager::wake_group() {
+  if (!group_wake_) return;
+  group_wake_ = false;
+  ctl_->group_bell.fetch_add(1, std::memory_order_seq_cst);
+  futex_wake_all(&ctl_->group_bell);
 }
 
 bool Manager::any_request_waiting() const {
@@ -347,7 +361,9 @@ void Manager::respond(int r, uint64_t ticket, uint32_t kernel_id, int status, co
   }
   std::atomic_thread_fence(std::memory_order_seq_cst);
   s->resp_bell.fetch_add(1, std::memory_order_seq_cst);
-  if (s->rank_sleeping.load(std::memory_order_seq_cst)) futex_wake_all(&s->resp_bell);
+  const uint32_t sleep = s->rank_sleeping.load(std::memory_order_seq_cst);
+  if (sleep == kSleepOwnBell) futex_wake_all(&s->resp_bell);
+  else if (sleep == kSleepGroupBell) group_wake_ = true;  // woken with the rest by wake_group()
   if (kernel_id >= GVM_K_VECADD && kernel_id <= GVM_K_EP) {
     std::lock_guard<std::mutex> lk(stats_mu_);
     if (status == GVM_OK) {
@@ -573,9 +589,10 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   j->copy_out = copy_out;
   j->t_admit_ns = now_ns();
   // small copies stay with the kernel; whole copies where a batch's device
-  // phase is timed as one span; pieces otherwise
+  // phase is timed as one span, or captured into a graph (a piece is
+  // enqueued when it lands, outside any capture); pieces otherwise
   j->local = (copy_in ? lay.in_bytes : 0) + (copy_out ? lay.out_bytes : 0) <= kLocalCopyBytes;
-  j->pieces = !j->local && !(cfg_.batch_timing && cfg_.mode == GVM_MODE_BATCH);
+  j->pieces = !j->local && !(cfg_.batch_timing && cfg_.mode == GVM_MODE_BATCH) && !cfg_.use_graphs;
   if (j->pieces && copy_out) j->out_pieces = piece_count(lay.out_bytes);
   if (copy_in) {
     j->stage = kStageCopyIn;

@@ -111,6 +111,8 @@ class Manager {
   std::string open_error_;
   uint64_t spin_ns_ = 200000;      // poll before sleeping once idle
   uint64_t service_cpu_ns() const;  // CPU time of the service thread so far
+  void wake_group();
+  bool group_wake_ = false;        // a rank asleep on the group doorbell was answered
 
   // statistics (guarded by stats_mu_)
   std::mutex stats_mu_;

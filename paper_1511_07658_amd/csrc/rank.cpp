@@ -186,14 +186,18 @@ int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
       for (int i = 0; i < 32; ++i) _mm_pause();
       continue;
     }
-    const uint32_t v = h.slot->resp_bell.load(std::memory_order_acquire);
-    h.slot->rank_sleeping.store(1, std::memory_order_seq_cst);
+    // batch mode: sleep on the shared group doorbell (one wake-up call per
+    // answered batch); serving mode: on the rank's own doorbell
+    const bool group = hdr->cfg.mode == GVM_MODE_BATCH;
+    std::atomic<uint32_t>* bell = group ? &hdr->group_bell : &h.slot->resp_bell;
+    const uint32_t v = bell->load(std::memory_order_acquire);
+    h.slot->rank_sleeping.store(group ? kSleepGroupBell : kSleepOwnBell, std::memory_order_seq_cst);
     std::atomic_thread_fence(std::memory_order_seq_cst);
     if (h.slot->resp.empty()) {
       uint64_t left = deadline - now;
-      futex_wait(&h.slot->resp_bell, v, static_cast<int64_t>(std::min<uint64_t>(left, 50000000ull)));
+      futex_wait(bell, v, static_cast<int64_t>(std::min<uint64_t>(left, 50000000ull)));
     }
-    h.slot->rank_sleeping.store(0, std::memory_order_relaxed);
+    h.slot->rank_sleeping.store(kAwake, std::memory_order_relaxed);
   }
 }
 

@@ -20,7 +20,7 @@
 namespace gvm {
 
 constexpr uint64_t kMagic = 0x31564d47534d5647ull;  // "GVMSGMV1"
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr uint32_t kRingCap = 64;  // entries, power of two
 constexpr int kMaxRanks = 256;
 
@@ -87,12 +87,15 @@ struct Ring {
   }
 };
 
+// What a rank waiting for a response is doing (RankSlot::rank_sleeping).
+enum RankSleep : uint32_t { kAwake = 0, kSleepOwnBell = 1, kSleepGroupBell = 2 };
+
 struct RankSlot {
   alignas(64) std::atomic<uint32_t> state;   // SlotState
   std::atomic<int32_t> pid;                  // owning process
   std::atomic<uint32_t> epoch;               // bumped by every attach
   alignas(64) std::atomic<uint32_t> resp_bell;      // futex: manager -> rank
-  std::atomic<uint32_t> rank_sleeping;
+  std::atomic<uint32_t> rank_sleeping;       // kAwake, kSleepOwnBell or kSleepGroupBell
   Ring<Request> req;                         // rank -> manager
   Ring<Response> resp;                       // manager -> rank
 };
@@ -109,6 +112,10 @@ struct CtlHeader {
   std::atomic<uint64_t> heartbeat_ns;
   alignas(64) std::atomic<uint32_t> bell;    // futex: ranks -> manager
   std::atomic<uint32_t> manager_sleeping;
+  // futex: manager -> every rank that sleeps on it.  In batch mode the ranks
+  // of a batch are answered together, so they sleep on this one word and a
+  // single wake-up call reaches all of them.
+  alignas(64) std::atomic<uint32_t> group_bell;
   alignas(64) gvm_config cfg;
 };
 
