@@ -1,6 +1,6 @@
 """Benchmark of the GVM hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sgemm8|vecadd4|bs16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sgemm8|vecadd4|vecadd16|bs16|ep8|mixed32]
 
 Default workload (the configuration the headline metric is quoted on): 8 SPMD
 rank processes, each an FP32 square GEMM C = A B with 1024 x 1024 A, B ~ N(0,1)
@@ -50,14 +50,17 @@ PEAK_EP_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # plain 1 GiB copy (fetch x2.000, write x1.000); valid only for the kernel
 # sources they were taken on (sha256 over `sources` in csrc/, in order;
-# profiles/sgemm_grouped_8x1024.md, profiles/blackscholes_grouped_16x4M.md).
+# profiles/sgemm_grouped_8x1024.md, profiles/blackscholes_grouped_16x4M.md,
+# profiles/vecadd_grouped_16x16M.md).
 SGEMM_SOURCES = ("sgemm.hip", "group_device.hpp", "kernels.hpp", "gemm_tiles.inc")
 STREAM_SOURCES = ("stream_kernels.hip", "group_device.hpp", "kernels.hpp")
 MEASURED_TRAFFIC = {
-    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "c0fed2cf09dea93cfa44c300047a25c4e21385462f7f721f563aec42d8314ae0",
+    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "00945b23a0f80c663fec083c50416b4742dacfd223d121907ff1b8d58b902ade",
                "fetch_kib": 32831.4, "fetch_factor": 2.000, "write_kib": 32768.0, "write_factor": 1.000},
-    "bs16": {"sources": STREAM_SOURCES, "kernels_sha256": "df0b567041278f6cf6db25ae3edfbc52b6cdec68be8d0251b1de4a330e18b50b",
-             "fetch_kib": 393286.6, "fetch_factor": 2.000, "write_kib": 524288.5, "write_factor": 1.000},
+    "bs16": {"sources": STREAM_SOURCES, "kernels_sha256": "b6e37850a81652cdfbfcb6ef5733e38694e16acd5b1e2a7223c8bda01e96637c",
+             "fetch_kib": 393326.6, "fetch_factor": 2.000, "write_kib": 524311.7, "write_factor": 1.000},
+    "vecadd16": {"sources": STREAM_SOURCES, "kernels_sha256": "b6e37850a81652cdfbfcb6ef5733e38694e16acd5b1e2a7223c8bda01e96637c",
+                 "fetch_kib": 1048597.1, "fetch_factor": 2.000, "write_kib": 1048576.0, "write_factor": 1.000},
 }
 
 
@@ -82,6 +85,8 @@ def measured_traffic(workload):
 WORKLOADS = {
     "sgemm8": "8 ranks via GVM, FP32 SGEMM 1024x1024 each, grouped MFMA launch, inputs resident in HBM",
     "vecadd4": "4 ranks via GVM, FP32 vector add n=2^20 each, inputs resident in HBM",
+    "vecadd16": "16 ranks via GVM, FP32 vector add n=2^24 each (3.2 GB per step, beyond the memory-side cache), "
+                "one grouped launch, inputs resident in HBM",
     "bs16": "16 ranks via GVM, FP32 Black-Scholes 4M options each, one fused launch, inputs resident in HBM",
     "mixed32": "32 ranks via GVM with uneven sizes: 16 vector adds n=floor(2^U[16,24]) and 16 SGEMMs "
                "n in {256..2048 step 64}, tuned tiles, one grouped launch per kernel per step, inputs resident in HBM",
@@ -96,6 +101,8 @@ def rank_specs(workload):
         return [(G.GVM_K_SGEMM, 1024, 1)] * 8
     if workload == "vecadd4":
         return [(G.GVM_K_VECADD, 1 << 20, 0)] * 4
+    if workload == "vecadd16":
+        return [(G.GVM_K_VECADD, 1 << 24, 0)] * 16
     if workload == "bs16":
         return [(G.GVM_K_BLACKSCHOLES, 4 << 20, 2)] * 16
     if workload == "ep8":

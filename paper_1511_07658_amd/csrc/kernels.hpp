@@ -98,7 +98,8 @@ int gemm_config_for(uint64_t n);
 void gemm_config_force(int idx);
 
 constexpr uint64_t kVecUnit = 4096;   // elements per vector work unit
-constexpr uint64_t kBsUnit = 2048;    // options per Black-Scholes work unit
+constexpr uint64_t kBsUnit = 4096;    // options per Black-Scholes work unit (the launcher
+                                      // recounts the units for its launch shape)
 
 // Persistent-grid launchers.  `grid_cap` bounds the number of workgroups
 // (0 = default for the kernel).  Return hipSuccess or the launch error.

@@ -1,6 +1,9 @@
 // Device ceilings of the MI355X the GVM runs on:
 //   copy   <MiB> <reps>   plain device-to-device copy kernel (HBM read+write rate;
 //                         also the reference kernel for scaling FETCH_SIZE/WRITE_SIZE)
+//   stream <M floats>     the Black-Scholes access mix (three input streams, two
+//                         output streams) and its read-only and write-only halves,
+//                         over float4s per thread, grid and cache policy
 //   mfma   <iters>        FP32 MFMA issue rate (v_mfma_f32_32x32x2_f32 chains)
 //   pcie   <MiB>          pinned host<->device copy rates, one direction and both
 //   hostcopy <MiB>        CPU memcpy pageable <-> pinned, 1 and 8 threads
@@ -17,6 +20,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #define CK(x)                                                                          \
@@ -52,6 +56,81 @@ __global__ __launch_bounds__(256) void copy_var_kernel(const f32x4* __restrict__
       const size_t i = base + u * 256ull;
       if (i < n4) {
         if (NT) __builtin_nontemporal_store(v[u], dst + i); else dst[i] = v[u];
+      }
+    }
+  }
+}
+
+template <bool NT>
+__device__ __forceinline__ f32x4 ld4(const f32x4* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void st4(f32x4 v, f32x4* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Three streams in, two out (o1 = a + b, o2 = b + c): Black-Scholes' 12 B
+// read and 8 B written per element without its arithmetic.  U float4 per
+// thread per round, grid-stride.
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void mix32_kernel(const f32x4* __restrict__ a, const f32x4* __restrict__ b,
+                                                    const f32x4* __restrict__ c, f32x4* __restrict__ o1,
+                                                    f32x4* __restrict__ o2, size_t n4) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * 256ull * U;
+  for (size_t base = blockIdx.x * 256ull * U + threadIdx.x; base < n4; base += stride) {
+    f32x4 va[U], vb[U], vc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = base + u * 256ull;
+      if (i < n4) {
+        va[u] = ld4<NT>(a + i);
+        vb[u] = ld4<NT>(b + i);
+        vc[u] = ld4<NT>(c + i);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = base + u * 256ull;
+      if (i < n4) {
+        st4<NT>(va[u] + vb[u], o1 + i);
+        st4<NT>(vb[u] + vc[u], o2 + i);
+      }
+    }
+  }
+}
+
+// Read half: three streams summed per thread, one float per thread written.
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void read3_kernel(const f32x4* __restrict__ a, const f32x4* __restrict__ b,
+                                                    const f32x4* __restrict__ c, float* __restrict__ sink, size_t n4) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * 256ull * U;
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (size_t base = blockIdx.x * 256ull * U + threadIdx.x; base < n4; base += stride) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = base + u * 256ull;
+      if (i < n4) acc += ld4<NT>(a + i) + ld4<NT>(b + i) + ld4<NT>(c + i);
+    }
+  }
+  sink[blockIdx.x * 256ull + threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
+}
+
+// Write half: two streams written from the index.
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void write2_kernel(f32x4* __restrict__ o1, f32x4* __restrict__ o2, size_t n4) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * 256ull * U;
+  for (size_t base = blockIdx.x * 256ull * U + threadIdx.x; base < n4; base += stride) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = base + u * 256ull;
+      if (i < n4) {
+        const float f = static_cast<float>(i);
+        st4<NT>(f32x4{f, f, f, f}, o1 + i);
+        st4<NT>(f32x4{f, -f, f, -f}, o2 + i);
       }
     }
   }
@@ -178,6 +257,67 @@ int main(int argc, char** argv) {
     }
     CK(hipFree(src));
     CK(hipFree(dst));
+  } else if (what == "stream") {
+    // five arrays of n floats (default 64 M each: 1.34 GB moved by the mix
+    // kernel, like sixteen 4M-option Black-Scholes requests)
+    const size_t n = size_t(argc > 2 ? strtoull(argv[2], nullptr, 10) : 64) << 20;
+    const size_t n4 = n / 4;
+    f32x4* buf[5];
+    for (auto& b : buf) {
+      CK(hipMalloc(&b, n * sizeof(float)));
+      CK(hipMemset(b, 0, n * sizeof(float)));
+    }
+    const int max_grid = static_cast<int>((n4 + 255) / 256);
+    float* sink;
+    CK(hipMalloc(&sink, static_cast<size_t>(max_grid) * 256 * sizeof(float)));
+    auto timeit = [&](auto launch) {
+      launch();
+      CK(hipDeviceSynchronize());
+      float best = 1e30f, total = 0.0f;
+      for (int r = 0; r < 5; ++r) {
+        CK(hipEventRecord(e0));
+        launch();
+        CK(hipEventRecord(e1));
+        CK(hipEventSynchronize(e1));
+        float ms;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+        total += ms;
+      }
+      return std::make_pair(best, total / 5);
+    };
+    auto report = [&](const char* kind, int u, bool nt, int grid, double bytes, std::pair<float, float> t) {
+      printf("{\"test\":\"stream\",\"kind\":\"%s\",\"u\":%d,\"nt\":%d,\"grid\":%d,\"bytes\":%.0f,"
+             "\"best_us\":%.2f,\"best_GBps\":%.1f,\"avg_GBps\":%.1f}\n",
+             kind, u, nt ? 1 : 0, grid, bytes, t.first * 1e3, bytes / (t.first * 1e-3) / 1e9, bytes / (t.second * 1e-3) / 1e9);
+    };
+    auto sweep = [&](auto u_tag, auto nt_tag) {
+      constexpr int U = decltype(u_tag)::value;
+      constexpr bool NT = decltype(nt_tag)::value;
+      const int full = static_cast<int>((n4 + 256ull * U - 1) / (256ull * U));
+      for (int grid : {256, 512, 1024, 2048, 4096, full}) {
+        if (grid > full) continue;
+        report("mix3r2w", U, NT, grid, 20.0 * n, timeit([&] {
+          hipLaunchKernelGGL((mix32_kernel<U, NT>), dim3(grid), dim3(256), 0, nullptr, buf[0], buf[1], buf[2], buf[3], buf[4], n4);
+        }));
+        report("read3", U, NT, grid, 12.0 * n, timeit([&] {
+          hipLaunchKernelGGL((read3_kernel<U, NT>), dim3(grid), dim3(256), 0, nullptr, buf[0], buf[1], buf[2], sink, n4);
+        }));
+        report("write2", U, NT, grid, 8.0 * n, timeit([&] {
+          hipLaunchKernelGGL((write2_kernel<U, NT>), dim3(grid), dim3(256), 0, nullptr, buf[3], buf[4], n4);
+        }));
+      }
+    };
+    using F = std::false_type;
+    using T = std::true_type;
+    sweep(std::integral_constant<int, 1>{}, F{});
+    sweep(std::integral_constant<int, 1>{}, T{});
+    sweep(std::integral_constant<int, 2>{}, F{});
+    sweep(std::integral_constant<int, 2>{}, T{});
+    sweep(std::integral_constant<int, 4>{}, F{});
+    sweep(std::integral_constant<int, 4>{}, T{});
+    for (auto& b : buf) CK(hipFree(b));
+    CK(hipFree(sink));
   } else if (what == "mfma") {
     const int iters = argc > 2 ? atoi(argv[2]) : 20000;
     const int blocks = p.multiProcessorCount * 8;

@@ -18,13 +18,17 @@ namespace gvm {
 
 namespace {
 
-// Launch shapes measured on the MI355X (grid x {cached, non-temporal} sweep
-// of the grouped launches): vector ops 1024 workgroups, Black-Scholes 512.
-// A group whose bytes exceed the 256 MB memory-side cache streams through
-// with non-temporal loads and stores; a smaller one stays cacheable, since
-// its inputs come back from that cache on the next request.
-constexpr int kVecGrid = 1024;
-constexpr int kBsGrid = 512;
+// Launch shapes measured on the MI355X (sweeps of grid, float4 per thread
+// and cache policy over the grouped launches): one workgroup per work unit
+// beats every persistent grid (512 to 4096 workgroups) for groups beyond the
+// memory-side cache, since the dispatcher keeps every SIMD at its register-
+// limited occupancy and balances the tail; for small groups the two
+// coincide.  A group whose bytes exceed the 256 MB memory-side cache
+// streams through with non-temporal loads and stores; a smaller one stays
+// cacheable, since its inputs come back from that cache on the next request.
+constexpr int kVecGrid = 1 << 24;     // i.e. one workgroup per unit
+constexpr int kBsGrid = 1 << 24;
+constexpr int kBsV4 = 4;              // float4 per thread per stream of a Black-Scholes unit
 constexpr uint64_t kMallBytes = 256ull << 20;
 
 // ---------------------------------------------------------------- vectors
@@ -118,51 +122,82 @@ __device__ __forceinline__ void bs_price(float S, float K, float T, float r, flo
   put = kd * (1.0f - n2) - S * (1.0f - n1);
 }
 
-template <bool NT>
+// Registers of one work unit: V4 float4 per thread of each input stream
+// (V4 * 1024 options per unit of 256 threads).
+template <int V4>
+struct BsUnitRegs {
+  f32x4 s[V4], k[V4], t[V4];
+};
+
+// Locate unit u and, when it is full and its streams are 16-byte aligned,
+// issue its loads; a ragged or unaligned unit returns false and is left to
+// the element-wise path.
+template <int V4, bool NT>
+__device__ __forceinline__ bool bs_load(const BsGroup& g, uint64_t u, int& q, uint64_t& e0, BsUnitRegs<V4>& x) {
+  constexpr uint64_t kUnit = V4 * 4 * kThreads;
+  q = find_request(g, u);
+  const BsDesc& d = g.d[q];
+  e0 = (u - d.unit_begin) * kUnit;
+  const uint64_t e1 = min(e0 + kUnit, d.n);
+  const bool aligned = ((reinterpret_cast<uintptr_t>(d.S) | reinterpret_cast<uintptr_t>(d.K) |
+                         reinterpret_cast<uintptr_t>(d.T) | reinterpret_cast<uintptr_t>(d.call) |
+                         reinterpret_cast<uintptr_t>(d.put)) & 15) == 0;
+  if (!aligned || e1 - e0 != kUnit) return false;
+  const f32x4* S4 = reinterpret_cast<const f32x4*>(d.S + e0);
+  const f32x4* K4 = reinterpret_cast<const f32x4*>(d.K + e0);
+  const f32x4* T4 = reinterpret_cast<const f32x4*>(d.T + e0);
+#pragma unroll
+  for (int j = 0; j < V4; ++j) {
+    x.s[j] = stream_load<f32x4, NT>(S4 + threadIdx.x + j * kThreads);
+    x.k[j] = stream_load<f32x4, NT>(K4 + threadIdx.x + j * kThreads);
+    x.t[j] = stream_load<f32x4, NT>(T4 + threadIdx.x + j * kThreads);
+  }
+  return true;
+}
+
+template <int V4, bool NT>
+__device__ __forceinline__ void bs_price_store(const BsDesc& d, uint64_t e0, const BsUnitRegs<V4>& x, float r,
+                                               float v, float half_v2) {
+  f32x4* C4 = reinterpret_cast<f32x4*>(d.call + e0);
+  f32x4* P4 = reinterpret_cast<f32x4*>(d.put + e0);
+#pragma unroll
+  for (int j = 0; j < V4; ++j) {
+    float c0, c1, c2, c3, p0, p1, p2, p3;
+    bs_price(x.s[j].x, x.k[j].x, x.t[j].x, r, v, half_v2, c0, p0);
+    bs_price(x.s[j].y, x.k[j].y, x.t[j].y, r, v, half_v2, c1, p1);
+    bs_price(x.s[j].z, x.k[j].z, x.t[j].z, r, v, half_v2, c2, p2);
+    bs_price(x.s[j].w, x.k[j].w, x.t[j].w, r, v, half_v2, c3, p3);
+    const f32x4 c = {c0, c1, c2, c3};
+    const f32x4 p = {p0, p1, p2, p3};
+    stream_store<f32x4, NT>(c, C4 + threadIdx.x + j * kThreads);
+    stream_store<f32x4, NT>(p, P4 + threadIdx.x + j * kThreads);
+  }
+}
+
+// Ragged or unaligned unit: one option per thread and step.
+template <int V4>
+__device__ __forceinline__ void bs_unit_elementwise(const BsDesc& d, uint64_t e0, float r, float v, float half_v2) {
+  constexpr uint64_t kUnit = V4 * 4 * kThreads;
+  const uint64_t e1 = min(e0 + kUnit, d.n);
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+    float c, p;
+    bs_price(d.S[e], d.K[e], d.T[e], r, v, half_v2, c, p);
+    d.call[e] = c;
+    d.put[e] = p;
+  }
+}
+
+// V4: float4 per thread of each stream per unit.  Every option is priced by
+// the same code whatever the shape or the group.
+template <int V4, bool NT>
 __global__ __launch_bounds__(kThreads) void bs_group_kernel(BsGroup g) {
-  constexpr int kV4 = kBsUnit / 4 / kThreads;
   const float r = g.rate, v = g.volatility, half_v2 = 0.5f * g.volatility * g.volatility;
   for (uint64_t u = blockIdx.x; u < g.total_units; u += gridDim.x) {
-    const int q = find_request(g, u);
-    const BsDesc& d = g.d[q];
-    const uint64_t e0 = (u - d.unit_begin) * kBsUnit;
-    const uint64_t e1 = min(e0 + kBsUnit, d.n);
-    const bool aligned = ((reinterpret_cast<uintptr_t>(d.S) | reinterpret_cast<uintptr_t>(d.K) |
-                           reinterpret_cast<uintptr_t>(d.T) | reinterpret_cast<uintptr_t>(d.call) |
-                           reinterpret_cast<uintptr_t>(d.put)) & 15) == 0;
-    if (aligned && e1 - e0 == kBsUnit) {
-      const f32x4* S4 = reinterpret_cast<const f32x4*>(d.S + e0);
-      const f32x4* K4 = reinterpret_cast<const f32x4*>(d.K + e0);
-      const f32x4* T4 = reinterpret_cast<const f32x4*>(d.T + e0);
-      f32x4* C4 = reinterpret_cast<f32x4*>(d.call + e0);
-      f32x4* P4 = reinterpret_cast<f32x4*>(d.put + e0);
-      f32x4 s[kV4], k[kV4], t[kV4];
-#pragma unroll
-      for (int j = 0; j < kV4; ++j) {
-        s[j] = stream_load<f32x4, NT>(S4 + threadIdx.x + j * kThreads);
-        k[j] = stream_load<f32x4, NT>(K4 + threadIdx.x + j * kThreads);
-        t[j] = stream_load<f32x4, NT>(T4 + threadIdx.x + j * kThreads);
-      }
-#pragma unroll
-      for (int j = 0; j < kV4; ++j) {
-        float c0, c1, c2, c3, p0, p1, p2, p3;
-        bs_price(s[j].x, k[j].x, t[j].x, r, v, half_v2, c0, p0);
-        bs_price(s[j].y, k[j].y, t[j].y, r, v, half_v2, c1, p1);
-        bs_price(s[j].z, k[j].z, t[j].z, r, v, half_v2, c2, p2);
-        bs_price(s[j].w, k[j].w, t[j].w, r, v, half_v2, c3, p3);
-        const f32x4 c = {c0, c1, c2, c3};
-        const f32x4 p = {p0, p1, p2, p3};
-        stream_store<f32x4, NT>(c, C4 + threadIdx.x + j * kThreads);
-        stream_store<f32x4, NT>(p, P4 + threadIdx.x + j * kThreads);
-      }
-    } else {
-      for (uint64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
-        float c, p;
-        bs_price(d.S[e], d.K[e], d.T[e], r, v, half_v2, c, p);
-        d.call[e] = c;
-        d.put[e] = p;
-      }
-    }
+    int q;
+    uint64_t e0;
+    BsUnitRegs<V4> x;
+    if (bs_load<V4, NT>(g, u, q, e0, x)) bs_price_store<V4, NT>(g.d[q], e0, x, r, v, half_v2);
+    else bs_unit_elementwise<V4>(g.d[q], e0, r, v, half_v2);
   }
 }
 
@@ -217,11 +252,39 @@ hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap) {
 
 hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap) { return launch_vec<MulOp>(g, s, grid_cap); }
 
-hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap) {
+// Black-Scholes launch shape: float4 per thread per stream (GVM_BS_V4 = 2, 4
+// or 8), read once per process.
+int bs_v4() {
+  static const int v4 = [] {
+    const char* e = getenv("GVM_BS_V4");
+    const int x = e ? atoi(e) : kBsV4;
+    return (x == 2 || x == 8) ? x : 4;
+  }();
+  return v4;
+}
+
+template <int V4>
+hipError_t launch_bs_shape(const BsGroup& g0, hipStream_t s, int grid_cap) {
+  // the unit size of the shape: recount the units of a copy of the group
+  BsGroup g = g0;
+  constexpr uint64_t kUnit = V4 * 4 * kThreads;
+  uint64_t u = 0;
+  for (uint32_t i = 0; i < g.count; ++i) {
+    g.d[i].unit_begin = u;
+    u += (g.d[i].n + kUnit - 1) / kUnit;
+  }
+  g.total_units = u;
   const int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap, kBsGrid))));
-  const uint64_t bytes = g.total_units * kBsUnit * 20;
-  return stream_nt(bytes) ? launch_group(bs_group_kernel<true>, grid, kThreads, s, g)
-                          : launch_group(bs_group_kernel<false>, grid, kThreads, s, g);
+  return stream_nt(g.total_units * kUnit * 20) ? launch_group(bs_group_kernel<V4, true>, grid, kThreads, s, g)
+                                               : launch_group(bs_group_kernel<V4, false>, grid, kThreads, s, g);
+}
+
+hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap) {
+  switch (bs_v4()) {
+    case 2: return launch_bs_shape<2>(g, s, grid_cap);
+    case 8: return launch_bs_shape<8>(g, s, grid_cap);
+    default: return launch_bs_shape<4>(g, s, grid_cap);
+  }
 }
 
 }  // namespace gvm
