@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 namespace gvm {
 
@@ -41,7 +42,7 @@ namespace {
 // request row-major) are dealt to the 8 XCDs in contiguous blocks, so that
 // tiles sharing rows of A and columns of B share an L2.
 
-template <int BM, int BN, int BK, int WM, int WN, bool BT, bool VEC>
+template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH, bool VEC>
 __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) {
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM, TN = BN / WN;
@@ -54,6 +55,7 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
   static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile must be a multiple of 32");
   static_assert(KH % 4 == 0, "BK must be a multiple of 8");
   static_assert(A4 >= 1 && B4 >= 1 && A4 * NT * 4 == BM * BK && B4 * NT * 4 == BK * BN, "tile/threads mismatch");
+  static_assert(DEPTH >= 1 && DEPTH <= 3, "global prefetch depth is one to three k-tiles");
 
   __shared__ __attribute__((aligned(16))) float As[2][BM * AST];
   __shared__ __attribute__((aligned(16))) float Bs[2][BT ? BN * BST : BK * BST];
@@ -106,13 +108,15 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
       return x;
     };
 
-    f32x4 ra[A4], rb[B4];
-    auto load_tile = [&](int k0) {
+    // DEPTH register slots of fetched k-tiles (slot index is a compile-time tag)
+    f32x4 ra[DEPTH][A4], rb[DEPTH][B4];
+    auto load_tile = [&](int k0, auto slot_tag) {
+      constexpr int SL = decltype(slot_tag)::value;
       const bool k_in = k0 + BK <= n;
 #pragma unroll
       for (int i = 0; i < A4; ++i) {
         const int f = tid + i * NT;
-        ra[i] = row4(A, row0 + f / (BK / 4), k0 + (f % (BK / 4)) * 4, rows_in && k_in);
+        ra[SL][i] = row4(A, row0 + f / (BK / 4), k0 + (f % (BK / 4)) * 4, rows_in && k_in);
       }
       if (BT) {
 #pragma unroll
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
           const int gr = k0 + 4 * kq, gc = col0 + c;
           const float* p = B + static_cast<size_t>(gr) * n + gc;
           if (cols_in && k_in) {
-            rb[i] = f32x4{p[0], p[n], p[2 * n], p[3 * n]};
+            rb[SL][i] = f32x4{p[0], p[n], p[2 * n], p[3 * n]};
           } else {
             f32x4 x = f32x4{0};
             if (gc < n) {
@@ -131,45 +135,54 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
               if (gr + 2 < n) x.z = p[2 * static_cast<size_t>(n)];
               if (gr + 3 < n) x.w = p[3 * static_cast<size_t>(n)];
             }
-            rb[i] = x;
+            rb[SL][i] = x;
           }
         }
       } else {
 #pragma unroll
         for (int i = 0; i < B4; ++i) {  // four columns of one k-row
           const int f = tid + i * NT;
-          rb[i] = row4(B, k0 + f / (BN / 4), col0 + (f % (BN / 4)) * 4, cols_in && k_in);
+          rb[SL][i] = row4(B, k0 + f / (BN / 4), col0 + (f % (BN / 4)) * 4, cols_in && k_in);
         }
       }
     };
-    auto store_tile = [&](int buf) {
+    auto store_tile = [&](int buf, auto slot_tag) {
+      constexpr int SL = decltype(slot_tag)::value;
 #pragma unroll
       for (int i = 0; i < A4; ++i) {
         const int f = tid + i * NT;
         const int r = f / (BK / 4), c = (f % (BK / 4)) * 4;
-        *reinterpret_cast<f32x4*>(&As[buf][r * AST + c]) = ra[i];
+        *reinterpret_cast<f32x4*>(&As[buf][r * AST + c]) = ra[SL][i];
       }
 #pragma unroll
       for (int i = 0; i < B4; ++i) {
         const int f = tid + i * NT;
         if (BT) {
           const int c = f % BN, kq = f / BN;
-          *reinterpret_cast<f32x4*>(&Bs[buf][c * BST + 4 * kq]) = rb[i];
+          *reinterpret_cast<f32x4*>(&Bs[buf][c * BST + 4 * kq]) = rb[SL][i];
         } else {
           const int r = f / (BN / 4), c = (f % (BN / 4)) * 4;
-          *reinterpret_cast<f32x4*>(&Bs[buf][r * BST + c]) = rb[i];
+          *reinterpret_cast<f32x4*>(&Bs[buf][r * BST + c]) = rb[SL][i];
         }
       }
     };
 
     const int ktiles = (n + BK - 1) / BK;
-    load_tile(0);
-    store_tile(0);
-    __syncthreads();
-    for (int kt = 0; kt < ktiles; ++kt) {
+    // One k-step: MFMAs on LDS buffer kt & 1.  Tile kt + 1 (in register
+    // slot `cur`) is written to the other buffer half-way through.  With
+    // DEPTH 1 its fetch is issued at the start of the same step, so a fetch
+    // has half a k-step to arrive; with DEPTH > 1 the step first issues the
+    // fetch of tile kt + DEPTH into slot `nxt` (tile kt's, written to LDS
+    // in the previous step), so a fetch has DEPTH - 1/2 k-steps.  Tile t
+    // lives in slot t % DEPTH.
+    auto step = [&](int kt, auto cur, auto nxt) {
       const int buf = kt & 1;
       const bool more = kt + 1 < ktiles;
-      if (more) load_tile((kt + 1) * BK);
+      if (DEPTH == 1) {
+        if (more) load_tile((kt + 1) * BK, cur);
+      } else if (kt + DEPTH < ktiles) {
+        load_tile((kt + DEPTH) * BK, nxt);
+      }
       float af[FM][KH], bf[FN][KH];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
@@ -198,7 +211,7 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
 #pragma unroll
       for (int s = 0; s < KH; ++s) {
         // The other buffer was last read before the previous barrier.
-        if (s == KH / 2 && more) store_tile(buf ^ 1);
+        if (s == KH / 2 && more) store_tile(buf ^ 1, cur);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -206,6 +219,29 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
       }
       __syncthreads();
+    };
+
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1 % DEPTH>;
+    using S2 = std::integral_constant<int, 2 % DEPTH>;
+    load_tile(0, S0{});
+    store_tile(0, S0{});
+    if constexpr (DEPTH >= 2) {
+      if (ktiles > 1) load_tile(BK, S1{});
+    }
+    if constexpr (DEPTH >= 3) {
+      if (ktiles > 2) load_tile(2 * BK, S2{});
+    }
+    __syncthreads();
+    // DEPTH steps per trip, so that every slot index is a compile-time tag
+    for (int kt = 0; kt < ktiles; kt += DEPTH) {
+      step(kt, S1{}, S0{});
+      if constexpr (DEPTH >= 2) {
+        if (kt + 1 < ktiles) step(kt + 1, S2{}, S1{});
+      }
+      if constexpr (DEPTH >= 3) {
+        if (kt + 2 < ktiles) step(kt + 2, S0{}, S2{});
+      }
     }
 
     float* __restrict__ C = d.C;
@@ -253,6 +289,16 @@ const GemmConfig kGemmConfigs[] = {
     {11, 256, 128, 32, 4, 2, false},
     {12, 128, 128, 32, 2, 2, false},
     {13, 64, 128, 16, 2, 2, false},
+    // row-major B tiles with two k-tiles fetched ahead (prefetch depth 2)
+    {14, 256, 128, 16, 4, 2, false},
+    {15, 128, 128, 16, 2, 2, false},
+    {16, 256, 128, 32, 4, 2, false},
+    {17, 64, 128, 16, 2, 2, false},
+    {18, 128, 128, 32, 2, 2, false},
+    // three k-tiles fetched ahead
+    {19, 256, 128, 16, 4, 2, false},
+    {20, 256, 128, 32, 4, 2, false},
+    {21, 128, 128, 16, 2, 2, false},
 };
 constexpr int kNumGemmConfigs = sizeof(kGemmConfigs) / sizeof(kGemmConfigs[0]);
 
@@ -260,14 +306,14 @@ int g_forced_config = -1;
 
 #include "gemm_tiles.inc"   // kTileTable: (n_max, config index) rows written by the tuner
 
-template <int BM, int BN, int BK, int WM, int WN, bool BT>
+template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH = 1>
 hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap) {
   constexpr int NT = WM * WN * 64;
   int cap = grid_cap > 0 ? grid_cap : 256 * 2;
   int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
   if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
-  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, true>, grid, NT, s, g)
-             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, false>, grid, NT, s, g);
+  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, true>, grid, NT, s, g)
+             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, false>, grid, NT, s, g);
 }
 
 }  // namespace
@@ -321,6 +367,14 @@ hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s,
     case 11: return launch_cfg<256, 128, 32, 4, 2, false>(g, vec, s, grid_cap);
     case 12: return launch_cfg<128, 128, 32, 2, 2, false>(g, vec, s, grid_cap);
     case 13: return launch_cfg<64, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
+    case 14: return launch_cfg<256, 128, 16, 4, 2, false, 2>(g, vec, s, grid_cap);
+    case 15: return launch_cfg<128, 128, 16, 2, 2, false, 2>(g, vec, s, grid_cap);
+    case 16: return launch_cfg<256, 128, 32, 4, 2, false, 2>(g, vec, s, grid_cap);
+    case 17: return launch_cfg<64, 128, 16, 2, 2, false, 2>(g, vec, s, grid_cap);
+    case 18: return launch_cfg<128, 128, 32, 2, 2, false, 2>(g, vec, s, grid_cap);
+    case 19: return launch_cfg<256, 128, 16, 4, 2, false, 3>(g, vec, s, grid_cap);
+    case 20: return launch_cfg<256, 128, 32, 4, 2, false, 3>(g, vec, s, grid_cap);
+    case 21: return launch_cfg<128, 128, 16, 2, 2, false, 3>(g, vec, s, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }

@@ -30,11 +30,13 @@ from . import workloads as wl
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "gemm_tiles.inc")
-NUM_CONFIGS = 14
-# "T": B staged k-contiguous (transposed) in LDS; "R": B row-major in LDS
+NUM_CONFIGS = 22
+# "T": B staged k-contiguous (transposed) in LDS; "R": B row-major in LDS;
+# "2", "3": k-tiles fetched two or three ahead instead of one
 CONFIG_NAMES = ["64x64x16T", "128x64x16T", "128x128x16T", "128x128x32T", "256x128x16T", "128x256x16T",
                 "256x128x32T", "64x128x16T", "128x128x16R", "256x128x16R", "128x256x16R", "256x128x32R",
-                "128x128x32R", "64x128x16R"]
+                "128x128x32R", "64x128x16R", "256x128x16R2", "128x128x16R2", "256x128x32R2", "64x128x16R2",
+                "128x128x32R2", "256x128x16R3", "256x128x32R3", "128x128x16R3"]
 
 
 def _time_size(ns, n, group, reps, configs):

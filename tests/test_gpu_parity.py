@@ -156,8 +156,9 @@ def test_sgemm_integer_inputs_bitexact(ns_name):
 
 
 def test_every_tile_configuration(ns_name):
-    # each compiled tile configuration, forced through the plain path
-    for n in (64, 200, 384):
+    # each compiled tile configuration, forced through the plain path; the
+    # sizes give one, an odd and an even number of k-tiles for BK 16 and 32
+    for n in (16, 40, 64, 200, 384):
         A, B = wl.sgemm_inputs(15, 0, n)
         x = wl.pack_request(3, A, B)
         outs = []
