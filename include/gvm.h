@@ -141,13 +141,28 @@ typedef struct gvm_config {
                                    in batch mode a batch is then enqueued as a whole once all of
                                    its inputs are staged, as in the execution model of Section
                                    4.2.3, so that its device phase is one span */
-  uint32_t reserved;
+  uint32_t latency_cus;         /* serving mode: spatial partition of the device for QoS
+                                   (0 = none).  A multiple of 32 below 256: requests whose
+                                   estimated device time is at most 50 us (the latency class)
+                                   run their kernels on a compute stream restricted to this
+                                   many CUs, all others on a stream restricted to the other
+                                   CUs, so that a short request never queues behind a long
+                                   one for compute units.  Both partitions hold CUs of every
+                                   XCD.  GVM_EINVAL for other values, in batch mode, or on a
+                                   device without 256 CUs (gvm_init). */
   char name[GVM_NAME_MAX];      /* shared-memory namespace; "" = "gvm.<uid>" */
 } gvm_config;
 
 /* Fill `cfg` with defaults (nranks 8, 64 MiB per rank, budget 16 GiB, batch mode,
  * AUTO policy, window 2000 us, HIP backend, r 0.02, sigma 0.30). */
 void gvm_config_default(gvm_config* cfg);
+
+/* The CU masks the manager uses for gvm_config.latency_cus (extension; no
+ * device needed): 8 words each, bit i = CU i of the 256 in HIP's numbering,
+ * latency partition and bulk partition, disjoint and covering all CUs, with
+ * the same share of every XCD in each.  Host-owned arrays of 8 uint32_t.
+ * GVM_EINVAL unless latency_cus is a multiple of 32 in 32..224. */
+int gvm_cu_partition_masks(uint32_t latency_cus, uint32_t* latency_mask, uint32_t* bulk_mask);
 
 /* Manager side (Section 5, "GVM run-time process"): create the control
  * segment and one shared-memory space per rank, the single HIP context on

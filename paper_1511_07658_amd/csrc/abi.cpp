@@ -36,6 +36,14 @@ void gvm_config_default(gvm_config* cfg) {
   cfg->name[0] = 0;
 }
 
+int gvm_cu_partition_masks(uint32_t latency_cus, uint32_t* latency_mask, uint32_t* bulk_mask) {
+  gvm::clear_error();
+  if (!latency_mask || !bulk_mask) return gvm::fail(GVM_EINVAL, "mask pointer is NULL");
+  const int rc = gvm::cu_partition_masks(latency_cus, latency_mask, bulk_mask);
+  if (rc != GVM_OK) return gvm::fail(rc, "latency_cus must be a multiple of 32 in 32..224");
+  return GVM_OK;
+}
+
 int gvm_init(const gvm_config* cfg) {
   gvm::clear_error();
   if (!cfg) return gvm::fail(GVM_EINVAL, "cfg is NULL");

@@ -66,6 +66,19 @@ bool request_layout(int kernel_id, uint64_t n, Layout* out) {
   }
 }
 
+int cu_partition_masks(uint32_t latency_cus, uint32_t* latency_mask, uint32_t* bulk_mask) {
+  if (latency_cus == 0 || latency_cus % 32 || latency_cus >= static_cast<uint32_t>(kPartitionCus)) return GVM_EINVAL;
+  const uint32_t m = latency_cus / 32, full = m / 2;
+  const bool half = m % 2 != 0;
+  for (int w = 0; w < kPartitionCus / 32; ++w) latency_mask[w] = bulk_mask[w] = 0;
+  for (uint32_t i = 0; i < static_cast<uint32_t>(kPartitionCus); ++i) {
+    const uint32_t a = i / 32, b = (i / 8) % 4, c = i % 8;
+    const bool lat = b < full || (half && b == full && (a + c) % 2 == 0);
+    (lat ? latency_mask : bulk_mask)[i / 32] |= 1u << (i % 32);
+  }
+  return GVM_OK;
+}
+
 int futex_wait(std::atomic<uint32_t>* word, uint32_t expected, int64_t timeout_ns) {
   timespec ts;
   timespec* tp = nullptr;

@@ -40,6 +40,20 @@ inline uint32_t piece_count(uint64_t bytes) { return static_cast<uint32_t>((byte
 // stream that runs its kernel: such a copy takes ~18 us on the link, less
 // than a dependency between two hardware queues costs (~15-20 us), and it
 // gains nothing from the copy FIFOs.
+// CU partition for serving QoS (gvm_config.latency_cus), on a device of
+// kPartitionCus CUs: bit i of a mask is CU i in HIP's numbering.  Write
+// i = 32a + 8b + c with c = i % 8, b = (i / 8) % 4 and a = i / 32.  The
+// latency partition of 32m CUs (m = 1..7) takes:
+//  * every CU with b < m / 2;
+//  * for odd m, also those with b == m / 2 and a + c even.
+// The bulk partition takes the rest.  Whether the 8 XCDs own CUs by i % 8
+// (interleaved) or by i / 32 (contiguous), every XCD then holds the same
+// share of each partition.  No queue is left with an XCD whose workgroups
+// could never be placed.  Fills kPartitionCus / 32 words of each mask;
+// GVM_EINVAL for other values of latency_cus.
+constexpr int kPartitionCus = 256;
+int cu_partition_masks(uint32_t latency_cus, uint32_t* latency_mask, uint32_t* bulk_mask);
+
 constexpr uint64_t kLocalCopyBytes = 1ull << 20;
 
 // EP-like kernel: pairs per work unit, and the 64-bit words of one result

@@ -45,6 +45,7 @@ struct Job {
   uint32_t in_pieces = 0, in_sent = 0;                 // input pieces; those whose H2D is queued
   std::unique_ptr<std::atomic<int>[]> in_pending;      // host copy chunks in flight per input piece
   uint32_t out_pieces = 0, out_taken = 0;              // output pieces; those handed to the host copy
+  int part = -1;                 // CU partition of its kernel (latency_cus): 0 latency class, 1 the rest
 };
 
 struct KernelStats {
@@ -59,6 +60,12 @@ struct KernelStats {
 // element, 20 B per option, 2 n^3 FLOP and 12 n^2 compulsory bytes per GEMM,
 // the 112 input and output bytes of an EP request, whose work is its n pairs).
 void request_work(int kernel_id, uint64_t n, double* flop, double* bytes);
+
+// Rough device time of one request on the whole MI355X (us), from its
+// algorithmic work at sustained rates (FP32 MFMA 110 TFLOP/s, HBM 5 TB/s,
+// 120 G EP pairs/s); it only sorts requests into the latency class.
+double estimate_device_us(int kernel_id, uint64_t n);
+constexpr double kLatencyClassUs = 50.0;
 
 class Device {
  public:

@@ -88,6 +88,17 @@ class HipDevice final : public Device {
     }
     HIPCHK(hipStreamCreateWithFlags(&h2d_, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&d2h_, hipStreamNonBlocking));
+    if (cfg.latency_cus) {
+      if (cus_ != kPartitionCus)
+        return fail(GVM_EINVAL, "latency_cus needs a device of %d CUs (this one has %d)", kPartitionCus, cus_);
+      if (cu_partition_masks(cfg.latency_cus, part_mask_[0], part_mask_[1]) != GVM_OK)
+        return fail(GVM_EINVAL, "latency_cus %u is not a multiple of 32 below %d", cfg.latency_cus, kPartitionCus);
+      for (int p = 0; p < 2; ++p) {
+        hipStream_t s;
+        HIPCHK(hipExtStreamCreateWithCUMask(&s, kPartitionCus / 32, part_mask_[p]));
+        part_streams_.push_back(s);
+      }
+    }
     HIPCHK(hipMalloc(reinterpret_cast<void**>(&arena_), cfg.hbm_budget_bytes));
     staging_.assign(cfg.nranks, nullptr);
     staging_bytes_ = cfg.staging_bytes ? cfg.staging_bytes : cfg.shm_bytes_per_rank;
@@ -156,6 +167,7 @@ class HipDevice final : public Device {
     if (jobs.empty()) return GVM_OK;
     if (policy != GVM_POLICY_PS1 && policy != GVM_POLICY_PS2)
       std::stable_sort(jobs.begin(), jobs.end(), [](const Job* x, const Job* y) { return x->rank < y->rank; });
+    if (jobs[0]->part >= 0 && part_streams_.size() == 2) ++part_launches_[jobs[0]->part];
     auto* b = new Batch;
     b->jobs = jobs;
     b->done.assign(jobs.size(), nullptr);
@@ -190,9 +202,11 @@ class HipDevice final : public Device {
       if (any_out) span_streams.push_back(d2h_);
       if (policy == GVM_POLICY_PS1 || policy == GVM_POLICY_PS2) {
         for (Job* j : jobs) {
-          hipStream_t s = rank_stream(j->rank);
+          hipStream_t s = kernel_stream(j);
           if (std::find(span_streams.begin(), span_streams.end(), s) == span_streams.end()) span_streams.push_back(s);
         }
+      } else if (jobs[0]->part >= 0 && part_streams_.size() == 2) {
+        span_streams.push_back(part_streams_[static_cast<size_t>(jobs[0]->part)]);
       } else if (grouped_launches(jobs) > 1) {
         span_streams.push_back(compute_streams_[1]);
       }
@@ -211,7 +225,7 @@ class HipDevice final : public Device {
       // rank i-1's result streams out.
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         Job* j = jobs[i];
-        hipStream_t s = rank_stream(j->rank);
+        hipStream_t s = kernel_stream(j);
         std::vector<Job*> one{j};
         if (j->local) {  // small: the whole chain on the rank stream
           rc = enqueue_in(j, s);
@@ -238,7 +252,7 @@ class HipDevice final : public Device {
       // stream), then every copy-out.
       std::vector<hipStream_t> ks;
       for (Job* j : jobs)
-        if (std::find(ks.begin(), ks.end(), rank_stream(j->rank)) == ks.end()) ks.push_back(rank_stream(j->rank));
+        if (std::find(ks.begin(), ks.end(), kernel_stream(j)) == ks.end()) ks.push_back(kernel_stream(j));
       bool any_in = false, any_out = false;
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         any_in |= jobs[i]->copy_in;
@@ -249,7 +263,7 @@ class HipDevice final : public Device {
         for (size_t k = 0; k < ks.size() && rc == GVM_OK; ++k) rc = after(ks[k], h2d_, b);
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         std::vector<Job*> one{jobs[i]};
-        rc = enqueue_kernels(one, {rank_stream(jobs[i]->rank)}, b, true, nullptr);
+        rc = enqueue_kernels(one, {kernel_stream(jobs[i])}, b, true, nullptr);
       }
       if (any_out)
         for (size_t k = 0; k < ks.size() && rc == GVM_OK; ++k) rc = after(d2h_, ks[k], b);
@@ -258,7 +272,7 @@ class HipDevice final : public Device {
           rc = enqueue_out(jobs[i], d2h_);
           if (rc == GVM_OK) rc = record_done(b, i, d2h_);
         } else {
-          rc = record_done(b, i, rank_stream(jobs[i]->rank));
+          rc = record_done(b, i, kernel_stream(jobs[i]));
         }
       }
     } else {
@@ -375,6 +389,8 @@ class HipDevice final : public Device {
     free_timed_.clear();
     for (hipStream_t s : rank_streams_) (void)hipStreamDestroy(s);
     for (hipStream_t s : compute_streams_) (void)hipStreamDestroy(s);
+    for (hipStream_t s : part_streams_) (void)hipStreamDestroy(s);
+    part_streams_.clear();
     if (h2d_) (void)hipStreamDestroy(h2d_);
     if (d2h_) (void)hipStreamDestroy(d2h_);
     h2d_ = d2h_ = nullptr;
@@ -411,12 +427,21 @@ class HipDevice final : public Device {
     return "{\"backend\":\"hip\",\"arch\":\"" + arch_ + "\",\"cus\":" + std::to_string(cus_) +
            ",\"rank_streams\":" + std::to_string(rank_streams_.size()) +
            ",\"compute_streams\":" + std::to_string(compute_streams_.size()) +
+           ",\"latency_cus\":" + std::to_string(part_streams_.empty() ? 0 : cfg_.latency_cus) +
+           ",\"partition_launches\":[" + std::to_string(part_launches_[0]) + "," + std::to_string(part_launches_[1]) + "]" +
            ",\"graphs_cached\":" + std::to_string(graphs_.size()) + ",\"graph_captures\":" + std::to_string(graph_captures_) +
            ",\"graph_launches\":" + std::to_string(graph_launches_) + "}";
   }
 
  private:
   hipStream_t rank_stream(int rank) { return rank_streams_[static_cast<size_t>(rank) % rank_streams_.size()]; }
+
+  // The stream a job's kernel runs on under PS-1 / PS-2: its rank's stream,
+  // or its CU partition's stream when the device is partitioned.
+  hipStream_t kernel_stream(const Job* j) {
+    if (j->part >= 0 && part_streams_.size() == 2) return part_streams_[static_cast<size_t>(j->part)];
+    return rank_stream(j->rank);
+  }
 
   hipEvent_t sync_event(Batch* b) {
     hipEvent_t e = nullptr;
@@ -712,6 +737,7 @@ class HipDevice final : public Device {
   int enqueue_grouped(Batch* b, bool capture) {
     std::vector<Job*>& jobs = b->jobs;
     hipStream_t c0 = compute_streams_[0], c1 = compute_streams_[1];
+    if (jobs[0]->part >= 0 && part_streams_.size() == 2) c0 = c1 = part_streams_[static_cast<size_t>(jobs[0]->part)];
     if (capture) {
       hipEvent_t fork = sync_event(b);
       if (!fork) return GVM_EDEVICE;
@@ -905,6 +931,9 @@ class HipDevice final : public Device {
   bool closed_ = false;
   std::vector<hipStream_t> rank_streams_;
   std::vector<hipStream_t> compute_streams_;
+  std::vector<hipStream_t> part_streams_;      // CU-masked: [0] latency class, [1] the rest (latency_cus)
+  uint32_t part_mask_[2][kPartitionCus / 32] = {};
+  uint64_t part_launches_[2] = {0, 0};
   hipStream_t h2d_ = nullptr, d2h_ = nullptr;  // copy FIFOs, one per direction
   std::map<const Job*, std::vector<TimedCopy>> pre_copies_;  // timed input pieces of jobs not yet launched
   std::vector<Batch*> retire_q_;                              // finished batches not yet retired

@@ -8,6 +8,7 @@
 // HIP backend.
 #include <sys/mman.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 
@@ -39,6 +40,14 @@ void request_work(int kernel_id, uint64_t n, double* flop, double* bytes) {
       *flop = 0.0;
       *bytes = 0.0;
   }
+}
+
+double estimate_device_us(int kernel_id, uint64_t n) {
+  if (kernel_id == GVM_K_EP) return static_cast<double>(n) / 120e9 * 1e6;
+  double flop = 0.0, bytes = 0.0;
+  request_work(kernel_id, n, &flop, &bytes);
+  const double t_mfma = kernel_id == GVM_K_SGEMM ? flop / 110e12 : 0.0;
+  return std::max(t_mfma, bytes / 5e12) * 1e6;
 }
 
 namespace {

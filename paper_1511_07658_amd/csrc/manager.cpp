@@ -76,6 +76,8 @@ int Manager::init(const gvm_config& cfg_in) {
   // HIP graph replay of repeated batches is switched off: its first GPU run
   // ended in a host segmentation fault whose cause has not been shown.
   if (cfg.use_graphs) return fail(GVM_EINVAL, "use_graphs is switched off in this build (graph replay disabled)");
+  if (cfg.latency_cus && (cfg.mode != GVM_MODE_SERVING || cfg.latency_cus % 32 || cfg.latency_cus >= 256))
+    return fail(GVM_EINVAL, "latency_cus must be 0, or in serving mode a multiple of 32 below 256");
   cfg.shm_bytes_per_rank = (cfg.shm_bytes_per_rank + 4095) / 4096 * 4096;
   if (cfg.max_inflight == 0) cfg.max_inflight = cfg.nranks;
   spin_ns_ = spin_env_ns("GVM_MANAGER_SPIN_US", 200);
@@ -529,7 +531,19 @@ bool Manager::launch_ready() {
   }
   const int policy = resolve_policy(ready);
   for (Job* j : ready) j->stage = kStageDevice;
-  dev_->launch(ready, policy);
+  if (cfg_.latency_cus == 0) {
+    dev_->launch(ready, policy);
+  } else {
+    // spatial partition: the latency class and the rest launch separately,
+    // each on its own CU-masked stream
+    std::vector<Job*> part[2];
+    for (Job* j : ready) {
+      j->part = estimate_device_us(static_cast<int>(j->req.kernel_id), j->req.n) <= kLatencyClassUs ? 0 : 1;
+      part[j->part].push_back(j);
+    }
+    for (auto& v : part)
+      if (!v.empty()) dev_->launch(v, policy);
+  }
   std::lock_guard<std::mutex> lk(stats_mu_);
   ++n_batches_;
   return true;

@@ -74,7 +74,7 @@ class gvm_config(ctypes.Structure):
         ("bs_rate", ctypes.c_float),
         ("bs_volatility", ctypes.c_float),
         ("batch_timing", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("latency_cus", ctypes.c_uint32),
         ("name", ctypes.c_char * GVM_NAME_MAX),
     ]
 
@@ -94,6 +94,8 @@ def lib():
         L.gvm_config_default.restype = None
         L.gvm_init.argtypes = [ctypes.POINTER(gvm_config)]
         L.gvm_init.restype = i32
+        L.gvm_cu_partition_masks.argtypes = [u32, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]
+        L.gvm_cu_partition_masks.restype = i32
         L.gvm_attach.argtypes = [i32]
         L.gvm_attach.restype = i32
         L.gvm_attach_ns.argtypes = [ctypes.c_char_p, i32]
@@ -148,6 +150,14 @@ def gvm_config_default(**overrides) -> gvm_config:
             v = v.encode() if isinstance(v, str) else v
         setattr(cfg, k, v)
     return cfg
+
+
+def gvm_cu_partition_masks(latency_cus: int):
+    """(latency mask, bulk mask) as two lists of 8 uint32 words, or raises."""
+    lat = (ctypes.c_uint32 * 8)()
+    bulk = (ctypes.c_uint32 * 8)()
+    check(lib().gvm_cu_partition_masks(latency_cus, lat, bulk), "gvm_cu_partition_masks")
+    return list(lat), list(bulk)
 
 
 def gvm_init(cfg: gvm_config) -> int:

@@ -325,6 +325,29 @@ def test_serving_mix_matches_alone(ns_name):
             assert spmd.digest(o) == jr["digest"], (r, k, n)
 
 
+def test_cu_partition_results_match_plain(ns_name):
+    # serving mode with 64 CUs for the latency class: small requests (latency
+    # class) and SGEMM 2048 (the rest) run on CU-masked streams; every result
+    # equals the plain path's byte for byte and both partitions are used
+    nr = 4
+    jobs = {r: [(1, 52, 70001 + r, 0, False), (3, 52, 2048, 1, False), (2, 52, 30001, 2, False),
+                (3, 52, 160 + r, 3, False)] for r in range(nr)}
+    with hip_manager(ns_name, nranks=nr, mode=G.GVM_MODE_SERVING, latency_cus=64):
+        res = run_ranks(ns_name, [jobs[r] for r in range(nr)])
+        st = G.gvm_stats_json()
+    assert st["device"]["latency_cus"] == 64
+    assert all(x > 0 for x in st["device"]["partition_launches"]), st["device"]
+    for r in range(nr):
+        assert res[r]["attach"] == 0
+        for (k, cfg, n, req, integer), jr in zip(jobs[r], res[r]["results"]):
+            assert jr["status"] == 0, jr
+            x = spmd.make_input(k, cfg, r, n, req, integer)
+            o = np.empty(G.out_elems(k, n), np.float32)
+            rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
+            assert rc == 0
+            assert spmd.digest(o) == jr["digest"], (r, k, n)
+
+
 def test_request_larger_than_budget(ns_name):
     with hip_manager(ns_name, nranks=1, hbm_budget_bytes=8 << 20, shm_bytes_per_rank=64 << 20):
         assert G.gvm_attach_ns(ns_name, 0) == 0

@@ -396,3 +396,70 @@ def test_graph_replay_is_switched_off(ns_name):
     cfg = loop_cfg(ns_name, use_graphs=1)
     assert G.gvm_init(cfg) == G.GVM_EINVAL
     assert "graph" in G.gvm_last_error()
+
+
+def _popcount(words):
+    return sum(bin(w).count("1") for w in words)
+
+
+@pytest.mark.parametrize("m", range(1, 8))
+def test_cu_partition_masks_cover_every_xcd(m):
+    # the two CU-masked partitions are disjoint, cover all 256 CUs, and give
+    # every XCD the same share whether XCDs own CUs by i % 8 or by i / 32
+    lat, bulk = G.gvm_cu_partition_masks(32 * m)
+    assert len(lat) == len(bulk) == 8
+    assert all((a & b) == 0 for a, b in zip(lat, bulk))
+    assert all((a | b) == 0xFFFFFFFF for a, b in zip(lat, bulk))
+    assert _popcount(lat) == 32 * m and _popcount(bulk) == 256 - 32 * m
+
+    def bit(words, i):
+        return (words[i // 32] >> (i % 32)) & 1
+
+    for xcd_of in (lambda i: i % 8, lambda i: i // 32):
+        for x in range(8):
+            cus = [i for i in range(256) if xcd_of(i) == x]
+            assert sum(bit(lat, i) for i in cus) == 4 * m
+            assert sum(bit(bulk, i) for i in cus) == 32 - 4 * m
+
+
+@pytest.mark.parametrize("bad", [0, 16, 33, 256, 512])
+def test_cu_partition_masks_reject_bad_sizes(bad):
+    with pytest.raises(G.GvmError):
+        G.gvm_cu_partition_masks(bad)
+
+
+def test_cu_partition_config_checks(ns_name):
+    # serving mode only, multiples of 32 below 256
+    for kw in (dict(latency_cus=64), dict(latency_cus=48, mode=G.GVM_MODE_SERVING),
+               dict(latency_cus=256, mode=G.GVM_MODE_SERVING)):
+        assert G.gvm_init(loop_cfg(ns_name, **kw)) == G.GVM_EINVAL
+        assert "latency_cus" in G.gvm_last_error()
+
+
+def test_cu_partition_serving_routes_both_classes(ns_name):
+    # small requests (latency class) and large ones (the rest) from the same
+    # ranks: each launches in its own class and gets its own data back
+    with Manager(ns_name, nranks=4, mode=G.GVM_MODE_SERVING, latency_cus=64, shm_bytes_per_rank=64 << 20,
+                 hbm_budget_bytes=256 << 20):
+        errs = []
+
+        def rank(r):
+            assert G.gvm_attach_ns(ns_name, r) == 0
+            for i in range(6):
+                n = 1000 + r if i % 2 == 0 else (1 << 22) + r   # ~0 us vs ~10 us of vector add
+                k = G.GVM_K_VECADD if i % 3 else G.GVM_K_SGEMM
+                if k == G.GVM_K_SGEMM:
+                    n = 64 if i % 2 == 0 else 1024               # ~0 us vs ~20 us
+                inp = np.arange(G.in_elems(k, n), dtype=np.float32) + 7 * r + i
+                out = np.zeros(G.out_elems(k, n), np.float32)
+                t = G.gvm_submit(r, k, inp, out, n)
+                st = G.gvm_wait(r, t, 30_000_000_000)
+                if st != 0 or not np.array_equal(out, expect_loopback(k, inp, n)):
+                    errs.append((r, i, st))
+            G.gvm_detach(r)
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(4)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+        assert G.gvm_stats_json()["requests_done"] == 24
