@@ -93,9 +93,14 @@ class HipDevice final : public Device {
         return fail(GVM_EINVAL, "latency_cus needs a device of %d CUs (this one has %d)", kPartitionCus, cus_);
       if (cu_partition_masks(cfg.latency_cus, part_mask_[0], part_mask_[1]) != GVM_OK)
         return fail(GVM_EINVAL, "latency_cus %u is not a multiple of 32 below %d", cfg.latency_cus, kPartitionCus);
+      // GVM_PARTITION_MASKS=0 keeps the two class streams but without CU
+      // masks (for measuring what the masks add to the separate streams)
+      const char* env = getenv("GVM_PARTITION_MASKS");
+      part_masked_ = !(env && env[0] == '0');
       for (int p = 0; p < 2; ++p) {
         hipStream_t s;
-        HIPCHK(hipExtStreamCreateWithCUMask(&s, kPartitionCus / 32, part_mask_[p]));
+        if (part_masked_) HIPCHK(hipExtStreamCreateWithCUMask(&s, kPartitionCus / 32, part_mask_[p]));
+        else HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         part_streams_.push_back(s);
       }
     }
@@ -428,6 +433,7 @@ class HipDevice final : public Device {
            ",\"rank_streams\":" + std::to_string(rank_streams_.size()) +
            ",\"compute_streams\":" + std::to_string(compute_streams_.size()) +
            ",\"latency_cus\":" + std::to_string(part_streams_.empty() ? 0 : cfg_.latency_cus) +
+           ",\"partition_masked\":" + std::string(part_masked_ ? "true" : "false") +
            ",\"partition_launches\":[" + std::to_string(part_launches_[0]) + "," + std::to_string(part_launches_[1]) + "]" +
            ",\"graphs_cached\":" + std::to_string(graphs_.size()) + ",\"graph_captures\":" + std::to_string(graph_captures_) +
            ",\"graph_launches\":" + std::to_string(graph_launches_) + "}";
@@ -934,6 +940,7 @@ class HipDevice final : public Device {
   std::vector<hipStream_t> part_streams_;      // CU-masked: [0] latency class, [1] the rest (latency_cus)
   uint32_t part_mask_[2][kPartitionCus / 32] = {};
   uint64_t part_launches_[2] = {0, 0};
+  bool part_masked_ = false;
   hipStream_t h2d_ = nullptr, d2h_ = nullptr;  // copy FIFOs, one per direction
   std::map<const Job*, std::vector<TimedCopy>> pre_copies_;  // timed input pieces of jobs not yet launched
   std::vector<Batch*> retire_q_;                              // finished batches not yet retired

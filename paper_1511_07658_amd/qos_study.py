@@ -13,6 +13,8 @@ Each configuration runs the same seeded arrivals for ``--seconds``:
   device);
 * ``shared``: both kinds, no partition: a small request's kernel waits for
   CUs that the bulk SGEMM's workgroups hold;
+* ``streams``: both kinds, each class on a stream of its own but without
+  CU masks (``GVM_PARTITION_MASKS=0``): what separate queues alone give;
 * ``cus=32`` and ``cus=64``: both kinds, the latency class restricted to 32
   or 64 CUs and the bulk class to the rest.
 
@@ -141,6 +143,7 @@ def run_case(latency_cus: int, bulk_ranks: int, lat_ranks: int, rate: float, sec
         "per_kernel_us": {k: {"count": len(v), "p50": _pct(v, 50), "p99": _pct(v, 99)} for k, v in lat_us.items()},
         "bulk_sgemm_TFLOPs": round(len(in_window) * 2.0 * BULK_N ** 3 / seconds / 1e12, 2),
         "partition_launches": st["device"].get("partition_launches"),
+        "partition_masked": st["device"].get("partition_masked"),
     }
 
 
@@ -153,10 +156,15 @@ def main(argv=None):
     ap.add_argument("--json", default=None)
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
     a = ap.parse_args(argv)
-    cases = [("alone", 0, 0), ("shared", 0, a.bulk_ranks), ("cus=32", 32, a.bulk_ranks), ("cus=64", 64, a.bulk_ranks)]
+    cases = [("alone", 0, 0, True), ("shared", 0, a.bulk_ranks, True), ("streams", 64, a.bulk_ranks, False),
+             ("cus=32", 32, a.bulk_ranks, True), ("cus=64", 64, a.bulk_ranks, True)]
     rows = []
-    for name, cus, bulk in cases:
-        row = {"case": name, **run_case(cus, bulk, a.latency_ranks, a.rate, a.seconds, a.loopback)}
+    for name, cus, bulk, masked in cases:
+        os.environ["GVM_PARTITION_MASKS"] = "1" if masked else "0"
+        try:
+            row = {"case": name, **run_case(cus, bulk, a.latency_ranks, a.rate, a.seconds, a.loopback)}
+        finally:
+            os.environ.pop("GVM_PARTITION_MASKS", None)
         rows.append(row)
         print(json.dumps(row), flush=True)
     if a.json:
