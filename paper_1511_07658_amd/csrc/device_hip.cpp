@@ -59,6 +59,42 @@ struct Batch {
   size_t remaining = 0;
 };
 
+// Tile configuration of a BK class of SGEMM requests, sorted by size from
+// the largest down.
+//  * One size: the table's configuration of that size.
+//  * Mixed sizes: 64x128x16 tiles with row-major B (configuration 13), the
+//    smallest tiles that still run near full rate.  They balance the short
+//    and the long tiles of a mix over the CUs: a 16-size mix runs at 65.2
+//    TFLOP/s with them, against 59 to 62 with 128x128 or larger tiles.
+//  * Mixed sizes of another BK: the table's configuration of the median size.
+// Every choice has the class's BK.  Tuning override, for mixed classes:
+// GVM_SGEMM_CLASS_CONFIG=<index>, when the index has the class's BK.
+constexpr int kMixConfig = 13;
+
+int gemm_class_config(const std::vector<Job*>& v) {
+  const int c = gemm_config_for(v[v.size() / 2]->req.n);
+  if (v.front()->req.n == v.back()->req.n) return c;
+  static const int env = [] {
+    const char* e = getenv("GVM_SGEMM_CLASS_CONFIG");
+    return e ? atoi(e) : -1;
+  }();
+  const int bk = gemm_config(c).bk;
+  if (env >= 0 && env < gemm_config_count() && gemm_config(env).bk == bk) return env;
+  return gemm_config(kMixConfig).bk == bk ? kMixConfig : c;
+}
+
+// Grid cap of an SGEMM launch over mixed sizes: one workgroup per tile, so
+// that the dispatcher hands the next tile to whichever CU frees up first
+// (tiles of different sizes differ in k-length by up to 5x; a persistent
+// grid deals them out statically).  GVM_SGEMM_MIX_GRID overrides.
+int gemm_mix_grid() {
+  static const int env = [] {
+    const char* e = getenv("GVM_SGEMM_MIX_GRID");
+    return e ? atoi(e) : 0;
+  }();
+  return env > 0 ? env : (1 << 24);
+}
+
 class HipDevice final : public Device {
  public:
   ~HipDevice() override { close(); }
@@ -479,7 +515,7 @@ class HipDevice final : public Device {
     std::map<std::pair<int, int>, size_t> groups;
     for (const Job* j : jobs) {
       const int k = static_cast<int>(j->req.kernel_id);
-      ++groups[{k, k == GVM_K_SGEMM ? gemm_config_for(j->req.n) : 0}];
+      ++groups[{k, k == GVM_K_SGEMM ? gemm_config(gemm_config_for(j->req.n)).bk : 0}];  // as enqueue_kernels
     }
     size_t n = 0;
     for (const auto& kv : groups) n += (kv.second + kMaxGroup - 1) / kMaxGroup;
@@ -574,15 +610,30 @@ class HipDevice final : public Device {
     std::map<const Job*, size_t> index;
     for (size_t i = 0; i < jobs.size(); ++i) index[jobs[i]] = i;
     size_t next_stream = 0;
+    // One grouped launch per kernel id; SGEMM requests are grouped by the k
+    // depth BK of their size's tile configuration.  A C element sums its k
+    // products in an order fixed by BK alone (ascending k-tiles of BK, each
+    // in KH = BK/2 MFMA steps over k = s and BK/2 + s), whatever the tile
+    // shape, staging or fetch depth, so every request of a BK class may run
+    // with the configuration of the class's largest request and still get
+    // the bits it gets alone.  A mix of sizes then fills the device with one
+    // launch instead of one small launch per configuration.
     std::map<std::pair<int, int>, std::vector<Job*>> groups;
     for (Job* j : jobs) {
       const int k = static_cast<int>(j->req.kernel_id);
-      const int cfg = (k == GVM_K_SGEMM) ? gemm_config_for(j->req.n) : 0;
-      groups[{k, cfg}].push_back(j);
+      const int cls = (k == GVM_K_SGEMM) ? gemm_config(gemm_config_for(j->req.n)).bk : 0;
+      groups[{k, cls}].push_back(j);
     }
     for (auto& kv : groups) {
-      const int k = kv.first.first, cfgi = kv.first.second;
+      const int k = kv.first.first;
       auto& v = kv.second;
+      int cfgi = 0;
+      if (k == GVM_K_SGEMM) {
+        // largest first: the launch's first round of workgroups takes the
+        // longest tiles and the later rounds fill in behind them
+        std::stable_sort(v.begin(), v.end(), [](const Job* x, const Job* y) { return x->req.n > y->req.n; });
+        cfgi = gemm_class_config(v);
+      }
       for (size_t base = 0; base < v.size(); base += kMaxGroup) {
         const size_t cnt = std::min<size_t>(kMaxGroup, v.size() - base);
         const size_t si = next_stream++ % streams.size();
@@ -650,7 +701,8 @@ class HipDevice final : public Device {
             g.d[i].n = static_cast<uint32_t>(n);
           }
           finalize_gemm_group(g, cfgi);
-          e = launch_sgemm_group(g, cfgi, s);
+          const bool mixed = v.front()->req.n != v.back()->req.n;
+          e = launch_sgemm_group(g, cfgi, s, mixed ? gemm_mix_grid() : 0);
         } else if (k == GVM_K_EP) {
           EpGroup g{};
           g.count = static_cast<uint32_t>(cnt);

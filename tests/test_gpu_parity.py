@@ -14,6 +14,7 @@ per-process path the outputs are identical.
 
 import contextlib
 import os
+import re
 import threading
 
 import numpy as np
@@ -172,6 +173,51 @@ def test_every_tile_configuration(ns_name):
                 del os.environ["GVM_SGEMM_CONFIG"]
             assert_sgemm(o, 15, 0, n)
             outs.append(o)
+
+
+def test_same_bk_tile_configurations_are_bit_identical():
+    # a C element's k order depends on BK alone, so every configuration of
+    # one BK gives the same bits (what lets a BK class share one launch)
+    from paper_1511_07658_amd.tune import CONFIG_NAMES
+    for n in (96, 200, 515):
+        A, B = wl.sgemm_inputs(16, 0, n)
+        x = wl.pack_request(3, A, B)
+        by_bk = {}
+        for cfg_idx, name in enumerate(CONFIG_NAMES):
+            bk = int(re.match(r"(\d+)x(\d+)x(\d+)", name).group(3))
+            os.environ["GVM_SGEMM_CONFIG"] = str(cfg_idx)
+            try:
+                o = np.empty(n * n, np.float32)
+                rc, _ = G.gvm_plain_run(3, x, o, n)
+                assert rc == 0, G.gvm_last_error()
+            finally:
+                del os.environ["GVM_SGEMM_CONFIG"]
+            by_bk.setdefault(bk, []).append((name, spmd.digest(o)))
+        for bk, outs in by_bk.items():
+            assert len({d for _, d in outs}) == 1, (n, bk, outs)
+
+
+def test_sgemm_size_mix_matches_plain(ns_name):
+    # 12 ranks of SGEMM sizes that the tile table maps to different
+    # configurations of both BK classes, in one batch: each result equals
+    # the plain path's (its size's own configuration) byte for byte
+    sizes = [160, 384, 600, 704, 768, 832, 896, 960, 1024, 1216, 1664, 1792]
+    nr = len(sizes)
+    jobs = {r: [(3, 53, sizes[r], 0, False)] for r in range(nr)}
+    with hip_manager(ns_name, nranks=nr, policy=G.GVM_POLICY_GROUPED, shm_bytes_per_rank=48 << 20,
+                     batch_window_us=10_000_000):
+        res = run_ranks(ns_name, [jobs[r] for r in range(nr)], barrier=threading.Barrier(nr))
+        st = G.gvm_stats_json()
+    assert st["kernels"]["sgemm"]["launches"] <= 2, st["kernels"]["sgemm"]
+    for r in range(nr):
+        (k, cfg, n, req, integer), = jobs[r]
+        assert res[r]["results"][0]["status"] == 0
+        x = spmd.make_input(k, cfg, r, n, req, integer)
+        o = np.empty(G.out_elems(k, n), np.float32)
+        rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
+        assert rc == 0
+        assert spmd.digest(o) == res[r]["results"][0]["digest"], (r, n)
+        assert_sgemm(o, cfg, r, n)
 
 
 def test_config1_four_ranks_vecadd(ns_name):
