@@ -218,8 +218,10 @@ void Manager::service(std::promise<int>* ready) {
     // next request of a synchronous SPMD step is seen without a futex wake-up
     if (idle_since == 0) idle_since = now_ns();
     if (now_ns() - idle_since < spin_ns_) {
-      if (now_ns() - idle_since > 50000) flush_deferred();  // nothing arrived for 50 us
-      _mm_pause();
+      // (finished batches are retired while the device works, or before the
+      // sleep below, not here: a synchronous rank's next request is due now)
+      // yield now and then, for a rank that shares this core
+      if (++spins % 64 == 0) sched_yield(); else _mm_pause();
       continue;
     }
     // idle: retire what finished, then sleep on the doorbell until a rank

@@ -172,6 +172,7 @@ int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
   const uint64_t t0 = now_ns();
   const uint64_t spin = rank_spin_ns(hdr);
   const uint64_t deadline = timeout_ns < 0 ? UINT64_MAX : t0 + static_cast<uint64_t>(timeout_ns);
+  uint32_t polls = 0;
   for (;;) {
     drain(h);
     if (done()) return GVM_OK;
@@ -184,6 +185,11 @@ int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
     if (now >= deadline) return fail(GVM_ETIMEDOUT, "timed out");
     if (now - t0 < spin) {  // poll before sleeping (GVM_RANK_SPIN_US)
       for (int i = 0; i < 32; ++i) _mm_pause();
+      // Give the core away now and then: a rank woken from its futex can be
+      // placed on the manager's core, and a poll that never yields would
+      // then hold off the manager (and the rank's own next request) for the
+      // whole poll budget.
+      if (++polls % 8 == 0) sched_yield();
       continue;
     }
     // batch mode: sleep on the shared group doorbell (one wake-up call per

@@ -56,15 +56,19 @@ def _rank(ns: str, n: int, warmup: int, reps: int, zero_copy: bool, barrier):
         G.check(G.gvm_wait(0, t, 60_000_000_000), "warm-up wait")
     barrier.wait()   # warm-up done
     barrier.wait()   # statistics reset
-    times = []
+    times, stages = [], []
     for _ in range(reps):
         t0 = time.perf_counter_ns()
         t = G.check(G.gvm_submit(0, G.GVM_K_VECADD, inb, outb, n), "submit")
-        G.check(G.gvm_wait(0, t, 60_000_000_000), "wait")
+        st, ts = G.gvm_wait_timed(0, t, 60_000_000_000)
+        G.check(st, "wait")
         times.append(time.perf_counter_ns() - t0)
+        # manager timestamps: submit -> admitted -> launched (input staged) ->
+        # device done -> answered (result back in shared memory)
+        stages.append([ts[1] - ts[0], ts[2] - ts[1], ts[3] - ts[2], ts[4] - ts[3]])
     ok = bool(np.array_equal(outb, a + b))
     G.check(G.gvm_detach(0), "detach")
-    return {"turnaround_ns": times, "exact": ok}
+    return {"turnaround_ns": times, "stages_ns": stages, "exact": ok}
 
 
 def run(sizes_mb, reps: int, warmup: int = 2, loopback: bool = False):
@@ -108,6 +112,10 @@ def run(sizes_mb, reps: int, warmup: int = 2, loopback: bool = False):
                     "h2d_us": round(h2d, 1), "kernel_us": round(kern, 1), "d2h_us": round(d2h, 1),
                     "overhead_us": round(turn - gpu, 1),
                     "overhead_frac": round((turn - gpu) / turn, 4),
+                    # medians of the manager's stage times (us)
+                    "stages_us": {name: round(statistics.median(x[i] for x in res["stages_ns"]) / 1e3, 1)
+                                  for i, name in enumerate(("submit_to_admit", "admit_to_launch",
+                                                            "launch_to_device_done", "device_done_to_answer"))},
                 }
                 rows.append(row)
                 print(json.dumps(row), flush=True)
