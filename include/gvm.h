@@ -97,8 +97,11 @@ enum gvm_mode {
  *   PS2      per rank: copy-in, kernel, copy-out on the rank's stream (Listing PS-2)
  *   GROUPED  copy-ins per rank, then ONE persistent launch per kernel id that
  *            covers every rank's request, then copy-outs per rank
- *   AUTO     the paper's rule (compute-intensive -> PS1, I/O-intensive -> PS2,
- *            end of Section 4.2.3), with GROUPED for sets of same-kernel requests */
+ *   AUTO     GROUPED when no request of the set moves more than 1 MiB over
+ *            PCIe (inputs and results resident, or small copies kept on the
+ *            kernel's stream); otherwise PS2, the paper's rule for I/O-intensive
+ *            kernels (end of Section 4.2.3), which every kernel here is once
+ *            its data crosses PCIe on this GPU */
 enum gvm_policy { GVM_POLICY_AUTO = 0, GVM_POLICY_PS1 = 1, GVM_POLICY_PS2 = 2, GVM_POLICY_GROUPED = 3 };
 
 /* Device backend.  HIP is the product path.  LOOPBACK runs the whole host
