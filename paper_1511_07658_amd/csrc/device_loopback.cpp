@@ -9,6 +9,7 @@
 #include <sys/mman.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 
@@ -79,7 +80,8 @@ class LoopbackDevice final : public Device {
     return staging_[rank];
   }
 
-  int launch(std::vector<Job*>& jobs, int /*policy*/) override {
+  int launch(std::vector<Job*>& jobs, int policy) override {
+    if (policy >= 0 && policy < 4) policy_launches_[policy].fetch_add(1, std::memory_order_relaxed);
     const uint64_t t_batch = now_ns();
     for (Job* j : jobs) {
       j->t_launch_ns = now_ns();
@@ -139,7 +141,13 @@ class LoopbackDevice final : public Device {
     batch_us_.clear();
     for (int d = 0; d < 2; ++d) copy_ms_[d] = copy_bytes_[d] = 0.0, copy_n_[d] = 0;
   }
-  std::string describe() const override { return "{\"backend\":\"loopback\"}"; }
+  // launch calls by the policy the manager chose (host-logic tests check it)
+  std::string describe() const override {
+    return "{\"backend\":\"loopback\",\"policy_launches\":{\"ps1\":" +
+           std::to_string(policy_launches_[GVM_POLICY_PS1].load()) +
+           ",\"ps2\":" + std::to_string(policy_launches_[GVM_POLICY_PS2].load()) +
+           ",\"grouped\":" + std::to_string(policy_launches_[GVM_POLICY_GROUPED].load()) + "}}";
+  }
 
   // Same layout as the HIP backend's, on the host clock (batch_timing).
   std::string timing_json() const override {
@@ -177,6 +185,7 @@ class LoopbackDevice final : public Device {
   std::vector<uint8_t*> staging_;
   uint64_t staging_bytes_ = 0;
   KernelStats stats_[kNumKernelIds];
+  std::atomic<uint64_t> policy_launches_[4] = {};
 };
 
 }  // namespace

@@ -463,3 +463,31 @@ def test_cu_partition_serving_routes_both_classes(ns_name):
         [t.join() for t in ths]
         assert not errs, errs
         assert G.gvm_stats_json()["requests_done"] == 24
+
+
+@pytest.mark.parametrize("n, expect", [(20_000, "grouped"), (400_000, "ps2")])
+def test_auto_policy_size_rule(ns_name, n, expect):
+    # AUTO: one grouped launch when every request's copies are small (kept on
+    # the kernel's stream), PS-2 once a request moves more than 1 MiB
+    with Manager(ns_name, nranks=4, policy=G.GVM_POLICY_AUTO, batch_window_us=10_000_000,
+                 shm_bytes_per_rank=16 << 20):
+        bar = threading.Barrier(4)
+        errs = []
+
+        def rank(r):
+            assert G.gvm_attach_ns(ns_name, r) == 0
+            bar.wait()
+            inp = np.arange(2 * n, dtype=np.float32) + r
+            out = np.zeros(n, np.float32)
+            t = G.gvm_submit(r, G.GVM_K_VECADD, inp, out, n)
+            if G.gvm_wait(r, t, 30_000_000_000) != 0 or not np.array_equal(out, expect_loopback(1, inp, n)):
+                errs.append(r)
+            G.gvm_detach(r)
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(4)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs
+        pl = G.gvm_stats_json()["device"]["policy_launches"]
+    other = "ps2" if expect == "grouped" else "grouped"
+    assert pl[expect] >= 1 and pl[other] == 0, pl
