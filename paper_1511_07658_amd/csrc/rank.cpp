@@ -176,7 +176,8 @@ int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
   for (;;) {
     drain(h);
     if (done()) return GVM_OK;
-    if (manager_gone(hdr)) {
+    // the liveness probe is a system call: every 64th poll while polling
+    if ((polls & 63) == 0 && manager_gone(hdr)) {
       drain(h);
       if (done()) return GVM_OK;
       return fail(GVM_EDEAD, "the GVM manager is gone");
@@ -184,14 +185,15 @@ int wait_until(RankHandle& h, CtlHeader* hdr, int64_t timeout_ns, Pred done) {
     const uint64_t now = now_ns();
     if (now >= deadline) return fail(GVM_ETIMEDOUT, "timed out");
     if (now - t0 < spin) {  // poll before sleeping (GVM_RANK_SPIN_US)
-      for (int i = 0; i < 32; ++i) _mm_pause();
+      for (int i = 0; i < 8; ++i) _mm_pause();
       // Give the core away now and then: a rank woken from its futex can be
       // placed on the manager's core, and a poll that never yields would
       // then hold off the manager (and the rank's own next request) for the
       // whole poll budget.
-      if (++polls % 8 == 0) sched_yield();
+      if (++polls % 32 == 0) sched_yield();
       continue;
     }
+    polls = 0;  // after a sleep: probe liveness on the next poll
     // batch mode: sleep on the shared group doorbell (one wake-up call per
     // answered batch); serving mode: on the rank's own doorbell
     const bool group = hdr->cfg.mode == GVM_MODE_BATCH;
