@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -418,6 +419,7 @@ class HipDevice final : public Device {
       (void)hipGraphDestroy(kv.second.graph);
     }
     graphs_.clear();
+    graphs_cached_.store(0);
     for (auto& kv : pre_copies_)
       for (auto& t : kv.second) {
         (void)hipEventDestroy(t.e0);
@@ -470,9 +472,9 @@ class HipDevice final : public Device {
            ",\"compute_streams\":" + std::to_string(compute_streams_.size()) +
            ",\"latency_cus\":" + std::to_string(part_streams_.empty() ? 0 : cfg_.latency_cus) +
            ",\"partition_masked\":" + std::string(part_masked_ ? "true" : "false") +
-           ",\"partition_launches\":[" + std::to_string(part_launches_[0]) + "," + std::to_string(part_launches_[1]) + "]" +
-           ",\"graphs_cached\":" + std::to_string(graphs_.size()) + ",\"graph_captures\":" + std::to_string(graph_captures_) +
-           ",\"graph_launches\":" + std::to_string(graph_launches_) + "}";
+           ",\"partition_launches\":[" + std::to_string(part_launches_[0].load()) + "," + std::to_string(part_launches_[1].load()) + "]" +
+           ",\"graphs_cached\":" + std::to_string(graphs_cached_.load()) + ",\"graph_captures\":" + std::to_string(graph_captures_.load()) +
+           ",\"graph_launches\":" + std::to_string(graph_launches_.load()) + "}";
   }
 
  private:
@@ -760,6 +762,7 @@ class HipDevice final : public Device {
         return fail(GVM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
       }
       it = graphs_.emplace(key, GraphEntry{g, ex, 0}).first;
+      graphs_cached_.store(graphs_.size());
       ++graph_captures_;
     }
     it->second.last_use = ++graph_clock_;
@@ -903,6 +906,7 @@ class HipDevice final : public Device {
     (void)hipGraphExecDestroy(victim->second.exec);
     (void)hipGraphDestroy(victim->second.graph);
     graphs_.erase(victim);
+    graphs_cached_.store(graphs_.size());
   }
 
   void retire(Batch* b) {
@@ -991,7 +995,7 @@ class HipDevice final : public Device {
   std::vector<hipStream_t> compute_streams_;
   std::vector<hipStream_t> part_streams_;      // CU-masked: [0] latency class, [1] the rest (latency_cus)
   uint32_t part_mask_[2][kPartitionCus / 32] = {};
-  uint64_t part_launches_[2] = {0, 0};
+  std::atomic<uint64_t> part_launches_[2] = {};  // counters read by describe() on the API thread
   bool part_masked_ = false;
   hipStream_t h2d_ = nullptr, d2h_ = nullptr;  // copy FIFOs, one per direction
   std::map<const Job*, std::vector<TimedCopy>> pre_copies_;  // timed input pieces of jobs not yet launched
@@ -1020,7 +1024,9 @@ class HipDevice final : public Device {
   };
   static constexpr size_t kMaxGraphs = 32;
   std::map<std::string, GraphEntry> graphs_;
-  uint64_t graph_clock_ = 0, graph_captures_ = 0, graph_launches_ = 0;
+  uint64_t graph_clock_ = 0;
+  std::atomic<uint64_t> graph_captures_{0}, graph_launches_{0};
+  std::atomic<size_t> graphs_cached_{0};  // graphs_.size(), for describe()
 };
 
 }  // namespace

@@ -110,13 +110,15 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
 
     // DEPTH register slots of fetched k-tiles (slot index is a compile-time tag)
     f32x4 ra[DEPTH][A4], rb[DEPTH][B4];
-    auto load_tile = [&](int k0, auto slot_tag) {
+    // FAST (a compile-time tag): an interior tile, every load unchecked
+    auto load_tile = [&](int k0, auto slot_tag, auto fast_tag) {
       constexpr int SL = decltype(slot_tag)::value;
-      const bool k_in = k0 + BK <= n;
+      constexpr bool FAST = decltype(fast_tag)::value;
+      const bool k_in = FAST || k0 + BK <= n;
 #pragma unroll
       for (int i = 0; i < A4; ++i) {
         const int f = tid + i * NT;
-        ra[SL][i] = row4(A, row0 + f / (BK / 4), k0 + (f % (BK / 4)) * 4, rows_in && k_in);
+        ra[SL][i] = row4(A, row0 + f / (BK / 4), k0 + (f % (BK / 4)) * 4, FAST || (rows_in && k_in));
       }
       if (BT) {
 #pragma unroll
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
           const int c = f % BN, kq = f / BN;
           const int gr = k0 + 4 * kq, gc = col0 + c;
           const float* p = B + static_cast<size_t>(gr) * n + gc;
-          if (cols_in && k_in) {
+          if (FAST || (cols_in && k_in)) {
             rb[SL][i] = f32x4{p[0], p[n], p[2 * n], p[3 * n]};
           } else {
             f32x4 x = f32x4{0};
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
 #pragma unroll
         for (int i = 0; i < B4; ++i) {  // four columns of one k-row
           const int f = tid + i * NT;
-          rb[SL][i] = row4(B, k0 + f / (BN / 4), col0 + (f % (BN / 4)) * 4, cols_in && k_in);
+          rb[SL][i] = row4(B, k0 + f / (BN / 4), col0 + (f % (BN / 4)) * 4, FAST || (cols_in && k_in));
         }
       }
     };
@@ -175,13 +177,26 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
     // fetch of tile kt + DEPTH into slot `nxt` (tile kt's, written to LDS
     // in the previous step), so a fetch has DEPTH - 1/2 k-steps.  Tile t
     // lives in slot t % DEPTH.
-    auto step = [&](int kt, auto cur, auto nxt) {
+    //
+    // On an interior tile whose k-tiles divide evenly (FAST), every step
+    // issues the same loads and LDS writes without a branch: the last steps
+    // fetch the last k-tile again and write it to the buffer no later step
+    // reads.  The compiler can then wait for exactly the fetch it needs
+    // (`s_waitcnt vmcnt(n)` with the newer fetch still in flight); with
+    // conditional fetches it waits for all of them (`vmcnt(0)`), which
+    // takes the fetch depth back to half a k-step.
+    auto step = [&](int kt, auto cur, auto nxt, auto fast_tag) {
+      constexpr bool FAST = decltype(fast_tag)::value;
       const int buf = kt & 1;
-      const bool more = kt + 1 < ktiles;
-      if (DEPTH == 1) {
-        if (more) load_tile((kt + 1) * BK, cur);
+      const bool more = FAST || kt + 1 < ktiles;
+      if constexpr (FAST) {
+        const int kf = min(kt + DEPTH, ktiles - 1) * BK;
+        if constexpr (DEPTH == 1) load_tile(kf, cur, fast_tag);
+        else load_tile(kf, nxt, fast_tag);
+      } else if (DEPTH == 1) {
+        if (more) load_tile((kt + 1) * BK, cur, fast_tag);
       } else if (kt + DEPTH < ktiles) {
-        load_tile((kt + DEPTH) * BK, nxt);
+        load_tile((kt + DEPTH) * BK, nxt, fast_tag);
       }
       float af[FM][KH], bf[FN][KH];
 #pragma unroll
@@ -224,25 +239,30 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, 1 % DEPTH>;
     using S2 = std::integral_constant<int, 2 % DEPTH>;
-    load_tile(0, S0{});
-    store_tile(0, S0{});
-    if constexpr (DEPTH >= 2) {
-      if (ktiles > 1) load_tile(BK, S1{});
-    }
-    if constexpr (DEPTH >= 3) {
-      if (ktiles > 2) load_tile(2 * BK, S2{});
-    }
-    __syncthreads();
-    // DEPTH steps per trip, so that every slot index is a compile-time tag
-    for (int kt = 0; kt < ktiles; kt += DEPTH) {
-      step(kt, S1{}, S0{});
+    auto run = [&](auto fast_tag) {
+      constexpr bool FAST = decltype(fast_tag)::value;
+      load_tile(0, S0{}, fast_tag);
+      store_tile(0, S0{});
       if constexpr (DEPTH >= 2) {
-        if (kt + 1 < ktiles) step(kt + 1, S2{}, S1{});
+        if (FAST || ktiles > 1) load_tile(min(1, ktiles - 1) * BK, S1{}, fast_tag);
       }
       if constexpr (DEPTH >= 3) {
-        if (kt + 2 < ktiles) step(kt + 2, S0{}, S2{});
+        if (FAST || ktiles > 2) load_tile(min(2, ktiles - 1) * BK, S2{}, fast_tag);
       }
-    }
+      __syncthreads();
+      // DEPTH steps per trip, so that every slot index is a compile-time tag
+      for (int kt = 0; kt < ktiles; kt += DEPTH) {
+        step(kt, S1{}, S0{}, fast_tag);
+        if constexpr (DEPTH >= 2) {
+          if (FAST || kt + 1 < ktiles) step(kt + 1, S2{}, S1{}, fast_tag);
+        }
+        if constexpr (DEPTH >= 3) {
+          if (FAST || kt + 2 < ktiles) step(kt + 2, S0{}, S2{}, fast_tag);
+        }
+      }
+    };
+    if (rows_in && cols_in && n % BK == 0 && ktiles % DEPTH == 0) run(std::true_type{});
+    else run(std::false_type{});
 
     float* __restrict__ C = d.C;
     if (rows_in && cols_in) {

@@ -129,6 +129,19 @@ def test_vecadd_bitexact_ragged(ns_name):
             assert_vecadd(o_mul, 11, r, n, req=1, mul=True)
 
 
+def test_vecadd_largest_serving_size_bitexact(ns_name):
+    # the largest vector of the serving workload (2^24), and one element past
+    # it, alone and as one group of three (one workgroup per 4096-element
+    # unit: 4097 units for the ragged one)
+    sizes = [1 << 24, (1 << 24) + 1, (1 << 24) - 5]
+    with hip_manager(ns_name, nranks=3, shm_bytes_per_rank=208 << 20, hbm_budget_bytes=2 << 30,
+                     policy=G.GVM_POLICY_GROUPED, batch_window_us=10_000_000):
+        res = run_ranks(ns_name, [[(1, 12, n, 0, False)] for n in sizes], barrier=threading.Barrier(3))
+        for r, n in enumerate(sizes):
+            (o,) = check_ok(res[r])
+            assert_vecadd(o, 12, r, n)
+
+
 def test_blackscholes_tolerance_ragged(ns_name):
     sizes = [1, 5, 2047, 2049, 100003, 1 << 20]
     with hip_manager(ns_name, nranks=len(sizes)):
