@@ -378,6 +378,35 @@ int main(int argc, char** argv) {
       }
       printf("{\"test\":\"pcie_pinned\",\"alloc\":\"%s\",\"bytes\":%zu,\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n",
              names[f], bytes, best[0], best[1], best[2]);
+      if (f == 0) {
+        // the same bytes in 4 MiB pieces, dealt round-robin over 1, 2 or 4
+        // streams per direction (one direction at a time, then both)
+        const size_t piece = size_t(4) << 20, np = bytes / piece;
+        hipStream_t ps[8];
+        for (auto& x : ps) CK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        for (int ns : {1, 2, 4}) {
+          double pb[3] = {0, 0, 0};
+          for (int rep = 0; rep < 4; ++rep) {
+            for (int dir = 0; dir < 3; ++dir) {  // 0 H2D, 1 D2H, 2 both
+              const double t0 = now_s();
+              for (size_t i = 0; i < np; ++i) {
+                if (dir != 1)
+                  CK(hipMemcpyAsync(static_cast<char*>(d1) + i * piece, static_cast<char*>(h1) + i * piece, piece,
+                                    hipMemcpyHostToDevice, ps[i % ns]));
+                if (dir != 0)
+                  CK(hipMemcpyAsync(static_cast<char*>(h2) + i * piece, static_cast<char*>(d2) + i * piece, piece,
+                                    hipMemcpyDeviceToHost, ps[4 + i % ns]));
+              }
+              for (auto& x : ps) CK(hipStreamSynchronize(x));
+              const double moved = (dir == 2 ? 2.0 : 1.0) * static_cast<double>(np * piece);
+              if (rep > 0) pb[dir] = std::max(pb[dir], moved / (now_s() - t0) / 1e9);
+            }
+          }
+          printf("{\"test\":\"pcie_pieces\",\"piece_bytes\":%zu,\"streams_per_direction\":%d,\"h2d_GBps\":%.1f,"
+                 "\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n", piece, ns, pb[0], pb[1], pb[2]);
+        }
+        for (auto& x : ps) CK(hipStreamDestroy(x));
+      }
       CK(hipHostFree(h1));
       CK(hipHostFree(h2));
     }
