@@ -66,6 +66,15 @@ bool request_layout(int kernel_id, uint64_t n, Layout* out) {
   }
 }
 
+uint64_t piece_bytes() {
+  static const uint64_t b = [] {
+    const char* e = getenv("GVM_PIECE_MB");
+    const long mb = e ? atol(e) : 8;
+    return static_cast<uint64_t>(mb >= 1 && mb <= 64 ? mb : 8) << 20;
+  }();
+  return b;
+}
+
 int cu_partition_masks(uint32_t latency_cus, uint32_t* latency_mask, uint32_t* bulk_mask) {
   if (latency_cus == 0 || latency_cus % 32 || latency_cus >= static_cast<uint32_t>(kPartitionCus)) return GVM_EINVAL;
   const uint32_t m = latency_cus / 32, full = m / 2;

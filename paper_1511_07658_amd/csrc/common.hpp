@@ -33,8 +33,10 @@ constexpr int kNumKernelIds = 6;  // kernel ids 1..5; index 0 collects mixed gra
 // Requests move between the ranks' shared memory, the pinned staging and the
 // device in pieces of this size (unless batch_timing asks for whole copies):
 // each piece's next hop starts as soon as it lands.
-constexpr uint64_t kPieceBytes = 4ull << 20;   // one host copy chunk: each piece lands on one worker
-inline uint32_t piece_count(uint64_t bytes) { return static_cast<uint32_t>((bytes + kPieceBytes - 1) / kPieceBytes); }
+// Bytes of one piece of a piecewise copy (default 8 MiB; GVM_PIECE_MB, read
+// once, overrides with 1..64).
+uint64_t piece_bytes();
+inline uint32_t piece_count(uint64_t bytes) { return static_cast<uint32_t>((bytes + piece_bytes() - 1) / piece_bytes()); }
 
 // A request whose copies total at most this many bytes keeps them on the
 // stream that runs its kernel: such a copy takes ~18 us on the link, less

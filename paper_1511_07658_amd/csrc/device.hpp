@@ -37,7 +37,7 @@ struct Job {
   int done_index = -1;
   int stage = kStageCopyIn;
   std::atomic<int> copies{0};   // host copy chunks still in flight
-  // Piecewise copies (kPieceBytes): the input's pieces go to the device as
+  // Piecewise copies (piece_bytes()): the input's pieces go to the device as
   // each lands in the pinned staging, the output's pieces come back to shared
   // memory as each leaves the device.
   bool local = false;            // small copies: on the kernel's own stream, whole

@@ -588,8 +588,8 @@ class HipDevice final : public Device {
     // leading pieces start while the rest is still on the link
     auto& evs = b->out_ev[static_cast<size_t>(j->done_index)];
     for (uint32_t i = 0; i < j->out_pieces; ++i) {
-      const uint64_t off = static_cast<uint64_t>(i) * kPieceBytes;
-      const int rc = timed_copy(j->pin + o + off, j->slot + o + off, std::min<uint64_t>(kPieceBytes, j->lay.out_bytes - off),
+      const uint64_t off = static_cast<uint64_t>(i) * piece_bytes();
+      const int rc = timed_copy(j->pin + o + off, j->slot + o + off, std::min<uint64_t>(piece_bytes(), j->lay.out_bytes - off),
                                 hipMemcpyDeviceToHost, s, &b->copies, i == 0);
       if (rc != GVM_OK) return rc;
       hipEvent_t e = sync_event(b);

@@ -438,9 +438,9 @@ bool Manager::complete_jobs() {
         j->status = n;
       } else {
         for (; j->out_taken < static_cast<uint32_t>(n); ++j->out_taken) {
-          const uint64_t off = static_cast<uint64_t>(j->out_taken) * kPieceBytes;
+          const uint64_t off = static_cast<uint64_t>(j->out_taken) * piece_bytes();
           copy_.submit(j->shm + j->req.off_out + off, j->pin + out_off + off,
-                       std::min<uint64_t>(kPieceBytes, j->lay.out_bytes - off), &j->copies);
+                       std::min<uint64_t>(piece_bytes(), j->lay.out_bytes - off), &j->copies);
           any = true;
         }
         if (j->out_taken < j->out_pieces) continue;
@@ -501,8 +501,8 @@ bool Manager::launch_ready() {
       if (j->pieces) {
         // each input piece goes to the device as soon as it is staged
         while (j->in_sent < j->in_pieces && j->in_pending[j->in_sent].load(std::memory_order_acquire) == 0) {
-          const uint64_t off = static_cast<uint64_t>(j->in_sent) * kPieceBytes;
-          const int rc = dev_->stream_in(j, off, std::min<uint64_t>(kPieceBytes, j->lay.in_bytes - off));
+          const uint64_t off = static_cast<uint64_t>(j->in_sent) * piece_bytes();
+          const int rc = dev_->stream_in(j, off, std::min<uint64_t>(piece_bytes(), j->lay.in_bytes - off));
           if (rc != GVM_OK && j->status == GVM_OK) j->status = rc;
           ++j->in_sent;
         }
@@ -616,8 +616,8 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
       j->in_pieces = piece_count(lay.in_bytes);
       j->in_pending.reset(new std::atomic<int>[j->in_pieces]());
       for (uint32_t i = 0; i < j->in_pieces; ++i) {
-        const uint64_t off = static_cast<uint64_t>(i) * kPieceBytes;
-        const uint64_t len = std::min<uint64_t>(kPieceBytes, lay.in_bytes - off);
+        const uint64_t off = static_cast<uint64_t>(i) * piece_bytes();
+        const uint64_t len = std::min<uint64_t>(piece_bytes(), lay.in_bytes - off);
         j->in_pending[i].store(0, std::memory_order_relaxed);
         copy_.submit(j->pin + off, j->shm + m.off_in + off, len, &j->in_pending[i]);
       }

@@ -379,12 +379,15 @@ int main(int argc, char** argv) {
       printf("{\"test\":\"pcie_pinned\",\"alloc\":\"%s\",\"bytes\":%zu,\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n",
              names[f], bytes, best[0], best[1], best[2]);
       if (f == 0) {
-        // the same bytes in 4 MiB pieces, dealt round-robin over 1, 2 or 4
+        // the same bytes in pieces of 2 to 16 MiB on one stream per
+        // direction, and in 4 MiB pieces dealt round-robin over 2 or 4
         // streams per direction (one direction at a time, then both)
-        const size_t piece = size_t(4) << 20, np = bytes / piece;
         hipStream_t ps[8];
         for (auto& x : ps) CK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-        for (int ns : {1, 2, 4}) {
+        const std::pair<int, int> shapes[] = {{2, 1}, {4, 1}, {8, 1}, {16, 1}, {4, 2}, {4, 4}};
+        for (const auto& sh : shapes) {
+          const size_t piece = size_t(sh.first) << 20, np = bytes / piece;
+          const int ns = sh.second;
           double pb[3] = {0, 0, 0};
           for (int rep = 0; rep < 4; ++rep) {
             for (int dir = 0; dir < 3; ++dir) {  // 0 H2D, 1 D2H, 2 both

@@ -9,7 +9,7 @@ size (a, b and c together) one after another.  For each request:
   clock;
 * GPU time: the time the request spends on the device inside the manager,
   its copy-in, kernel and copy-out device times (HIP events, ``batch_timing``;
-  a request's copies move in 4 MiB pieces and the piece times are summed).
+  a request's copies move in 8 MiB pieces and the piece times are summed).
 
 overhead = (turnaround - GPU time) / turnaround.  Two submission modes:
 ``copy`` (the rank's arrays are copied into its shared-memory data space by

@@ -149,8 +149,8 @@ def test_batch_barrier_holds_until_all_ranks_submit(ns_name):
 
 @pytest.mark.parametrize("timing", [0, 1])
 def test_large_requests_move_in_pieces(ns_name, timing):
-    # inputs of 10 and 18 pieces (4 MiB each, the last one short), outputs
-    # of 5 and 9; with batch_timing the copies are whole instead
+    # inputs of 5 and 9 pieces (8 MiB each, the last one short), outputs
+    # of 3 and 5; with batch_timing the copies are whole instead
     sizes = [5_000_003, 9_000_001]
     with Manager(ns_name, nranks=2, mode=G.GVM_MODE_SERVING, batch_timing=timing,
                  shm_bytes_per_rank=(3 * max(sizes) + 8) * 4 + (1 << 20), hbm_budget_bytes=1 << 30):
