@@ -38,11 +38,21 @@ namespace {
 // per k-step remains.  Interior tiles take unchecked loads and stores; edge
 // tiles check every element and read zeros outside the matrix.
 //
+// PIPE variant: the fragments of the next k-tile are read from LDS into a
+// second register set while the MFMAs of the current one run, so no k-step
+// starts by waiting for LDS.  Tile t is written to LDS buffer t % 2 during
+// step t - 2, its fragments read during step t - 1 and multiplied in step t;
+// one barrier at the end of each step orders both hazards (a write of tile
+// t + 2 follows every read of tile t, which shares its buffer; a read of
+// tile t + 1 follows every write of it).  Tile 0's fragments are read in the
+// prologue, so a barrier follows them before step 0 writes tile 2.  The k
+// order of every C element is the same as without PIPE.
+//
 // Persistent grid, XCD-aware: the units (tiles, requests in order, tiles of a
 // request row-major) are dealt to the 8 XCDs in contiguous blocks, so that
 // tiles sharing rows of A and columns of B share an L2.
 
-template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH, bool VEC>
+template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH, bool VEC, bool PIPE>
 __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) {
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM, TN = BN / WN;
@@ -56,6 +66,7 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
   static_assert(KH % 4 == 0, "BK must be a multiple of 8");
   static_assert(A4 >= 1 && B4 >= 1 && A4 * NT * 4 == BM * BK && B4 * NT * 4 == BK * BN, "tile/threads mismatch");
   static_assert(DEPTH >= 1 && DEPTH <= 3, "global prefetch depth is one to three k-tiles");
+  static_assert(!PIPE || DEPTH <= 2, "the pipelined loop takes a fetch depth of one or two");
 
   __shared__ __attribute__((aligned(16))) float As[2][BM * AST];
   __shared__ __attribute__((aligned(16))) float Bs[2][BT ? BN * BST : BK * BST];
@@ -261,8 +272,114 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
         }
       }
     };
-    if (rows_in && cols_in && n % BK == 0 && ktiles % DEPTH == 0) run(std::true_type{});
-    else run(std::false_type{});
+    // ---- PIPE: fragments of tile kt + 1 read during the MFMAs of tile kt
+    float pa[2][FM][KH], pb[2][FN][KH];
+    auto read_frags = [&](int buf, auto fset_tag) {
+      constexpr int F = decltype(fset_tag)::value;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const float* src = &As[buf][(wm * TM + i * 32 + li) * AST + lg * KH];
+#pragma unroll
+        for (int j = 0; j < KH; j += 4) {
+          const f32x4 x = *reinterpret_cast<const f32x4*>(src + j);
+          pa[F][i][j] = x.x; pa[F][i][j + 1] = x.y; pa[F][i][j + 2] = x.z; pa[F][i][j + 3] = x.w;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < FN; ++i) {
+        if (BT) {
+          const float* src = &Bs[buf][(wn * TN + i * 32 + li) * BST + lg * KH];
+#pragma unroll
+          for (int j = 0; j < KH; j += 4) {
+            const f32x4 x = *reinterpret_cast<const f32x4*>(src + j);
+            pb[F][i][j] = x.x; pb[F][i][j + 1] = x.y; pb[F][i][j + 2] = x.z; pb[F][i][j + 3] = x.w;
+          }
+        } else {
+          const float* src = &Bs[buf][(lg * KH) * BST + wn * TN + i * 32 + li];
+#pragma unroll
+          for (int j = 0; j < KH; ++j) pb[F][i][j] = src[j * BST];
+        }
+      }
+    };
+    // Step kt: MFMAs of tile kt (fragment set `fc`), fragments of tile
+    // kt + 1 into set `fn`; half-way, tile kt + 2 (register slot `ws`) goes
+    // to LDS buffer kt % 2 and the fetch of tile kt + 2 + DEPTH takes its
+    // slot.  FAST: the same instructions every step, indexes clamped to the
+    // last k-tile (the extra reads and writes land where no step uses them).
+    //
+    // The MFMAs touch no memory, so the compiler may move them across the
+    // barrier; the two empty asm statements keep each step's MFMAs between
+    // the LDS reads of the next fragments and the step's barrier (the first
+    // makes the current fragments appear to change after the reads, the
+    // second makes the last MFMA of each accumulator chain appear to be read
+    // before the barrier), so the barrier's wait for those reads is covered
+    // by the step's MFMAs.
+    auto step_pipe = [&](int kt, auto fc, auto fn, auto ws, auto fast_tag) {
+      constexpr bool FAST = decltype(fast_tag)::value;
+      constexpr int FC = decltype(fc)::value;
+      const int buf = kt & 1;
+      if (FAST || kt + 1 < ktiles) read_frags(buf ^ 1, fn);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int s = 0; s < KH; ++s) asm volatile("" : "+v"(pa[FC][i][s])::"memory");
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int s = 0; s < KH; ++s) asm volatile("" : "+v"(pb[FC][j][s])::"memory");
+#pragma unroll
+      for (int s = 0; s < KH; ++s) {
+        if (s == KH / 2 && (FAST || kt + 2 < ktiles)) {
+          store_tile(buf, ws);
+          if constexpr (FAST) load_tile(min(kt + 2 + DEPTH, ktiles - 1) * BK, ws, fast_tag);
+          else if (kt + 2 + DEPTH < ktiles) load_tile((kt + 2 + DEPTH) * BK, ws, fast_tag);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[FC][i][s], pb[FC][j][s], acc[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) asm volatile("" ::"v"(acc[i][j][15]) : "memory");
+      __syncthreads();
+    };
+    using F0 = std::integral_constant<int, 0>;
+    using F1 = std::integral_constant<int, 1>;
+    using W0 = std::integral_constant<int, 2 % DEPTH>;   // slot of tile kt + 2, kt even
+    using W1 = std::integral_constant<int, 3 % DEPTH>;   // slot of tile kt + 3
+    auto run_pipe = [&](auto fast_tag) {
+      constexpr bool FAST = decltype(fast_tag)::value;
+      load_tile(0, S0{}, fast_tag);
+      store_tile(0, S0{});
+      if (FAST || ktiles > 1) {
+        load_tile(min(1, ktiles - 1) * BK, S1{}, fast_tag);
+        store_tile(1, S1{});
+      }
+      // tiles 2 .. 1 + DEPTH into their slots
+      if (FAST || ktiles > 2) load_tile(min(2, ktiles - 1) * BK, W0{}, fast_tag);
+      if constexpr (DEPTH >= 2) {
+        if (FAST || ktiles > 3) load_tile(min(3, ktiles - 1) * BK, W1{}, fast_tag);
+      }
+      __syncthreads();
+      read_frags(0, F0{});
+      // step 0 writes tile 2 over tile 0's buffer: every wave must have read
+      // tile 0's fragments first
+      __syncthreads();
+      for (int kt = 0; kt < ktiles; kt += 2) {
+        step_pipe(kt, F0{}, F1{}, W0{}, fast_tag);
+        if (FAST || kt + 1 < ktiles) step_pipe(kt + 1, F1{}, F0{}, W1{}, fast_tag);
+      }
+    };
+    if constexpr (PIPE) {
+      if (rows_in && cols_in && n % BK == 0 && ktiles % 2 == 0) run_pipe(std::true_type{});
+      else run_pipe(std::false_type{});
+    } else {
+      if (rows_in && cols_in && n % BK == 0 && ktiles % DEPTH == 0) run(std::true_type{});
+      else run(std::false_type{});
+    }
 
     float* __restrict__ C = d.C;
     if (rows_in && cols_in) {
@@ -319,6 +436,13 @@ const GemmConfig kGemmConfigs[] = {
     {19, 256, 128, 16, 4, 2, false},
     {20, 256, 128, 32, 4, 2, false},
     {21, 128, 128, 16, 2, 2, false},
+    // fragments of the next k-tile read during the current MFMAs (PIPE), two ahead
+    {22, 256, 128, 16, 4, 2, false},
+    {23, 128, 128, 32, 2, 2, false},
+    {24, 128, 128, 16, 2, 2, false},
+    {25, 64, 128, 16, 2, 2, false},
+    // the same with one k-tile fetched ahead (a fetch still has a whole step)
+    {26, 256, 128, 16, 4, 2, false},
 };
 constexpr int kNumGemmConfigs = sizeof(kGemmConfigs) / sizeof(kGemmConfigs[0]);
 
@@ -326,14 +450,14 @@ int g_forced_config = -1;
 
 #include "gemm_tiles.inc"   // kTileTable: (n_max, config index) rows written by the tuner
 
-template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH = 1>
+template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH = 1, bool PIPE = false>
 hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap) {
   constexpr int NT = WM * WN * 64;
   int cap = grid_cap > 0 ? grid_cap : 256 * 2;
   int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
   if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
-  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, true>, grid, NT, s, g)
-             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, false>, grid, NT, s, g);
+  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, true, PIPE>, grid, NT, s, g)
+             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, false, PIPE>, grid, NT, s, g);
 }
 
 }  // namespace
@@ -395,6 +519,11 @@ hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s,
     case 19: return launch_cfg<256, 128, 16, 4, 2, false, 3>(g, vec, s, grid_cap);
     case 20: return launch_cfg<256, 128, 32, 4, 2, false, 3>(g, vec, s, grid_cap);
     case 21: return launch_cfg<128, 128, 16, 2, 2, false, 3>(g, vec, s, grid_cap);
+    case 22: return launch_cfg<256, 128, 16, 4, 2, false, 2, true>(g, vec, s, grid_cap);
+    case 23: return launch_cfg<128, 128, 32, 2, 2, false, 2, true>(g, vec, s, grid_cap);
+    case 24: return launch_cfg<128, 128, 16, 2, 2, false, 2, true>(g, vec, s, grid_cap);
+    case 25: return launch_cfg<64, 128, 16, 2, 2, false, 2, true>(g, vec, s, grid_cap);
+    case 26: return launch_cfg<256, 128, 16, 4, 2, false, 1, true>(g, vec, s, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }

@@ -192,7 +192,7 @@ def test_same_bk_tile_configurations_are_bit_identical():
     # a C element's k order depends on BK alone, so every configuration of
     # one BK gives the same bits (what lets a BK class share one launch)
     from paper_1511_07658_amd.tune import CONFIG_NAMES
-    for n in (96, 200, 515):
+    for n in (96, 200, 384, 515):   # 384: interior tiles take the branch-free loop
         A, B = wl.sgemm_inputs(16, 0, n)
         x = wl.pack_request(3, A, B)
         by_bk = {}
@@ -231,6 +231,36 @@ def test_sgemm_size_mix_matches_plain(ns_name):
         assert rc == 0
         assert spmd.digest(o) == res[r]["results"][0]["digest"], (r, n)
         assert_sgemm(o, cfg, r, n)
+
+
+def test_pipelined_tiles_under_load_match_plain(ns_name):
+    # the configurations that read the next k-tile's fragments during the
+    # MFMAs, in grouped launches of 8 x 1024 where two workgroups share each
+    # CU, so that a workgroup's waves drift apart (a missing barrier shows
+    # there, not in a launch with one workgroup per CU): every result equals
+    # the plain path's bits for the same configuration
+    from paper_1511_07658_amd.tune import CONFIG_NAMES
+    n, nr = 1024, 8
+    pipelined = [i for i, name in enumerate(CONFIG_NAMES) if name.endswith("P")]
+    assert pipelined
+    jobs = [[(3, 61, n, 0, False), (3, 61, n, 1, False)] for _ in range(nr)]
+    for c in pipelined:
+        os.environ["GVM_SGEMM_CONFIG"] = str(c)
+        try:
+            with hip_manager(f"{ns_name}.{c}", nranks=nr, shm_bytes_per_rank=16 << 20,
+                             policy=G.GVM_POLICY_GROUPED, batch_window_us=10_000_000):
+                res = run_ranks(f"{ns_name}.{c}", jobs, barrier=threading.Barrier(nr))
+            for r in range(nr):
+                for q in range(2):
+                    jr = res[r]["results"][q]
+                    assert jr["status"] == 0, (CONFIG_NAMES[c], r, q)
+                    x = spmd.make_input(3, 61, r, n, q, False)
+                    o = np.empty(n * n, np.float32)
+                    rc, _ = G.gvm_plain_run(3, x, o, n)
+                    assert rc == 0, G.gvm_last_error()
+                    assert spmd.digest(o) == jr["digest"], (CONFIG_NAMES[c], r, q)
+        finally:
+            del os.environ["GVM_SGEMM_CONFIG"]
 
 
 def test_config1_four_ranks_vecadd(ns_name):
