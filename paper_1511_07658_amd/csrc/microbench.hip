@@ -456,9 +456,10 @@ int main(int argc, char** argv) {
     free(pageable);
   } else if (what == "latency") {
     // launch -> completion observed by the host, for an empty kernel, by
-    // event query, by stream synchronize and by a flag in pinned host memory
-    // that a trailing kernel stores (vector store, system-scope release);
-    // and the cost of a 1.3 KiB kernel argument
+    // event query, by stream synchronize, by a flag in pinned host memory
+    // that a trailing kernel stores (vector store, system-scope release) and
+    // by a flag that the stream itself writes (hipStreamWriteValue64); and
+    // the cost of a 1.3 KiB kernel argument
     const int iters = argc > 2 ? atoi(argv[2]) : 2000;
     hipStream_t s;
     CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -467,6 +468,10 @@ int main(int argc, char** argv) {
     uint32_t* flag = nullptr;
     CK(hipHostMalloc(reinterpret_cast<void**>(&flag), 4096, hipHostMallocDefault));
     *flag = 0;
+    uint64_t* flag64 = reinterpret_cast<uint64_t*>(flag + 16);   // its own 64-byte line
+    *flag64 = 0;
+    void* flag64_dev = nullptr;
+    CK(hipHostGetDevicePointer(&flag64_dev, flag64, 0));
     Big big;
     memset(&big, 0, sizeof(big));
     hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, s, 0);
@@ -482,6 +487,10 @@ int main(int argc, char** argv) {
           }
         } else if (mode == 1) {
           CK(hipStreamSynchronize(s));
+        } else if (mode == 4) {
+          CK(hipStreamWriteValue64(s, flag64_dev, static_cast<uint64_t>(i + 1), 0));
+          while (__atomic_load_n(flag64, __ATOMIC_ACQUIRE) != static_cast<uint64_t>(i + 1)) {
+          }
         } else {
           hipLaunchKernelGGL(signal_kernel, dim3(1), dim3(64), 0, s, flag, static_cast<uint32_t>(i + 1));
           while (__atomic_load_n(flag, __ATOMIC_ACQUIRE) != static_cast<uint32_t>(i + 1)) {
@@ -490,10 +499,10 @@ int main(int argc, char** argv) {
       }
       return (now_s() - t0) / iters * 1e6;
     };
-    const double q = run(0), sy = run(1), wv = run(2), big_q = run(3);
+    const double q = run(0), sy = run(1), wv = run(2), big_q = run(3), sw = run(4);
     printf("{\"test\":\"latency\",\"iters\":%d,\"event_query_us\":%.2f,\"stream_sync_us\":%.2f,"
-           "\"host_flag_us\":%.2f,\"big_arg_event_query_us\":%.2f,\"big_arg_bytes\":%zu}\n",
-           iters, q, sy, wv, big_q, sizeof(Big));
+           "\"host_flag_us\":%.2f,\"stream_write_value_us\":%.2f,\"big_arg_event_query_us\":%.2f,\"big_arg_bytes\":%zu}\n",
+           iters, q, sy, wv, sw, big_q, sizeof(Big));
     CK(hipHostFree(flag));
   } else {
     fprintf(stderr, "unknown test %s\n", what.c_str());
