@@ -491,3 +491,29 @@ def test_auto_policy_size_rule(ns_name, n, expect):
         pl = G.gvm_stats_json()["device"]["policy_launches"]
     other = "ps2" if expect == "grouped" else "grouped"
     assert pl[expect] >= 1 and pl[other] == 0, pl
+
+
+def test_tile_configuration_names_match_the_compiled_table():
+    # the tuner's names and count, the kernel's configuration table, the
+    # launch switch and the size table must describe the same configurations
+    import re
+    from paper_1511_07658_amd import tune
+    csrc = os.path.join(os.path.dirname(G.__file__), "csrc")
+    src = open(os.path.join(csrc, "sgemm.hip")).read()
+    rows = re.findall(r"\{(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (true|false)\}", src)
+    assert [int(r[0]) for r in rows] == list(range(tune.NUM_CONFIGS))
+    assert len(tune.CONFIG_NAMES) == tune.NUM_CONFIGS
+    for (idx, bm, bn, bk, wm, wn, bt), name in zip(rows, tune.CONFIG_NAMES):
+        m = re.match(r"(\d+)x(\d+)x(\d+)([TR])", name)
+        assert m and m.groups() == (bm, bn, bk, "T" if bt == "true" else "R"), (idx, name)
+    cases = [int(c) for c in re.findall(r"case (\d+): return launch_cfg<", src)]
+    assert cases == list(range(tune.NUM_CONFIGS))
+    # the launch switch instantiates the same shape as the table row
+    for c, (bm, bn, bk, wm, wn, bt) in zip(cases, re.findall(
+            r"case \d+: return launch_cfg<(\d+), (\d+), (\d+), (\d+), (\d+), (true|false)", src)):
+        assert (bm, bn, bk, wm, wn, bt) == rows[c][1:], c
+    table = open(os.path.join(csrc, "gemm_tiles.inc")).read()
+    for n, c in re.findall(r"\{(\d+)u, (\d+)\}", table):
+        assert 0 <= int(c) < tune.NUM_CONFIGS, (n, c)
+    mix = int(re.search(r"constexpr int kMixConfig = (\d+);", open(os.path.join(csrc, "device_hip.cpp")).read()).group(1))
+    assert tune.config_bk(mix) == 16
