@@ -212,15 +212,45 @@ def step_detail(rr):
             "last_submitter_counts": last.tolist()}
 
 
-def plain_rank(kernel_id, n, cfg_idx, rank, barrier):
+PLAIN_WARM_N = {G.GVM_K_VECADD: 4096, G.GVM_K_VECMUL: 4096, G.GVM_K_BLACKSCHOLES: 4096, G.GVM_K_SGEMM: 64,
+                G.GVM_K_EP: 4096}
+
+
+def plain_rank(kernel_id, n, cfg_idx, rank, barrier, warm=False, baton=None):
     """One process of the plain method (no virtualization): its own device
-    context, pageable copies, the same kernel code object (Section 4.1)."""
+    context, pageable copies, the same kernel code object (Section 4.1).
+
+    Variants of the baseline:
+    * cold (default): the context is created inside the timed region, as in
+      the paper's turnaround (T_init included);
+    * ``warm``: a small request of the same kernel runs before the start
+      barrier, so context creation and code-object loading fall outside it;
+    * ``baton`` (a shared turn counter and its condition): the processes run
+      their GPU phases one after another in rank order, the sequential
+      execution that Eq. 1 models, instead of letting the device's
+      scheduler interleave them."""
     x = spmd.make_input(kernel_id, cfg_idx, rank, n)
     out = np.empty(G.out_elems(kernel_id, n), np.float32)
     G.lib()
+    args = (float(np.float32(wl.BS_RATE)), float(np.float32(wl.BS_VOLATILITY)))
+    if warm:
+        m = PLAIN_WARM_N[kernel_id]
+        wx = spmd.make_input(kernel_id, cfg_idx, rank, m)
+        wo = np.empty(G.out_elems(kernel_id, m), np.float32)
+        rc, _ = G.gvm_plain_run(kernel_id, wx, wo, m, *args)
+        if rc != 0:
+            return {"rc": rc, "t0": 0, "t1": 0, "stages": [0.0] * 6, "digest": ""}
     barrier.wait()
     t0 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
-    rc, stages = G.gvm_plain_run(kernel_id, x, out, n, float(np.float32(wl.BS_RATE)), float(np.float32(wl.BS_VOLATILITY)))
+    if baton is not None:
+        turn, cond = baton
+        with cond:
+            cond.wait_for(lambda: turn.value == rank)
+    rc, stages = G.gvm_plain_run(kernel_id, x, out, n, *args)
+    if baton is not None:
+        with cond:
+            turn.value += 1
+            cond.notify_all()
     t1 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
     return {"rc": rc, "t0": t0, "t1": t1, "stages": stages, "digest": spmd.digest(out)}
 
@@ -318,24 +348,35 @@ def main(argv=None):
     ctx = None if a.rank_threads else spmd.context()
     mixed = len(kinds) > 1
 
-    # 1. plain per-process baseline (before this process touches the GPU)
-    plain = None
-    if not a.no_plain and not a.loopback and nranks <= 16:
-        log(f"plain baseline: {nranks} processes, each its own context")
+    # 1. plain per-process baselines (before this process touches the GPU):
+    # cold with the device's own scheduling (the paper's turnaround), warm
+    # (contexts created before the start), and cold with the GPU phases run
+    # one rank after another (Eq. 1)
+    plain = plain_warm = plain_seq = None
+
+    def run_plain(warm=False, seq=False):
         bar = ctx.Barrier(nranks)
-        res = spmd.run_processes(plain_rank, [(k, n, c, r, bar) for r, (k, n, c) in enumerate(specs)], timeout_s=300)
+        baton = (ctx.Value("i", 0), ctx.Condition()) if seq else None
+        res = spmd.run_processes(plain_rank, [(k, n, c, r, bar, warm, baton) for r, (k, n, c) in enumerate(specs)],
+                                 timeout_s=300)
         bad = [r for r in res if r["rc"] != 0]
         if bad:
             raise SystemExit(f"plain baseline failed: {bad}")
         turn = (max(r["t1"] for r in res) - min(r["t0"] for r in res)) * 1e-9
         stages = np.array([r["stages"] for r in res])
-        plain = {"turnaround_s": round(turn, 6),
-                 "value": round((flop_total if main_kernel == G.GVM_K_SGEMM else
-                                 sum(n for _, n, _ in specs) if main_kernel == G.GVM_K_EP else bytes_total)
-                                / turn / 1e9, 3),
-                 "mean_stage_s": dict(zip(["init", "alloc", "copy_in", "kernel", "copy_out", "free"],
-                                          [round(float(v), 6) for v in stages.mean(axis=0)])),
-                 "digests": [r["digest"] for r in res]}
+        return {"turnaround_s": round(turn, 6),
+                "value": round((flop_total if main_kernel == G.GVM_K_SGEMM else
+                                sum(n for _, n, _ in specs) if main_kernel == G.GVM_K_EP else bytes_total)
+                               / turn / 1e9, 3),
+                "mean_stage_s": dict(zip(["init", "alloc", "copy_in", "kernel", "copy_out", "free"],
+                                         [round(float(v), 6) for v in stages.mean(axis=0)])),
+                "digests": [r["digest"] for r in res]}
+
+    if not a.no_plain and not a.loopback and nranks <= 16:
+        log(f"plain baseline: {nranks} processes, each its own context (cold, warm, sequential)")
+        plain = run_plain()
+        plain_warm = run_plain(warm=True)
+        plain_seq = run_plain(seq=True)
 
     # 2. the GVM manager in this process, ranks in forked processes
     ns = f"gvm.bench.{os.getpid()}"
@@ -462,10 +503,16 @@ def main(argv=None):
         "e2e_pcie": {"value": round(e2e_value, 3), "unit": unit, "steps": a.e2e_steps,
                      "ms_per_step": round(e2e / max(a.e2e_steps, 1) * 1e3, 3)},
         "plain": None if plain is None else {k: v for k, v in plain.items() if k != "digests"},
+        "plain_warm": None if plain_warm is None else {k: v for k, v in plain_warm.items() if k != "digests"},
+        "plain_sequential": None if plain_seq is None else {k: v for k, v in plain_seq.items() if k != "digests"},
         "gvm_vs_plain_turnaround": None if plain is None else round(plain["turnaround_s"] / (e2e / max(a.e2e_steps, 1)), 3),
+        "gvm_vs_plain_warm_turnaround": None if plain_warm is None else round(
+            plain_warm["turnaround_s"] / (e2e / max(a.e2e_steps, 1)), 3),
+        "gvm_vs_plain_sequential_turnaround": None if plain_seq is None else round(
+            plain_seq["turnaround_s"] / (e2e / max(a.e2e_steps, 1)), 3),
         **extra,
-        "results_unchanged_by_virtualization": all(r["same_bytes"] for r in rr) and (
-            plain is None or [r["digest"] for r in rr] == plain["digests"]),
+        "results_unchanged_by_virtualization": all(r["same_bytes"] for r in rr) and all(
+            p is None or [r["digest"] for r in rr] == p["digests"] for p in (plain, plain_warm, plain_seq)),
         "host": {"nproc": os.cpu_count(), "machine": platform.machine(),
                  "GPU_MAX_HW_QUEUES": os.environ.get("GPU_MAX_HW_QUEUES")},
     }
