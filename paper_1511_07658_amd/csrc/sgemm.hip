@@ -443,6 +443,9 @@ const GemmConfig kGemmConfigs[] = {
     {25, 64, 128, 16, 2, 2, false},
     // the same with one k-tile fetched ahead (a fetch still has a whole step)
     {26, 256, 128, 16, 4, 2, false},
+    // larger tiles for large n, two ahead
+    {27, 128, 256, 32, 2, 4, false},
+    {28, 256, 256, 16, 4, 2, false},
 };
 constexpr int kNumGemmConfigs = sizeof(kGemmConfigs) / sizeof(kGemmConfigs[0]);
 
@@ -524,6 +527,8 @@ hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s,
     case 24: return launch_cfg<128, 128, 16, 2, 2, false, 2, true>(g, vec, s, grid_cap);
     case 25: return launch_cfg<64, 128, 16, 2, 2, false, 2, true>(g, vec, s, grid_cap);
     case 26: return launch_cfg<256, 128, 16, 4, 2, false, 1, true>(g, vec, s, grid_cap);
+    case 27: return launch_cfg<128, 256, 32, 2, 4, false, 2>(g, vec, s, grid_cap);
+    case 28: return launch_cfg<256, 256, 16, 4, 2, false, 2>(g, vec, s, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }
