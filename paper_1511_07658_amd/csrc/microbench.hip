@@ -12,6 +12,7 @@
 //   init                  time to create the device context in a fresh process
 // Prints one JSON object per test.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <chrono>
@@ -463,8 +464,10 @@ int main(int argc, char** argv) {
     const int iters = argc > 2 ? atoi(argv[2]) : 2000;
     hipStream_t s;
     CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    hipEvent_t ev;
+    hipEvent_t ev, te0, te1;
     CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    CK(hipEventCreate(&te0));
+    CK(hipEventCreate(&te1));
     uint32_t* flag = nullptr;
     CK(hipHostMalloc(reinterpret_cast<void**>(&flag), 4096, hipHostMallocDefault));
     *flag = 0;
@@ -479,8 +482,31 @@ int main(int argc, char** argv) {
     auto run = [&](int mode) {
       double t0 = now_s();
       for (int i = 0; i < iters; ++i) {
+        if (mode == 5 || mode == 6 || mode == 8 || mode == 9) {
+          // completion (and timing) events carried by the dispatch itself
+          if (mode == 8) CK(hipEventRecord(te0, s));
+          hipEvent_t stop = mode == 9 ? ev : te1;
+          hipExtLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, s, mode == 6 ? te0 : nullptr, stop, 0, i);
+          while (hipEventQuery(stop) == hipErrorNotReady) {
+          }
+          continue;
+        }
+        if (mode == 10) {   // timing marker after the launch only
+          hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, s, i);
+          CK(hipEventRecord(te1, s));
+          while (hipEventQuery(te1) == hipErrorNotReady) {
+          }
+          continue;
+        }
+        if (mode == 7) CK(hipEventRecord(te0, s));   // the manager's pattern: markers around the launch
         if (mode == 3) hipLaunchKernelGGL(big_arg_kernel, dim3(1), dim3(64), 0, s, big);
         else hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, s, i);
+        if (mode == 7) {
+          CK(hipEventRecord(te1, s));
+          while (hipEventQuery(te1) == hipErrorNotReady) {
+          }
+          continue;
+        }
         if (mode == 0 || mode == 3) {
           CK(hipEventRecord(ev, s));
           while (hipEventQuery(ev) == hipErrorNotReady) {
@@ -500,9 +526,13 @@ int main(int argc, char** argv) {
       return (now_s() - t0) / iters * 1e6;
     };
     const double q = run(0), sy = run(1), wv = run(2), big_q = run(3), sw = run(4);
+    const double ext_stop = run(5), ext_both = run(6), markers = run(7);
+    const double marker_then_ext = run(8), ext_untimed = run(9), marker_after = run(10);
     printf("{\"test\":\"latency\",\"iters\":%d,\"event_query_us\":%.2f,\"stream_sync_us\":%.2f,"
-           "\"host_flag_us\":%.2f,\"stream_write_value_us\":%.2f,\"big_arg_event_query_us\":%.2f,\"big_arg_bytes\":%zu}\n",
-           iters, q, sy, wv, sw, big_q, sizeof(Big));
+           "\"host_flag_us\":%.2f,\"stream_write_value_us\":%.2f,\"big_arg_event_query_us\":%.2f,\"big_arg_bytes\":%zu,"
+           "\"timed_markers_us\":%.2f,\"ext_launch_stop_event_us\":%.2f,\"ext_launch_start_stop_events_us\":%.2f,"
+           "\"timed_marker_then_ext_launch_us\":%.2f,\"ext_launch_untimed_stop_us\":%.2f,\"timed_marker_after_us\":%.2f}\n",
+           iters, q, sy, wv, sw, big_q, sizeof(Big), markers, ext_stop, ext_both, marker_then_ext, ext_untimed, marker_after);
     CK(hipHostFree(flag));
   } else {
     fprintf(stderr, "unknown test %s\n", what.c_str());
