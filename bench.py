@@ -55,11 +55,11 @@ PEAK_EP_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
 SGEMM_SOURCES = ("sgemm.hip", "group_device.hpp", "kernels.hpp", "gemm_tiles.inc")
 STREAM_SOURCES = ("stream_kernels.hip", "group_device.hpp", "kernels.hpp")
 MEASURED_TRAFFIC = {
-    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "77e39eebe5063494456286be8d5b0e3919434ba3344f2ecddec56f1e6c17a047",
+    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "452827a72b9d2496626dc6a41bb430ee412892a55e6c23e19a35f4b924dc6957",
                "fetch_kib": 32854.9, "fetch_factor": 2.000, "write_kib": 32768.0, "write_factor": 1.000},
-    "bs16": {"sources": STREAM_SOURCES, "kernels_sha256": "29520b632bad37ed5d5e371c2dfd48cd118b536b38ad6c680b22e4cf7e84d31f",
-             "fetch_kib": 393326.6, "fetch_factor": 2.000, "write_kib": 524289.6, "write_factor": 1.000},
-    "vecadd16": {"sources": STREAM_SOURCES, "kernels_sha256": "29520b632bad37ed5d5e371c2dfd48cd118b536b38ad6c680b22e4cf7e84d31f",
+    "bs16": {"sources": STREAM_SOURCES, "kernels_sha256": "b6e37850a81652cdfbfcb6ef5733e38694e16acd5b1e2a7223c8bda01e96637c",
+             "fetch_kib": 393326.6, "fetch_factor": 2.000, "write_kib": 524311.7, "write_factor": 1.000},
+    "vecadd16": {"sources": STREAM_SOURCES, "kernels_sha256": "b6e37850a81652cdfbfcb6ef5733e38694e16acd5b1e2a7223c8bda01e96637c",
                  "fetch_kib": 1048597.1, "fetch_factor": 2.000, "write_kib": 1048576.0, "write_factor": 1.000},
 }
 

@@ -658,9 +658,6 @@ class HipDevice final : public Device {
           t.bytes += by;
         }
         if (timed) HIPCHK(hipEventRecord(t.e0, s));
-        // the launch's end: completed by the kernel's own dispatch, not by a
-        // marker behind it, which the host sees about 3 us sooner
-        hipEvent_t stop = timed ? t.e1 : nullptr;
         hipError_t e = hipSuccess;
         if (k == GVM_K_VECADD || k == GVM_K_VECMUL) {
           VecGroup g{};
@@ -674,7 +671,7 @@ class HipDevice final : public Device {
             g.d[i].n = j->req.n;
           }
           finalize_vec_group(g);
-          e = (k == GVM_K_VECADD) ? launch_vecadd_group(g, s, 0, stop) : launch_vecmul_group(g, s, 0, stop);
+          e = (k == GVM_K_VECADD) ? launch_vecadd_group(g, s) : launch_vecmul_group(g, s);
         } else if (k == GVM_K_BLACKSCHOLES) {
           BsGroup g{};
           g.count = static_cast<uint32_t>(cnt);
@@ -693,7 +690,7 @@ class HipDevice final : public Device {
             g.d[i].n = n;
           }
           finalize_bs_group(g);
-          e = launch_bs_group(g, s, 0, stop);
+          e = launch_bs_group(g, s);
         } else if (k == GVM_K_SGEMM) {
           GemmGroup g{};
           g.count = static_cast<uint32_t>(cnt);
@@ -708,7 +705,7 @@ class HipDevice final : public Device {
           }
           finalize_gemm_group(g, cfgi);
           const bool mixed = v.front()->req.n != v.back()->req.n;
-          e = launch_sgemm_group(g, cfgi, s, mixed ? gemm_mix_grid() : 0, stop);
+          e = launch_sgemm_group(g, cfgi, s, mixed ? gemm_mix_grid() : 0);
         } else if (k == GVM_K_EP) {
           EpGroup g{};
           g.count = static_cast<uint32_t>(cnt);
@@ -720,12 +717,13 @@ class HipDevice final : public Device {
             g.d[i].n = j->req.n;
           }
           finalize_ep_group(g);
-          e = launch_ep_group(g, s, 0, stop);
+          e = launch_ep_group(g, s);
         } else {
           return fail(GVM_EINVAL, "unknown kernel id %d", k);
         }
         if (e != hipSuccess) return fail(GVM_EDEVICE, "kernel launch (%s): %s", kernel_name(k), hipGetErrorString(e));
         if (timed) {
+          HIPCHK(hipEventRecord(t.e1, s));
           b->timed.push_back(t);
           if (last_event) (*last_event)[si] = t.e1;  // also marks the end of this stream's kernels
         }

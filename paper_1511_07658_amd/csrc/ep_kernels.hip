@@ -176,12 +176,12 @@ void finalize_ep_group(EpGroup& g) {
   g.total_units = u;
 }
 
-hipError_t launch_ep_group(const EpGroup& g, hipStream_t s, int grid_cap, hipEvent_t stop) {
+hipError_t launch_ep_group(const EpGroup& g, hipStream_t s, int grid_cap) {
   const int cap = grid_cap > 0 ? grid_cap : kEpGrid;
   const int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(cap)));
   const hipError_t e = launch_group(ep_units_kernel, grid, kEpThreads, s, g);
   if (e != hipSuccess) return e;
-  return launch_group(ep_reduce_kernel, static_cast<int>(g.count), kEpThreads, s, g, stop);
+  return launch_group(ep_reduce_kernel, static_cast<int>(g.count), kEpThreads, s, g);
 }
 
 }  // namespace gvm

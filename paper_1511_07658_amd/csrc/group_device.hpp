@@ -1,8 +1,6 @@
 // Device-side helpers shared by the grouped kernels (hipcc only).
 #pragma once
 
-#include <hip/hip_ext.h>
-
 #include "kernels.hpp"
 
 namespace gvm {
@@ -25,17 +23,11 @@ __device__ __forceinline__ int find_request(const G& g, uint64_t u) {
   return lo;
 }
 
-// Launch `kernel(g)` on `s` (nothing for an empty grid).  A non-null `stop`
-// event is completed by the kernel's own dispatch (hipExtLaunchKernel), not
-// by a marker behind it: the host then sees the kernel done about 3 us
-// sooner (`gvm_microbench latency`).  An empty grid records `stop` on `s`.
+// Launch `kernel(g)` on `s` (nothing for an empty grid).
 template <class G>
-hipError_t launch_group(void (*kernel)(G), int grid, int block, hipStream_t s, const G& g, hipEvent_t stop = nullptr) {
-  if (grid <= 0) return stop ? hipEventRecord(stop, s) : hipSuccess;
+hipError_t launch_group(void (*kernel)(G), int grid, int block, hipStream_t s, const G& g) {
+  if (grid <= 0) return hipSuccess;
   void* args[] = {const_cast<G*>(&g)};
-  if (stop)
-    return hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block), args, 0, s, nullptr,
-                              stop, 0);
   return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block), args, 0, s);
 }
 

@@ -102,16 +102,14 @@ constexpr uint64_t kBsUnit = 4096;    // options per Black-Scholes work unit (th
                                       // recounts the units for its launch shape)
 
 // Persistent-grid launchers.  `grid_cap` bounds the number of workgroups
-// (0 = default for the kernel); a non-null `stop` event completes with the
-// (last) kernel of the launch.  Return hipSuccess or the launch error.
-hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap = 0, hipEvent_t stop = nullptr);
-hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap = 0, hipEvent_t stop = nullptr);
-hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap = 0, hipEvent_t stop = nullptr);
-hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap = 0,
-                              hipEvent_t stop = nullptr);
+// (0 = default for the kernel).  Return hipSuccess or the launch error.
+hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap = 0);
+hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap = 0);
+hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap = 0);
+hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap = 0);
 // EP-like tally: one launch over the work units of every request (partials),
 // then one workgroup per request sums its partials.
-hipError_t launch_ep_group(const EpGroup& g, hipStream_t s, int grid_cap = 0, hipEvent_t stop = nullptr);
+hipError_t launch_ep_group(const EpGroup& g, hipStream_t s, int grid_cap = 0);
 
 // Fill the unit bookkeeping of a group (unit_begin, tiles, totals).
 void finalize_vec_group(VecGroup& g);

@@ -454,13 +454,13 @@ int g_forced_config = -1;
 #include "gemm_tiles.inc"   // kTileTable: (n_max, config index) rows written by the tuner
 
 template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH = 1, bool PIPE = false>
-hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap, hipEvent_t stop) {
+hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap) {
   constexpr int NT = WM * WN * 64;
   int cap = grid_cap > 0 ? grid_cap : 256 * 2;
   int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
   if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
-  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, true, PIPE>, grid, NT, s, g, stop)
-             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, false, PIPE>, grid, NT, s, g, stop);
+  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, true, PIPE>, grid, NT, s, g)
+             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, false, PIPE>, grid, NT, s, g);
 }
 
 }  // namespace
@@ -493,42 +493,42 @@ void finalize_gemm_group(GemmGroup& g, int config_idx) {
   }
   g.total_units = u;
 }
-hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap, hipEvent_t stop) {
+hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap) {
   bool vec = true;
   for (uint32_t i = 0; i < g.count; ++i)
     if ((g.d[i].n % 4) != 0 || (reinterpret_cast<uintptr_t>(g.d[i].A) & 15) ||
         (reinterpret_cast<uintptr_t>(g.d[i].B) & 15))
       vec = false;
   switch (config_idx) {
-    case 0: return launch_cfg<64, 64, 16, 2, 2, true>(g, vec, s, grid_cap, stop);
-    case 1: return launch_cfg<128, 64, 16, 2, 2, true>(g, vec, s, grid_cap, stop);
-    case 2: return launch_cfg<128, 128, 16, 2, 2, true>(g, vec, s, grid_cap, stop);
-    case 3: return launch_cfg<128, 128, 32, 2, 2, true>(g, vec, s, grid_cap, stop);
-    case 4: return launch_cfg<256, 128, 16, 4, 2, true>(g, vec, s, grid_cap, stop);
-    case 5: return launch_cfg<128, 256, 16, 2, 4, true>(g, vec, s, grid_cap, stop);
-    case 6: return launch_cfg<256, 128, 32, 4, 2, true>(g, vec, s, grid_cap, stop);
-    case 7: return launch_cfg<64, 128, 16, 2, 2, true>(g, vec, s, grid_cap, stop);
-    case 8: return launch_cfg<128, 128, 16, 2, 2, false>(g, vec, s, grid_cap, stop);
-    case 9: return launch_cfg<256, 128, 16, 4, 2, false>(g, vec, s, grid_cap, stop);
-    case 10: return launch_cfg<128, 256, 16, 2, 4, false>(g, vec, s, grid_cap, stop);
-    case 11: return launch_cfg<256, 128, 32, 4, 2, false>(g, vec, s, grid_cap, stop);
-    case 12: return launch_cfg<128, 128, 32, 2, 2, false>(g, vec, s, grid_cap, stop);
-    case 13: return launch_cfg<64, 128, 16, 2, 2, false>(g, vec, s, grid_cap, stop);
-    case 14: return launch_cfg<256, 128, 16, 4, 2, false, 2>(g, vec, s, grid_cap, stop);
-    case 15: return launch_cfg<128, 128, 16, 2, 2, false, 2>(g, vec, s, grid_cap, stop);
-    case 16: return launch_cfg<256, 128, 32, 4, 2, false, 2>(g, vec, s, grid_cap, stop);
-    case 17: return launch_cfg<64, 128, 16, 2, 2, false, 2>(g, vec, s, grid_cap, stop);
-    case 18: return launch_cfg<128, 128, 32, 2, 2, false, 2>(g, vec, s, grid_cap, stop);
-    case 19: return launch_cfg<256, 128, 16, 4, 2, false, 3>(g, vec, s, grid_cap, stop);
-    case 20: return launch_cfg<256, 128, 32, 4, 2, false, 3>(g, vec, s, grid_cap, stop);
-    case 21: return launch_cfg<128, 128, 16, 2, 2, false, 3>(g, vec, s, grid_cap, stop);
-    case 22: return launch_cfg<256, 128, 16, 4, 2, false, 2, true>(g, vec, s, grid_cap, stop);
-    case 23: return launch_cfg<128, 128, 32, 2, 2, false, 2, true>(g, vec, s, grid_cap, stop);
-    case 24: return launch_cfg<128, 128, 16, 2, 2, false, 2, true>(g, vec, s, grid_cap, stop);
-    case 25: return launch_cfg<64, 128, 16, 2, 2, false, 2, true>(g, vec, s, grid_cap, stop);
-    case 26: return launch_cfg<256, 128, 16, 4, 2, false, 1, true>(g, vec, s, grid_cap, stop);
-    case 27: return launch_cfg<128, 256, 32, 2, 4, false, 2>(g, vec, s, grid_cap, stop);
-    case 28: return launch_cfg<256, 256, 16, 4, 2, false, 2>(g, vec, s, grid_cap, stop);
+    case 0: return launch_cfg<64, 64, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 1: return launch_cfg<128, 64, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 2: return launch_cfg<128, 128, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 3: return launch_cfg<128, 128, 32, 2, 2, true>(g, vec, s, grid_cap);
+    case 4: return launch_cfg<256, 128, 16, 4, 2, true>(g, vec, s, grid_cap);
+    case 5: return launch_cfg<128, 256, 16, 2, 4, true>(g, vec, s, grid_cap);
+    case 6: return launch_cfg<256, 128, 32, 4, 2, true>(g, vec, s, grid_cap);
+    case 7: return launch_cfg<64, 128, 16, 2, 2, true>(g, vec, s, grid_cap);
+    case 8: return launch_cfg<128, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
+    case 9: return launch_cfg<256, 128, 16, 4, 2, false>(g, vec, s, grid_cap);
+    case 10: return launch_cfg<128, 256, 16, 2, 4, false>(g, vec, s, grid_cap);
+    case 11: return launch_cfg<256, 128, 32, 4, 2, false>(g, vec, s, grid_cap);
+    case 12: return launch_cfg<128, 128, 32, 2, 2, false>(g, vec, s, grid_cap);
+    case 13: return launch_cfg<64, 128, 16, 2, 2, false>(g, vec, s, grid_cap);
+    case 14: return launch_cfg<256, 128, 16, 4, 2, false, 2>(g, vec, s, grid_cap);
+    case 15: return launch_cfg<128, 128, 16, 2, 2, false, 2>(g, vec, s, grid_cap);
+    case 16: return launch_cfg<256, 128, 32, 4, 2, false, 2>(g, vec, s, grid_cap);
+    case 17: return launch_cfg<64, 128, 16, 2, 2, false, 2>(g, vec, s, grid_cap);
+    case 18: return launch_cfg<128, 128, 32, 2, 2, false, 2>(g, vec, s, grid_cap);
+    case 19: return launch_cfg<256, 128, 16, 4, 2, false, 3>(g, vec, s, grid_cap);
+    case 20: return launch_cfg<256, 128, 32, 4, 2, false, 3>(g, vec, s, grid_cap);
+    case 21: return launch_cfg<128, 128, 16, 2, 2, false, 3>(g, vec, s, grid_cap);
+    case 22: return launch_cfg<256, 128, 16, 4, 2, false, 2, true>(g, vec, s, grid_cap);
+    case 23: return launch_cfg<128, 128, 32, 2, 2, false, 2, true>(g, vec, s, grid_cap);
+    case 24: return launch_cfg<128, 128, 16, 2, 2, false, 2, true>(g, vec, s, grid_cap);
+    case 25: return launch_cfg<64, 128, 16, 2, 2, false, 2, true>(g, vec, s, grid_cap);
+    case 26: return launch_cfg<256, 128, 16, 4, 2, false, 1, true>(g, vec, s, grid_cap);
+    case 27: return launch_cfg<128, 256, 32, 2, 4, false, 2>(g, vec, s, grid_cap);
+    case 28: return launch_cfg<256, 256, 16, 4, 2, false, 2>(g, vec, s, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }

@@ -241,20 +241,16 @@ bool stream_nt(uint64_t group_bytes) {
 }
 
 template <class Op>
-hipError_t launch_vec(const VecGroup& g, hipStream_t s, int grid_cap, hipEvent_t stop) {
+hipError_t launch_vec(const VecGroup& g, hipStream_t s, int grid_cap) {
   const int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap, kVecGrid))));
   const uint64_t bytes = g.total_units * kVecUnit * 12;
-  return stream_nt(bytes) ? launch_group(vec_group_kernel<Op, true>, grid, kThreads, s, g, stop)
-                          : launch_group(vec_group_kernel<Op, false>, grid, kThreads, s, g, stop);
+  return stream_nt(bytes) ? launch_group(vec_group_kernel<Op, true>, grid, kThreads, s, g)
+                          : launch_group(vec_group_kernel<Op, false>, grid, kThreads, s, g);
 }
 
-hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap, hipEvent_t stop) {
-  return launch_vec<AddOp>(g, s, grid_cap, stop);
-}
+hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap) { return launch_vec<AddOp>(g, s, grid_cap); }
 
-hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap, hipEvent_t stop) {
-  return launch_vec<MulOp>(g, s, grid_cap, stop);
-}
+hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap) { return launch_vec<MulOp>(g, s, grid_cap); }
 
 // Black-Scholes launch shape: float4 per thread per stream (GVM_BS_V4 = 2, 4
 // or 8), read once per process.
@@ -268,7 +264,7 @@ int bs_v4() {
 }
 
 template <int V4>
-hipError_t launch_bs_shape(const BsGroup& g0, hipStream_t s, int grid_cap, hipEvent_t stop) {
+hipError_t launch_bs_shape(const BsGroup& g0, hipStream_t s, int grid_cap) {
   // the unit size of the shape: recount the units of a copy of the group
   BsGroup g = g0;
   constexpr uint64_t kUnit = V4 * 4 * kThreads;
@@ -279,15 +275,15 @@ hipError_t launch_bs_shape(const BsGroup& g0, hipStream_t s, int grid_cap, hipEv
   }
   g.total_units = u;
   const int grid = static_cast<int>(std::min<uint64_t>(g.total_units, static_cast<uint64_t>(stream_grid(grid_cap, kBsGrid))));
-  return stream_nt(g.total_units * kUnit * 20) ? launch_group(bs_group_kernel<V4, true>, grid, kThreads, s, g, stop)
-                                               : launch_group(bs_group_kernel<V4, false>, grid, kThreads, s, g, stop);
+  return stream_nt(g.total_units * kUnit * 20) ? launch_group(bs_group_kernel<V4, true>, grid, kThreads, s, g)
+                                               : launch_group(bs_group_kernel<V4, false>, grid, kThreads, s, g);
 }
 
-hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap, hipEvent_t stop) {
+hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap) {
   switch (bs_v4()) {
-    case 2: return launch_bs_shape<2>(g, s, grid_cap, stop);
-    case 8: return launch_bs_shape<8>(g, s, grid_cap, stop);
-    default: return launch_bs_shape<4>(g, s, grid_cap, stop);
+    case 2: return launch_bs_shape<2>(g, s, grid_cap);
+    case 8: return launch_bs_shape<8>(g, s, grid_cap);
+    default: return launch_bs_shape<4>(g, s, grid_cap);
   }
 }
 
