@@ -134,7 +134,10 @@ typedef struct gvm_config {
   uint32_t batch_window_us;     /* batch mode: longest wait for the barrier after the first request */
   uint32_t max_inflight;        /* serving mode: requests on the device at once (0 = nranks) */
   uint32_t nstreams;            /* HIP streams for per-rank work (0 = min(nranks, 8)) */
-  uint32_t use_graphs;          /* 1: replay repeated batch templates as HIP graphs */
+  uint32_t use_graphs;          /* 1: grouped batches are captured once per template (ranks,
+                                   kernels, sizes, copy flags, buffers) into a HIP graph and
+                                   replayed with one hipGraphLaunch; requests then copy whole,
+                                   not in pieces.  GVM_EINVAL together with latency_cus */
   uint32_t backend;             /* gvm_backend */
   uint32_t copy_threads;        /* host threads for shared-memory <-> pinned copies (0 = 4) */
   float bs_rate;                /* Black-Scholes risk-free rate r (default 0.02) */

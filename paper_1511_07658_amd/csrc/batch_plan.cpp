@@ -1,0 +1,118 @@
+#include "batch_plan.hpp"
+
+#include "gvm.h"
+
+#include <algorithm>
+#include <map>
+#include <utility>
+
+namespace gvm {
+
+std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstreams) {
+  // One grouped launch per kernel id; SGEMM requests are grouped by the k
+  // depth BK of their size's tile configuration (a C element's k order
+  // depends on BK alone, so a class may share one launch and every request
+  // still gets the bits it gets alone).
+  std::map<std::pair<int, int>, std::vector<int>> classes;
+  for (size_t i = 0; i < jobs.size(); ++i) classes[{jobs[i].kernel_id, jobs[i].cls}].push_back(static_cast<int>(i));
+  std::vector<PlanGroup> out;
+  int next = 0;
+  for (auto& kv : classes) {
+    std::vector<int>& v = kv.second;
+    if (kv.first.first == GVM_K_SGEMM) {  // largest first, so the longest tiles start first
+      std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return jobs[x].n > jobs[y].n; });
+    }
+    for (size_t base = 0; base < v.size(); base += kPlanMaxGroup) {
+      PlanGroup g;
+      g.kernel_id = kv.first.first;
+      g.cls = kv.first.second;
+      g.stream = next++ % std::max(nstreams, 1);
+      const size_t end = std::min(v.size(), base + kPlanMaxGroup);
+      g.jobs.assign(v.begin() + static_cast<long>(base), v.begin() + static_cast<long>(end));
+      out.push_back(std::move(g));
+    }
+  }
+  return out;
+}
+
+BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool capture) {
+  BatchPlan p;
+  p.groups = plan_groups(jobs, 2);
+  p.stream_of.assign(jobs.size(), kPlanC0);
+  for (const PlanGroup& g : p.groups)
+    for (int j : g.jobs) p.stream_of[static_cast<size_t>(j)] = g.stream == 0 ? kPlanC0 : kPlanC1;
+
+  auto op = [&](int kind, int stream, int ev = -1, int job = -1, int group = -1) {
+    p.ops.push_back(PlanOp{kind, stream, ev, job, group});
+  };
+  auto record = [&](int stream) {
+    const int e = p.events++;
+    op(kOpRecord, stream, e);
+    return e;
+  };
+
+  if (capture) {  // fork: the other streams join the capture through C0
+    const int fork = record(kPlanC0);
+    for (int s : {kPlanH2D, kPlanD2H, kPlanC1}) op(kOpWait, s, fork);
+  }
+
+  // copy-ins in job order: small ones on C0 ahead of its kernels, the rest on
+  // the H2D FIFO (a piecewise input is already queued there)
+  bool fifo_in = false, local_in = false;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const PlanJob& j = jobs[i];
+    if (!j.copy_in) continue;
+    if (j.local) local_in = true;
+    else fifo_in = true;
+    if (!j.pieces) op(kOpCopyIn, j.local ? kPlanC0 : kPlanH2D, -1, static_cast<int>(i));
+  }
+  if (local_in && p.groups.size() > 1) op(kOpWait, kPlanC1, record(kPlanC0));  // C1's kernels may read C0's copies
+  if (fifo_in) {
+    const int e = record(kPlanH2D);
+    op(kOpWait, kPlanC0, e);
+    op(kOpWait, kPlanC1, e);
+  }
+
+  // grouped launches; the last one on each compute stream marks the end of
+  // that stream's kernels
+  int last[2] = {-1, -1};
+  for (size_t g = 0; g < p.groups.size(); ++g) {
+    const int s = p.groups[g].stream == 0 ? kPlanC0 : kPlanC1;
+    op(kOpLaunch, s, -1, -1, static_cast<int>(g));
+    last[s] = static_cast<int>(p.ops.size() - 1);
+  }
+  int kend[2] = {-1, -1};
+  for (int c = 0; c < 2; ++c)
+    if (last[c] >= 0) kend[c] = p.ops[static_cast<size_t>(last[c])].ev = p.events++;
+
+  // copy-outs in job order: small ones on the stream that computed them, the
+  // rest on the D2H FIFO after that stream's kernels
+  int waited = -1;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const PlanJob& j = jobs[i];
+    const int ks = p.stream_of[i];
+    const int job = static_cast<int>(i);
+    if (!j.copy_out) {
+      if (!capture) op(kOpDone, ks, kend[ks], job);
+      continue;
+    }
+    if (j.local) {
+      op(kOpCopyOut, ks, -1, job);
+      if (!capture) op(kOpDone, ks, -1, job);
+      continue;
+    }
+    if (waited != ks) {
+      op(kOpWait, kPlanD2H, kend[ks]);
+      waited = ks;
+    }
+    op(kOpCopyOut, kPlanD2H, -1, job);
+    if (!capture) op(kOpDone, kPlanD2H, -1, job);
+  }
+
+  if (capture) {  // join: every forked stream ends in C0 after its last operation
+    for (int s : {kPlanC1, kPlanH2D, kPlanD2H}) op(kOpWait, kPlanC0, record(s));
+  }
+  return p;
+}
+
+}  // namespace gvm

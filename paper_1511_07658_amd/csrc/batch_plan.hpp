@@ -1,0 +1,81 @@
+// Schedule of one grouped batch on the manager's four streams, as a list of
+// stream operations (host logic only, no HIP calls).  The HIP device walks the
+// list eagerly, or inside a stream capture to build the batch's graph; a CPU
+// test replays it against the dependency rules of streams and events and the
+// capture rules (every stream forked into a capture joins its origin again).
+//
+// Streams: compute streams C0 and C1 carry the grouped launches (dealt round
+// robin) and the small "local" copies of their own requests; H2D and D2H are
+// the copy FIFOs, one per direction, in the role of the execution model's
+// copy engines (Section 4.2.3).  C0 is the capture origin.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace gvm {
+
+enum PlanStream : int { kPlanC0 = 0, kPlanC1 = 1, kPlanH2D = 2, kPlanD2H = 3, kPlanStreams = 4 };
+
+enum PlanOpKind : int {
+  kOpRecord = 0,   // record event `ev` on `stream`
+  kOpWait = 1,     // `stream` waits for event `ev`
+  kOpCopyIn = 2,   // whole copy-in of job `job` on `stream`
+  kOpCopyOut = 3,  // copy-out of job `job` on `stream`
+  kOpLaunch = 4,   // grouped launch of group `group` on `stream`; with ev >= 0,
+                   // event `ev` is recorded right after it (end of that stream's kernels)
+  kOpDone = 5,     // completion of job `job`: ev >= 0 names an event already
+                   // recorded; otherwise a new one is recorded on `stream`
+};
+
+struct PlanOp {
+  int kind;
+  int stream;
+  int ev;
+  int job;
+  int group;
+};
+
+// What the schedule needs to know of one request.
+struct PlanJob {
+  int kernel_id;
+  int cls;        // class within the kernel id: the SGEMM k depth BK, else 0
+  uint64_t n;
+  bool copy_in;
+  bool copy_out;
+  bool local;     // copies small enough to stay on the kernel's own stream
+  bool pieces;    // input already queued piecewise on the H2D FIFO before the batch
+};
+
+// One grouped launch: requests of one kernel id and class, at most
+// kPlanMaxGroup of them, SGEMM sizes from the largest down.
+struct PlanGroup {
+  int kernel_id;
+  int cls;
+  int stream;               // index into the stream list the groups are dealt to
+  std::vector<int> jobs;    // indices into the job list, in launch order
+};
+
+constexpr int kPlanMaxGroup = 32;
+
+struct BatchPlan {
+  std::vector<PlanOp> ops;
+  std::vector<PlanGroup> groups;
+  std::vector<int> stream_of;  // per job: the compute stream of its kernel
+  int events = 0;              // event ids 0 .. events-1
+};
+
+// The grouped launches of `jobs` dealt round robin over `nstreams` streams
+// (one group per kernel id and class, split every kPlanMaxGroup requests).
+std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstreams);
+
+// Grouped policy: copy-ins (local ones on C0 ahead of its kernels, the rest
+// on the H2D FIFO), the grouped launches on C0 and C1 after the inputs they
+// read, copy-outs (local ones on the launch's own stream, the rest on the
+// D2H FIFO after the launch that computed them) and one completion per job.
+// With `capture`: the batch forks from C0 into the other three streams first
+// and every one of them joins C0 again after its last operation; no
+// completions (the replayed graph completes as a whole); no piecewise inputs.
+BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool capture);
+
+}  // namespace gvm

@@ -14,12 +14,15 @@
 #include <string>
 #include <vector>
 
+#include "batch_plan.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
 namespace gvm {
 
 namespace {
+
+static_assert(kPlanMaxGroup == kMaxGroup, "the batch plan splits groups at the kernel-argument capacity");
 
 #define HIPCHK(expr)                                                                     \
   do {                                                                                   \
@@ -208,6 +211,16 @@ class HipDevice final : public Device {
 
   int launch(std::vector<Job*>& jobs, int policy) override {
     if (jobs.empty()) return GVM_OK;
+    if (broken_) {
+      // after a capture that left a stream capturing nothing more is enqueued;
+      // the jobs fail here, without a batch
+      const int rc = fail(GVM_EDEVICE, "the device takes no more work after a failed batch capture");
+      for (Job* j : jobs) {
+        j->status = rc;
+        j->batch = nullptr;
+      }
+      return rc;
+    }
     if (policy != GVM_POLICY_PS1 && policy != GVM_POLICY_PS2)
       std::stable_sort(jobs.begin(), jobs.end(), [](const Job* x, const Job* y) { return x->rank < y->rank; });
     if (jobs[0]->part >= 0 && part_streams_.size() == 2) ++part_launches_[jobs[0]->part];
@@ -272,7 +285,7 @@ class HipDevice final : public Device {
         std::vector<Job*> one{j};
         if (j->local) {  // small: the whole chain on the rank stream
           rc = enqueue_in(j, s);
-          if (rc == GVM_OK) rc = enqueue_kernels(one, {s}, b, true, nullptr);
+          if (rc == GVM_OK) rc = enqueue_kernels(one, {s}, b);
           if (rc == GVM_OK) rc = enqueue_out(j, s);
           if (rc == GVM_OK) rc = record_done(b, i, s);
           continue;
@@ -281,7 +294,7 @@ class HipDevice final : public Device {
           rc = enqueue_in(j, h2d_);
           if (rc == GVM_OK) rc = after(s, h2d_, b);
         }
-        if (rc == GVM_OK) rc = enqueue_kernels(one, {s}, b, true, nullptr);
+        if (rc == GVM_OK) rc = enqueue_kernels(one, {s}, b);
         if (rc == GVM_OK && j->copy_out) {
           rc = after(d2h_, s, b);
           if (rc == GVM_OK) rc = enqueue_out(j, d2h_);
@@ -306,7 +319,7 @@ class HipDevice final : public Device {
         for (size_t k = 0; k < ks.size() && rc == GVM_OK; ++k) rc = after(ks[k], h2d_, b);
       for (size_t i = 0; i < jobs.size() && rc == GVM_OK; ++i) {
         std::vector<Job*> one{jobs[i]};
-        rc = enqueue_kernels(one, {kernel_stream(jobs[i])}, b, true, nullptr);
+        rc = enqueue_kernels(one, {kernel_stream(jobs[i])}, b);
       }
       if (any_out)
         for (size_t k = 0; k < ks.size() && rc == GVM_OK; ++k) rc = after(d2h_, ks[k], b);
@@ -339,8 +352,9 @@ class HipDevice final : public Device {
     batches_.push_back(b);
     if (rc != GVM_OK) {
       // Device state is unknown after a failed enqueue: wait for what was
-      // queued, then fail every job of the batch.
-      (void)hipDeviceSynchronize();
+      // queued (unless a stream was left capturing, where a synchronisation
+      // is not allowed), then fail every job of the batch.
+      if (!broken_) (void)hipDeviceSynchronize();
       for (Job* j : jobs) j->status = rc;
       for (size_t i = 0; i < jobs.size(); ++i) b->done[i] = nullptr;
     }
@@ -418,6 +432,7 @@ class HipDevice final : public Device {
     for (auto& kv : graphs_) {
       (void)hipGraphExecDestroy(kv.second.exec);
       (void)hipGraphDestroy(kv.second.graph);
+      for (hipEvent_t e : kv.second.events) (void)hipEventDestroy(e);
     }
     graphs_.clear();
     graphs_cached_.store(0);
@@ -488,8 +503,20 @@ class HipDevice final : public Device {
     return rank_stream(j->rank);
   }
 
+  // An untimed event for ordering streams, owned by batch `b` and recycled
+  // when the batch retires.  During a stream capture the event is created
+  // fresh and owned by the graph being built instead: it is never handed to
+  // an eager batch while that graph exists.
   hipEvent_t sync_event(Batch* b) {
     hipEvent_t e = nullptr;
+    if (capturing_) {
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        fail(GVM_EDEVICE, "hipEventCreate failed");
+        return nullptr;
+      }
+      capture_events_.push_back(e);
+      return e;
+    }
     if (!free_sync_.empty()) {
       e = free_sync_.back();
       free_sync_.pop_back();
@@ -512,17 +539,11 @@ class HipDevice final : public Device {
     return e;
   }
 
-  // Number of grouped launches enqueue_kernels makes for `jobs` (one per
-  // kernel id and SGEMM tile configuration, per kMaxGroup requests).
+  // Number of grouped launches the grouped policy makes for `jobs`.
   static size_t grouped_launches(const std::vector<Job*>& jobs) {
-    std::map<std::pair<int, int>, size_t> groups;
-    for (const Job* j : jobs) {
-      const int k = static_cast<int>(j->req.kernel_id);
-      ++groups[{k, k == GVM_K_SGEMM ? gemm_config(gemm_config_for(j->req.n)).bk : 0}];  // as enqueue_kernels
-    }
-    size_t n = 0;
-    for (const auto& kv : groups) n += (kv.second + kMaxGroup - 1) / kMaxGroup;
-    return n;
+    std::vector<PlanJob> pj;
+    for (const Job* j : jobs) pj.push_back(plan_job(j));
+    return plan_groups(pj, 2).size();
   }
 
   // `waiter` continues only after everything enqueued so far on `producer`.
@@ -602,140 +623,126 @@ class HipDevice final : public Device {
     return GVM_OK;
   }
 
-  // One grouped launch per kernel id (per tile configuration for SGEMM), at
-  // most kMaxGroup requests each.  Groups are dealt round-robin to
-  // `streams`; `stream_of[i]` receives the stream index that computes
-  // jobs[i].  With `timed`, each launch is bracketed by timing events.
-  int enqueue_kernels(const std::vector<Job*>& jobs, const std::vector<hipStream_t>& streams, Batch* b, bool timed,
-                      std::vector<int>* stream_of, std::vector<hipEvent_t>* last_event = nullptr) {
-    if (stream_of) stream_of->assign(jobs.size(), 0);
-    if (last_event) last_event->assign(streams.size(), nullptr);
-    std::map<const Job*, size_t> index;
-    for (size_t i = 0; i < jobs.size(); ++i) index[jobs[i]] = i;
-    size_t next_stream = 0;
-    // One grouped launch per kernel id; SGEMM requests are grouped by the k
-    // depth BK of their size's tile configuration.  A C element sums its k
-    // products in an order fixed by BK alone (ascending k-tiles of BK, each
-    // in KH = BK/2 MFMA steps over k = s and BK/2 + s), whatever the tile
-    // shape, staging or fetch depth, so every request of a BK class may run
-    // with the configuration of the class's largest request and still get
-    // the bits it gets alone.  A mix of sizes then fills the device with one
-    // launch instead of one small launch per configuration.
-    std::map<std::pair<int, int>, std::vector<Job*>> groups;
-    for (Job* j : jobs) {
-      const int k = static_cast<int>(j->req.kernel_id);
-      const int cls = (k == GVM_K_SGEMM) ? gemm_config(gemm_config_for(j->req.n)).bk : 0;
-      groups[{k, cls}].push_back(j);
-    }
-    for (auto& kv : groups) {
-      const int k = kv.first.first;
-      auto& v = kv.second;
-      int cfgi = 0;
-      if (k == GVM_K_SGEMM) {
-        // largest first: the launch's first round of workgroups takes the
-        // longest tiles and the later rounds fill in behind them
-        std::stable_sort(v.begin(), v.end(), [](const Job* x, const Job* y) { return x->req.n > y->req.n; });
-        cfgi = gemm_class_config(v);
-      }
-      for (size_t base = 0; base < v.size(); base += kMaxGroup) {
-        const size_t cnt = std::min<size_t>(kMaxGroup, v.size() - base);
-        const size_t si = next_stream++ % streams.size();
-        hipStream_t s = streams[si];
-        if (stream_of)
-          for (size_t i = 0; i < cnt; ++i) (*stream_of)[index[v[base + i]]] = static_cast<int>(si);
-        TimedLaunch t{};
-        t.kernel_id = k;
-        t.requests = static_cast<uint32_t>(cnt);
-        if (timed) {
-          t.e0 = timed_event();
-          t.e1 = timed_event();
-          if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
-        }
-        for (size_t i = 0; i < cnt; ++i) {
-          double f, by;
-          request_work(k, v[base + i]->req.n, &f, &by);
-          t.flop += f;
-          t.bytes += by;
-        }
-        if (timed) HIPCHK(hipEventRecord(t.e0, s));
-        hipError_t e = hipSuccess;
-        if (k == GVM_K_VECADD || k == GVM_K_VECMUL) {
-          VecGroup g{};
-          g.count = static_cast<uint32_t>(cnt);
-          for (size_t i = 0; i < cnt; ++i) {
-            Job* j = v[base + i];
-            float* in = reinterpret_cast<float*>(j->slot);
-            g.d[i].a = in;
-            g.d[i].b = in + j->req.n;
-            g.d[i].c = reinterpret_cast<float*>(j->slot + slot_out_offset(j->lay));
-            g.d[i].n = j->req.n;
-          }
-          finalize_vec_group(g);
-          e = (k == GVM_K_VECADD) ? launch_vecadd_group(g, s) : launch_vecmul_group(g, s);
-        } else if (k == GVM_K_BLACKSCHOLES) {
-          BsGroup g{};
-          g.count = static_cast<uint32_t>(cnt);
-          g.rate = cfg_.bs_rate;
-          g.volatility = cfg_.bs_volatility;
-          for (size_t i = 0; i < cnt; ++i) {
-            Job* j = v[base + i];
-            const uint64_t n = j->req.n;
-            float* in = reinterpret_cast<float*>(j->slot);
-            float* out = reinterpret_cast<float*>(j->slot + slot_out_offset(j->lay));
-            g.d[i].S = in;
-            g.d[i].K = in + n;
-            g.d[i].T = in + 2 * n;
-            g.d[i].call = out;
-            g.d[i].put = out + n;
-            g.d[i].n = n;
-          }
-          finalize_bs_group(g);
-          e = launch_bs_group(g, s);
-        } else if (k == GVM_K_SGEMM) {
-          GemmGroup g{};
-          g.count = static_cast<uint32_t>(cnt);
-          for (size_t i = 0; i < cnt; ++i) {
-            Job* j = v[base + i];
-            const uint64_t n = j->req.n;
-            float* in = reinterpret_cast<float*>(j->slot);
-            g.d[i].A = in;
-            g.d[i].B = in + n * n;
-            g.d[i].C = reinterpret_cast<float*>(j->slot + slot_out_offset(j->lay));
-            g.d[i].n = static_cast<uint32_t>(n);
-          }
-          finalize_gemm_group(g, cfgi);
-          const bool mixed = v.front()->req.n != v.back()->req.n;
-          e = launch_sgemm_group(g, cfgi, s, mixed ? gemm_mix_grid() : 0);
-        } else if (k == GVM_K_EP) {
-          EpGroup g{};
-          g.count = static_cast<uint32_t>(cnt);
-          for (size_t i = 0; i < cnt; ++i) {
-            Job* j = v[base + i];
-            g.d[i].key = reinterpret_cast<const uint64_t*>(j->slot);
-            g.d[i].out = reinterpret_cast<uint64_t*>(j->slot + slot_out_offset(j->lay));
-            g.d[i].partial = reinterpret_cast<uint64_t*>(j->slot + slot_scratch_offset(j->lay));
-            g.d[i].n = j->req.n;
-          }
-          finalize_ep_group(g);
-          e = launch_ep_group(g, s);
-        } else {
-          return fail(GVM_EINVAL, "unknown kernel id %d", k);
-        }
-        if (e != hipSuccess) return fail(GVM_EDEVICE, "kernel launch (%s): %s", kernel_name(k), hipGetErrorString(e));
-        if (timed) {
-          HIPCHK(hipEventRecord(t.e1, s));
-          b->timed.push_back(t);
-          if (last_event) (*last_event)[si] = t.e1;  // also marks the end of this stream's kernels
-        }
-      }
+  // The plan's view of a job.
+  static PlanJob plan_job(const Job* j) {
+    const int k = static_cast<int>(j->req.kernel_id);
+    return PlanJob{k, k == GVM_K_SGEMM ? gemm_config(gemm_config_for(j->req.n)).bk : 0, j->req.n,
+                   j->copy_in, j->copy_out, j->local, j->pieces};
+  }
+
+  // One grouped launch per kernel id (per k depth class for SGEMM), at most
+  // kMaxGroup requests each, dealt round robin to `streams` (PS-1 and PS-2
+  // call it with one job and its own stream).  Each launch is timed.
+  int enqueue_kernels(const std::vector<Job*>& jobs, const std::vector<hipStream_t>& streams, Batch* b) {
+    std::vector<PlanJob> pj;
+    for (const Job* j : jobs) pj.push_back(plan_job(j));
+    for (const PlanGroup& g : plan_groups(pj, static_cast<int>(streams.size()))) {
+      const int rc = launch_group(g, jobs, streams[static_cast<size_t>(g.stream)], b, true, nullptr);
+      if (rc != GVM_OK) return rc;
     }
     return GVM_OK;
   }
 
-  // Grouped policy: copy-ins on the host-to-device FIFO, one grouped launch
-  // per kernel id spread over the two compute streams, copy-outs on the
-  // device-to-host FIFO.  With use_graphs the whole batch is captured once per batch
-  // template (ranks, kernels, sizes, copies, buffers) and replayed.
+  // One grouped launch of the requests `g.jobs` of `jobs` on stream `s`.
+  // `timed`: bracketed by timing events, and *end receives the closing one
+  // (it also marks the end of the launch on its stream); otherwise *end is
+  // left null.
+  int launch_group(const PlanGroup& g, const std::vector<Job*>& jobs, hipStream_t s, Batch* b, bool timed,
+                   hipEvent_t* end) {
+    const int k = g.kernel_id;
+    const size_t cnt = g.jobs.size();
+    if (cnt == 0 || cnt > static_cast<size_t>(kMaxGroup)) return fail(GVM_EINVAL, "group of %zu requests", cnt);
+    std::vector<Job*> v;
+    for (int i : g.jobs) v.push_back(jobs[static_cast<size_t>(i)]);
+    if (end) *end = nullptr;
+    TimedLaunch t{};
+    t.kernel_id = k;
+    t.requests = static_cast<uint32_t>(cnt);
+    if (timed) {
+      t.e0 = timed_event();
+      t.e1 = timed_event();
+      if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
+    }
+    for (Job* j : v) {
+      double f, by;
+      request_work(k, j->req.n, &f, &by);
+      t.flop += f;
+      t.bytes += by;
+    }
+    if (timed) HIPCHK(hipEventRecord(t.e0, s));
+    hipError_t e = hipSuccess;
+    if (k == GVM_K_VECADD || k == GVM_K_VECMUL) {
+      VecGroup vg{};
+      vg.count = static_cast<uint32_t>(cnt);
+      for (size_t i = 0; i < cnt; ++i) {
+        float* in = reinterpret_cast<float*>(v[i]->slot);
+        vg.d[i].a = in;
+        vg.d[i].b = in + v[i]->req.n;
+        vg.d[i].c = reinterpret_cast<float*>(v[i]->slot + slot_out_offset(v[i]->lay));
+        vg.d[i].n = v[i]->req.n;
+      }
+      finalize_vec_group(vg);
+      e = (k == GVM_K_VECADD) ? launch_vecadd_group(vg, s) : launch_vecmul_group(vg, s);
+    } else if (k == GVM_K_BLACKSCHOLES) {
+      BsGroup bg{};
+      bg.count = static_cast<uint32_t>(cnt);
+      bg.rate = cfg_.bs_rate;
+      bg.volatility = cfg_.bs_volatility;
+      for (size_t i = 0; i < cnt; ++i) {
+        const uint64_t n = v[i]->req.n;
+        float* in = reinterpret_cast<float*>(v[i]->slot);
+        float* out = reinterpret_cast<float*>(v[i]->slot + slot_out_offset(v[i]->lay));
+        bg.d[i].S = in;
+        bg.d[i].K = in + n;
+        bg.d[i].T = in + 2 * n;
+        bg.d[i].call = out;
+        bg.d[i].put = out + n;
+        bg.d[i].n = n;
+      }
+      finalize_bs_group(bg);
+      e = launch_bs_group(bg, s);
+    } else if (k == GVM_K_SGEMM) {
+      GemmGroup gg{};
+      gg.count = static_cast<uint32_t>(cnt);
+      for (size_t i = 0; i < cnt; ++i) {
+        const uint64_t n = v[i]->req.n;
+        float* in = reinterpret_cast<float*>(v[i]->slot);
+        gg.d[i].A = in;
+        gg.d[i].B = in + n * n;
+        gg.d[i].C = reinterpret_cast<float*>(v[i]->slot + slot_out_offset(v[i]->lay));
+        gg.d[i].n = static_cast<uint32_t>(n);
+      }
+      const int cfgi = gemm_class_config(v);
+      finalize_gemm_group(gg, cfgi);
+      const bool mixed = v.front()->req.n != v.back()->req.n;
+      e = launch_sgemm_group(gg, cfgi, s, mixed ? gemm_mix_grid() : 0);
+    } else if (k == GVM_K_EP) {
+      EpGroup eg{};
+      eg.count = static_cast<uint32_t>(cnt);
+      for (size_t i = 0; i < cnt; ++i) {
+        eg.d[i].key = reinterpret_cast<const uint64_t*>(v[i]->slot);
+        eg.d[i].out = reinterpret_cast<uint64_t*>(v[i]->slot + slot_out_offset(v[i]->lay));
+        eg.d[i].partial = reinterpret_cast<uint64_t*>(v[i]->slot + slot_scratch_offset(v[i]->lay));
+        eg.d[i].n = v[i]->req.n;
+      }
+      finalize_ep_group(eg);
+      e = launch_ep_group(eg, s);
+    } else {
+      return fail(GVM_EINVAL, "unknown kernel id %d", k);
+    }
+    if (e != hipSuccess) return fail(GVM_EDEVICE, "kernel launch (%s): %s", kernel_name(k), hipGetErrorString(e));
+    if (timed) {
+      HIPCHK(hipEventRecord(t.e1, s));
+      b->timed.push_back(t);
+      if (end) *end = t.e1;
+    }
+    return GVM_OK;
+  }
+
+  // Grouped policy: the batch plan (copy-ins, grouped launches on the two
+  // compute streams, copy-outs, completions), executed eagerly, or captured
+  // once per batch template (ranks, kernels, sizes, copies, buffers) and
+  // replayed as a graph with use_graphs.
   int launch_grouped(Batch* b) {
     std::vector<Job*>& jobs = b->jobs;
     hipStream_t c0 = compute_streams_[0];
@@ -745,24 +752,41 @@ class HipDevice final : public Device {
     auto it = graphs_.find(key);
     if (it == graphs_.end()) {
       if (graphs_.size() >= kMaxGraphs) evict_graph();
+      for (Job* j : jobs)
+        if (j->pieces) return fail(GVM_EINVAL, "a piecewise input cannot be part of a captured batch");
       HIPCHK(hipStreamBeginCapture(c0, hipStreamCaptureModeThreadLocal));
       capturing_ = true;
+      capture_events_.clear();
       int rc = enqueue_grouped(b, true);
       capturing_ = false;
       hipGraph_t g = nullptr;
-      hipError_t e = hipStreamEndCapture(c0, &g);
-      if (rc != GVM_OK) {
+      const hipError_t e = hipStreamEndCapture(c0, &g);
+      std::vector<hipEvent_t> evs;
+      evs.swap(capture_events_);
+      // Whatever went wrong, no stream of the batch may stay in capture mode:
+      // work enqueued later on such a stream would be added to a graph that
+      // no longer exists.  If one does, the device stops taking work.
+      for (hipStream_t s : {compute_streams_[0], compute_streams_[1], h2d_, d2h_}) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) broken_ = true;
+      }
+      if (broken_) {
         if (g) (void)hipGraphDestroy(g);
-        return rc;
+        return fail(GVM_EDEVICE, "a stream was left capturing after the batch capture; the device takes no more work");
       }
-      if (e != hipSuccess) return fail(GVM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      if (rc != GVM_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        for (hipEvent_t x : evs) (void)hipEventDestroy(x);
+        return rc != GVM_OK ? rc : fail(GVM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      }
       hipGraphExec_t ex = nullptr;
-      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
+      const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
         (void)hipGraphDestroy(g);
-        return fail(GVM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        for (hipEvent_t x : evs) (void)hipEventDestroy(x);
+        return fail(GVM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
       }
-      it = graphs_.emplace(key, GraphEntry{g, ex, 0}).first;
+      it = graphs_.emplace(key, GraphEntry{g, ex, 0, std::move(evs)}).first;
       graphs_cached_.store(graphs_.size());
       ++graph_captures_;
     }
@@ -793,96 +817,66 @@ class HipDevice final : public Device {
     return GVM_OK;
   }
 
-  // The device work of a grouped batch.  `capture`: everything forks from
-  // and joins back into compute stream 0 (required to end a stream
-  // capture), no timing events, one completion for the batch.
+  // Execute the batch plan of a grouped batch.  `capture`: inside a stream
+  // capture on compute stream 0 (untimed; the plan forks from and joins
+  // back into it, and has no per-job completions).
   int enqueue_grouped(Batch* b, bool capture) {
     std::vector<Job*>& jobs = b->jobs;
-    hipStream_t c0 = compute_streams_[0], c1 = compute_streams_[1];
-    if (jobs[0]->part >= 0 && part_streams_.size() == 2) c0 = c1 = part_streams_[static_cast<size_t>(jobs[0]->part)];
-    if (capture) {
-      hipEvent_t fork = sync_event(b);
-      if (!fork) return GVM_EDEVICE;
-      HIPCHK(hipEventRecord(fork, c0));
-      HIPCHK(hipStreamWaitEvent(h2d_, fork, 0));
-      HIPCHK(hipStreamWaitEvent(d2h_, fork, 0));
-      HIPCHK(hipStreamWaitEvent(c1, fork, 0));
-    }
-    // copy-ins in rank order on the host-to-device FIFO (small ones on
-    // compute stream 0, ahead of its kernels), then both compute streams
-    // wait for the FIFO
-    bool fifo_in = false, local_in = false;
-    for (Job* j : jobs) {
-      const int rc0 = enqueue_in(j, j->local ? c0 : h2d_);
-      if (rc0 != GVM_OK) return rc0;
-      fifo_in |= j->copy_in && !j->local;
-      local_in |= j->copy_in && j->local;
-    }
-    if (local_in && grouped_launches(jobs) > 1) {  // c1's kernels may need c0's local copies
-      hipEvent_t ev = sync_event(b);
-      if (!ev) return GVM_EDEVICE;
-      HIPCHK(hipEventRecord(ev, c0));
-      HIPCHK(hipStreamWaitEvent(c1, ev, 0));
-    }
-    if (fifo_in) {
-      hipEvent_t ev = sync_event(b);
-      if (!ev) return GVM_EDEVICE;
-      HIPCHK(hipEventRecord(ev, h2d_));
-      HIPCHK(hipStreamWaitEvent(c0, ev, 0));
-      HIPCHK(hipStreamWaitEvent(c1, ev, 0));
-    }
-    std::vector<int> stream_of;
-    std::vector<hipEvent_t> last;
-    int rc = enqueue_kernels(jobs, {c0, c1}, b, !capture, &stream_of, &last);
-    if (rc != GVM_OK) return rc;
-    // the end of each compute stream's kernels: the timing event after its
-    // last launch when timed; one extra marker only when capturing
-    hipEvent_t k[2] = {last[0], last[1]};
-    bool needed[2] = {capture, capture};
-    for (int x : stream_of) needed[x] = true;
-    for (int c = 0; c < 2; ++c) {
-      if (!needed[c] || (k[c] && !capture)) continue;
-      k[c] = sync_event(b);
-      if (!k[c]) return GVM_EDEVICE;
-      HIPCHK(hipEventRecord(k[c], c == 0 ? c0 : c1));
-    }
-    // copy-outs in rank order on the device-to-host FIFO, each after the
-    // launch that computed it (small ones on that launch's own stream)
-    int waited = -1;
-    for (size_t i = 0; i < jobs.size(); ++i) {
-      Job* j = jobs[i];
-      hipEvent_t kev = k[stream_of[i]];
-      hipStream_t ks = stream_of[i] == 0 ? c0 : c1;
-      if (!j->copy_out) {
-        b->done[i] = kev;
-        if (!capture) track(b, kev, ks);
-        continue;
+    hipStream_t st[kPlanStreams] = {compute_streams_[0], compute_streams_[1], h2d_, d2h_};
+    if (jobs[0]->part >= 0 && part_streams_.size() == 2)
+      st[kPlanC0] = st[kPlanC1] = part_streams_[static_cast<size_t>(jobs[0]->part)];
+    std::vector<PlanJob> pj;
+    for (const Job* j : jobs) pj.push_back(plan_job(j));
+    const BatchPlan p = plan_grouped(pj, capture);
+    std::vector<hipEvent_t> ev(static_cast<size_t>(p.events), nullptr);
+    std::vector<hipStream_t> ev_stream(static_cast<size_t>(p.events), nullptr);
+    for (const PlanOp& o : p.ops) {
+      hipStream_t s = st[o.stream];
+      int rc = GVM_OK;
+      switch (o.kind) {
+        case kOpRecord: {
+          hipEvent_t e = sync_event(b);
+          if (!e) return GVM_EDEVICE;
+          HIPCHK(hipEventRecord(e, s));
+          ev[static_cast<size_t>(o.ev)] = e;
+          ev_stream[static_cast<size_t>(o.ev)] = s;
+          break;
+        }
+        case kOpWait:
+          HIPCHK(hipStreamWaitEvent(s, ev[static_cast<size_t>(o.ev)], 0));
+          break;
+        case kOpCopyIn:
+          rc = enqueue_in(jobs[static_cast<size_t>(o.job)], s);
+          break;
+        case kOpCopyOut:
+          rc = enqueue_out(jobs[static_cast<size_t>(o.job)], s);
+          break;
+        case kOpLaunch: {
+          hipEvent_t end = nullptr;
+          rc = launch_group(p.groups[static_cast<size_t>(o.group)], jobs, s, b, !capture, &end);
+          if (rc == GVM_OK && o.ev >= 0) {
+            if (!end) {  // untimed: a marker of its own
+              end = sync_event(b);
+              if (!end) return GVM_EDEVICE;
+              HIPCHK(hipEventRecord(end, s));
+            }
+            ev[static_cast<size_t>(o.ev)] = end;
+            ev_stream[static_cast<size_t>(o.ev)] = s;
+          }
+          break;
+        }
+        case kOpDone:
+          if (o.ev >= 0) {
+            b->done[static_cast<size_t>(o.job)] = ev[static_cast<size_t>(o.ev)];
+            track(b, ev[static_cast<size_t>(o.ev)], ev_stream[static_cast<size_t>(o.ev)]);
+          } else {
+            rc = record_done(b, static_cast<size_t>(o.job), s);
+          }
+          break;
+        default:
+          return fail(GVM_EINVAL, "unknown plan operation %d", o.kind);
       }
-      if (j->local) {
-        rc = enqueue_out(j, ks);
-        if (rc == GVM_OK && !capture) rc = record_done(b, i, ks);
-        if (rc != GVM_OK) return rc;
-        continue;
-      }
-      if (waited != stream_of[i]) {
-        HIPCHK(hipStreamWaitEvent(d2h_, kev, 0));
-        waited = stream_of[i];
-      }
-      rc = enqueue_out(j, d2h_);
       if (rc != GVM_OK) return rc;
-      if (!capture) {
-        rc = record_done(b, i, d2h_);
-        if (rc != GVM_OK) return rc;
-      }
-    }
-    if (capture) {  // join
-      for (hipStream_t s : {h2d_, d2h_}) {
-        hipEvent_t ev = sync_event(b);
-        if (!ev) return GVM_EDEVICE;
-        HIPCHK(hipEventRecord(ev, s));
-        HIPCHK(hipStreamWaitEvent(c0, ev, 0));
-      }
-      HIPCHK(hipStreamWaitEvent(c0, k[1], 0));
     }
     return GVM_OK;
   }
@@ -906,6 +900,7 @@ class HipDevice final : public Device {
     (void)hipStreamSynchronize(compute_streams_[0]);  // no launch of it may be pending
     (void)hipGraphExecDestroy(victim->second.exec);
     (void)hipGraphDestroy(victim->second.graph);
+    for (hipEvent_t e : victim->second.events) (void)hipEventDestroy(e);
     graphs_.erase(victim);
     graphs_cached_.store(graphs_.size());
   }
@@ -1008,6 +1003,8 @@ class HipDevice final : public Device {
   };
   std::map<hipStream_t, std::deque<FifoEntry>> fifo_;
   bool capturing_ = false;
+  std::vector<hipEvent_t> capture_events_;  // events recorded during the capture in progress
+  bool broken_ = false;                     // a stream was left capturing: no more device work
   std::vector<double> batch_us_;
   double copy_ms_[2] = {0, 0}, copy_bytes_[2] = {0, 0};
   uint64_t copy_n_[2] = {0, 0};
@@ -1022,6 +1019,7 @@ class HipDevice final : public Device {
     hipGraph_t graph;
     hipGraphExec_t exec;
     uint64_t last_use;
+    std::vector<hipEvent_t> events;  // recorded during its capture; destroyed with the graph
   };
   static constexpr size_t kMaxGraphs = 32;
   std::map<std::string, GraphEntry> graphs_;

@@ -73,9 +73,9 @@ int Manager::init(const gvm_config& cfg_in) {
   if (cfg.hbm_budget_bytes < (1u << 20)) return fail(GVM_EINVAL, "hbm_budget_bytes must be >= 1 MiB");
   if (cfg.mode > GVM_MODE_SERVING || cfg.policy > GVM_POLICY_GROUPED || cfg.backend > GVM_BACKEND_LOOPBACK)
     return fail(GVM_EINVAL, "bad mode/policy/backend");
-  // HIP graph replay of repeated batches is switched off: its first GPU run
-  // ended in a host segmentation fault whose cause has not been shown.
-  if (cfg.use_graphs) return fail(GVM_EINVAL, "use_graphs is switched off in this build (graph replay disabled)");
+  // Graph replay captures a batch on the unmasked compute streams; the CU
+  // partition launches on masked streams of its own, so the two do not mix.
+  if (cfg.use_graphs && cfg.latency_cus) return fail(GVM_EINVAL, "use_graphs and latency_cus cannot be combined");
   if (cfg.latency_cus && (cfg.mode != GVM_MODE_SERVING || cfg.latency_cus % 32 || cfg.latency_cus >= 256))
     return fail(GVM_EINVAL, "latency_cus must be 0, or in serving mode a multiple of 32 below 256");
   cfg.shm_bytes_per_rank = (cfg.shm_bytes_per_rank + 4095) / 4096 * 4096;

@@ -85,6 +85,36 @@ def ep_result(out) -> dict:
             "q": w[2:12].astype(np.int64)}
 
 
+def edge_floats():
+    """Binary32 operands at the edges of the format: signed zeros, the
+    smallest normal and subnormals, values one ulp and half an ulp from 1,
+    the largest finite value, 2**24 and its neighbour, and a few ordinary
+    numbers."""
+    vals = [0.0, -0.0, 1.0, -1.0, 1.5, 2.0 ** -126, 2.0 ** -149, -(2.0 ** -149), 3 * 2.0 ** -149,
+            1.0 + 2.0 ** -23, 1.0 - 2.0 ** -24, 3.4028234663852886e38, 2.0 ** 24, 2.0 ** 24 + 2.0,
+            0.1, 1e-30, 5e-39]
+    return [float(np.float32(v)) for v in vals]
+
+
+def edge_pairs():
+    """Every ordered pair of edge_floats (plus their negations), then the
+    infinities and NaN against each other and against 1 and the largest
+    finite value, and rounding ties: operand arrays (a, b) in binary32."""
+    e = edge_floats()
+    e = e + [-x for x in e if x != 0.0]
+    a = [x for x in e for _ in e]
+    b = [y for _ in e for y in e]
+    special = [math.inf, -math.inf, math.nan, 1.0, 3.4028234663852886e38, -3.4028234663852886e38]
+    a += [x for x in special for _ in special]
+    b += [y for _ in special for y in special]
+    # ties: halfway between two binary32 values, both parities of the lower one
+    for m in range(1, 64):
+        x = 1.0 + m * 2.0 ** -23
+        a += [x, -x, x * 2.0 ** -120]
+        b += [2.0 ** -24, -(2.0 ** -24), 2.0 ** -144]
+    return np.array(a, dtype=np.float32), np.array(b, dtype=np.float32)
+
+
 def pack_request(kernel_id: int, *arrays) -> np.ndarray:
     """Concatenate the input arrays of one request into the packed binary32
     layout the C-ABI expects (``[a|b]``, ``[S|K|T]`` or ``[A|B]``)."""

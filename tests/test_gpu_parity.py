@@ -45,13 +45,13 @@ def hip_manager(name, **kw):
         G.gvm_shutdown()
 
 
-def run_ranks(ns, jobs_by_rank, zero_copy=False, barrier=None):
+def run_ranks(ns, jobs_by_rank, zero_copy=False, barrier=None, outputs=True):
     """Each rank (a thread) runs its job list; returns the per-rank results.
     With `barrier`, every rank attaches before any submits."""
     out = [None] * len(jobs_by_rank)
 
     def body(r):
-        out[r] = spmd.rank_program(ns, r, jobs_by_rank[r], True, zero_copy, barrier=barrier)
+        out[r] = spmd.rank_program(ns, r, jobs_by_rank[r], outputs, zero_copy, barrier=barrier)
 
     ths = [threading.Thread(target=body, args=(r,)) for r in range(len(jobs_by_rank)) if jobs_by_rank[r]]
     for t in ths:
@@ -103,8 +103,6 @@ def assert_sgemm(out, cfg, rank, n, req=0, integer=False):
         assert rel <= 1e-4, f"rank {rank} n {n}: relative Frobenius {rel:.3e}"
 
 
-# ------------------------------------------------------------------ tests
-
 EP_TOL_ULPS = 256
 
 
@@ -117,6 +115,24 @@ def assert_ep(out, cfg, rank, n, req=0):
         tol = EP_TOL_ULPS * eps * ref[a]
         assert abs(got[s] - ref[s]) <= tol, f"rank {rank} n {n} {s}: {got[s]!r} vs {ref[s]!r} (tol {tol:.3e})"
 
+
+def assert_oracle(kernel_id, out, cfg, rank, n, req=0, integer=False):
+    """The oracle's bar for one request of any kernel."""
+    if kernel_id == G.GVM_K_VECADD:
+        assert_vecadd(out, cfg, rank, n, req)
+    elif kernel_id == G.GVM_K_VECMUL:
+        assert_vecadd(out, cfg, rank, n, req, mul=True)
+    elif kernel_id == G.GVM_K_BLACKSCHOLES:
+        assert_bs(out, cfg, rank, n, req)
+    elif kernel_id == G.GVM_K_SGEMM:
+        assert_sgemm(out, cfg, rank, n, req, integer)
+    elif kernel_id == G.GVM_K_EP:
+        assert_ep(out, cfg, rank, n, req)
+    else:
+        raise ValueError(kernel_id)
+
+
+# ------------------------------------------------------------------ tests
 
 def test_vecadd_bitexact_ragged(ns_name):
     sizes = [1, 3, 4, 4095, 4097, 65537, (1 << 20) + 3]
@@ -313,6 +329,8 @@ def test_alone_equals_mix_equals_plain(ns_name, policy):
         for r in range(nr):
             mixed[r] = res[r]["results"][0]
             assert mixed[r]["status"] == 0
+            (k, cfg, n, req, integer), = _jobs_mix(r)
+            assert_oracle(k, mixed[r]["out"], cfg, r, n, req, integer)
     with hip_manager(ns_name + f"a{policy}", nranks=nr, policy=policy):
         for r in range(nr):  # one rank at a time: alone on the device
             res = run_ranks(ns_name + f"a{policy}", [(_jobs_mix(r) if q == r else []) for q in range(nr)])
@@ -407,6 +425,7 @@ def test_serving_mix_matches_alone(ns_name):
         assert res[r]["attach"] == 0
         for (k, cfg, n, req, integer), jr in zip(jobs[r], res[r]["results"]):
             assert jr["status"] == 0, jr
+            assert_oracle(k, jr["out"], cfg, r, n, req, integer)
             x = spmd.make_input(k, cfg, r, n, req, integer)
             o = np.empty(G.out_elems(k, n), np.float32)
             rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
@@ -430,6 +449,7 @@ def test_cu_partition_results_match_plain(ns_name):
         assert res[r]["attach"] == 0
         for (k, cfg, n, req, integer), jr in zip(jobs[r], res[r]["results"]):
             assert jr["status"] == 0, jr
+            assert_oracle(k, jr["out"], cfg, r, n, req, integer)
             x = spmd.make_input(k, cfg, r, n, req, integer)
             o = np.empty(G.out_elems(k, n), np.float32)
             rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
@@ -449,11 +469,6 @@ def test_request_larger_than_budget(ns_name):
         G.gvm_detach(0)
 
 
-GRAPH_SKIP = ("HIP graph replay is switched off: its first GPU run ended in a host segmentation "
-              "fault whose cause is not yet shown (gvm_init rejects use_graphs)")
-
-
-@pytest.mark.skip(reason=GRAPH_SKIP)
 def test_graph_replays_match_eager(ns_name):
     # one batch template replayed as a HIP graph: every replay, with fresh
     # inputs copied in between, must equal the plain (eager) result
@@ -474,9 +489,9 @@ def test_graph_replays_match_eager(ns_name):
             rc, _ = G.gvm_plain_run(k, x, o, n, R32, V32)
             assert rc == 0
             assert spmd.digest(o) == jr["digest"], (r, k, n, req)
+            assert_oracle(k, jr["out"], cfg, r, n, req, integer)
 
 
-@pytest.mark.skip(reason=GRAPH_SKIP)
 def test_graph_resident_sgemm_matches_oracle(ns_name):
     n = 1024
     with hip_manager(ns_name, nranks=8, policy=G.GVM_POLICY_GROUPED, use_graphs=1, batch_window_us=10_000_000):
@@ -505,3 +520,93 @@ def test_graph_resident_sgemm_matches_oracle(ns_name):
         assert not errs, errs
         st = G.gvm_stats_json()
         assert st["device"]["graph_launches"] >= 5
+
+
+def test_vecadd_vecmul_edge_values_bitexact(ns_name):
+    # operands at the edges of binary32 (signed zeros, subnormals, ties,
+    # the largest finite value, infinities, NaN): the kernels' results equal
+    # the oracle's bit for bit; a NaN result only has to be a NaN
+    a, b = wl.edge_pairs()
+    n = a.size
+    x = wl.pack_request(G.GVM_K_VECADD, a, b)
+    with hip_manager(ns_name, nranks=1):
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        try:
+            for k, ref in ((G.GVM_K_VECADD, ok.vecadd_f32(a, b)), (G.GVM_K_VECMUL, ok.vecmul_f32(a, b))):
+                o = np.full(n, np.nan, np.float32)
+                t = G.gvm_submit(0, k, x, o, n)
+                assert t > 0, G.gvm_last_error()
+                assert G.gvm_wait(0, t, 60_000_000_000) == 0, G.gvm_last_error()
+                nan = np.isnan(ref)
+                assert np.array_equal(np.isnan(o), nan), (k, a[np.isnan(o) != nan], b[np.isnan(o) != nan])
+                bad = (o.view(np.uint32) != ref.view(np.uint32)) & ~nan
+                assert not bad.any(), (k, list(zip(a[bad][:8], b[bad][:8], o[bad][:8], ref[bad][:8])))
+        finally:
+            G.gvm_detach(0)
+
+
+C4 = 3   # seed index of the uneven-size batch (the bench's mixed32 uses the same draw)
+
+
+def _c4_jobs(reqs=1):
+    vec = wl.uneven_vecadd_sizes(C4, 16)
+    gemm = wl.uneven_sgemm_sizes(C4, 16)
+    specs = [(G.GVM_K_VECADD, n) for n in vec] + [(G.GVM_K_SGEMM, n) for n in gemm]
+    return [[(k, C4, n, q, False) for q in range(reqs)] for k, n in specs]
+
+
+def _c4_space(jobs):
+    return max((G.in_elems(k, n) + G.out_elems(k, n)) * 4 for js in jobs for (k, _, n, _, _) in js) + (1 << 20)
+
+
+def test_config4_uneven_batch_full_scale(ns_name):
+    # 32 ranks in one batch: 16 vector adds of n = floor(2^U[16,24]) and 16
+    # SGEMMs of sizes from {256, ..., 2048 step 64}, copies over PCIe in
+    # pieces, one grouped launch per kernel class.  Every output matches the
+    # oracle (vector add bit-exact, SGEMM <= 1e-4) and equals the same
+    # request run alone in the plain per-process path byte for byte.
+    jobs = _c4_jobs()
+    nr = len(jobs)
+    assert nr == 32
+    with hip_manager(ns_name, nranks=nr, policy=G.GVM_POLICY_GROUPED, shm_bytes_per_rank=_c4_space(jobs),
+                     hbm_budget_bytes=8 << 30, batch_window_us=30_000_000):
+        res = run_ranks(ns_name, jobs, barrier=threading.Barrier(nr))
+        st = G.gvm_stats_json()
+    assert st["batches"] == 1, st["batches"]
+    assert st["kernels"]["vecadd"]["launches"] == 1 and st["kernels"]["vecadd"]["requests"] == 16
+    assert st["kernels"]["sgemm"]["launches"] <= 2 and st["kernels"]["sgemm"]["requests"] == 16
+    for r in range(nr):
+        (k, cfg, n, req, integer), = jobs[r]
+        (o,) = check_ok(res[r])
+        assert_oracle(k, o, cfg, r, n, req, integer)
+        alone = np.empty(G.out_elems(k, n), np.float32)
+        rc, _ = G.gvm_plain_run(k, spmd.make_input(k, cfg, r, n, req, integer), alone, n)
+        assert rc == 0, G.gvm_last_error()
+        assert spmd.digest(alone) == res[r]["results"][0]["digest"], (r, k, n)
+
+
+def test_config4_graph_replay_equals_eager(ns_name):
+    # the same 32-rank uneven batch captured once as a HIP graph (copy-ins,
+    # the grouped launches, copy-outs) and replayed with one hipGraphLaunch
+    # per step for three steps of fresh inputs; every replay's result matches
+    # the oracle and equals the eager grouped batch byte for byte
+    jobs = _c4_jobs(reqs=3)
+    nr = len(jobs)
+    space = _c4_space(jobs)
+    with hip_manager(ns_name + "e", nranks=nr, policy=G.GVM_POLICY_GROUPED, shm_bytes_per_rank=space,
+                     hbm_budget_bytes=8 << 30, batch_window_us=30_000_000):
+        eager = run_ranks(ns_name + "e", jobs, barrier=threading.Barrier(nr), outputs=False)
+    with hip_manager(ns_name + "g", nranks=nr, policy=G.GVM_POLICY_GROUPED, shm_bytes_per_rank=space,
+                     hbm_budget_bytes=8 << 30, batch_window_us=30_000_000, use_graphs=1):
+        graph = run_ranks(ns_name + "g", jobs, barrier=threading.Barrier(nr))
+        st = G.gvm_stats_json()
+    assert st["device"]["graph_captures"] == 1, st["device"]
+    assert st["device"]["graph_launches"] == 3, st["device"]
+    assert st["batches"] == 3
+    for r in range(nr):
+        assert eager[r]["attach"] == 0 and graph[r]["attach"] == 0
+        for q, (k, cfg, n, req, integer) in enumerate(jobs[r]):
+            je, jg = eager[r]["results"][q], graph[r]["results"][q]
+            assert je["status"] == 0 and jg["status"] == 0, (je, jg)
+            assert jg["digest"] == je["digest"], (r, k, n, q)
+            assert_oracle(k, jg["out"], cfg, r, n, req, integer)

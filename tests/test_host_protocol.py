@@ -392,10 +392,10 @@ def test_hip_backend_fails_loudly_without_gpu(ns_name):
     assert glob.glob(f"/dev/shm/{ns_name}.*") == []
 
 
-def test_graph_replay_is_switched_off(ns_name):
-    cfg = loop_cfg(ns_name, use_graphs=1)
+def test_graph_replay_not_combined_with_cu_partition(ns_name):
+    cfg = loop_cfg(ns_name, use_graphs=1, mode=G.GVM_MODE_SERVING, latency_cus=64)
     assert G.gvm_init(cfg) == G.GVM_EINVAL
-    assert "graph" in G.gvm_last_error()
+    assert "use_graphs" in G.gvm_last_error()
 
 
 def _popcount(words):

@@ -51,10 +51,7 @@ def _bits(x) -> int:
 
 
 def _edge_floats():
-    vals = [0.0, -0.0, 1.0, -1.0, 1.5, 2.0 ** -126, 2.0 ** -149, -(2.0 ** -149), 3 * 2.0 ** -149,
-            1.0 + 2.0 ** -23, 1.0 - 2.0 ** -24, 3.4028234663852886e38, 2.0 ** 24, 2.0 ** 24 + 2.0,
-            0.1, 1e-30, 5e-39]
-    return [float(np.float32(v)) for v in vals]
+    return wl.edge_floats()
 
 
 def test_vecadd_matches_exact_rounding_random():
@@ -87,6 +84,34 @@ def test_vecadd_edge_values_and_ties():
     assert t[0] == np.float32(1.0)
     t = ok.vecadd_f32(np.array([1.0 + 2.0 ** -23], np.float32), np.array([2.0 ** -24], np.float32))
     assert t[0] == np.float32(1.0 + 2.0 ** -22)
+
+
+def test_vecadd_and_vecmul_on_the_edge_pair_grid():
+    # the operand grid the GPU parity test feeds the kernels: every finite
+    # pair against exact rational rounding (zeros by the IEEE sign rule),
+    # specials by the IEEE rules for inf and NaN
+    a, b = wl.edge_pairs()
+    for op, f in ((ok.vecadd_f32, lambda x, y: x + y), (ok.vecmul_f32, lambda x, y: x * y)):
+        c = op(a, b)
+        for x, y, z in zip(a.tolist(), b.tolist(), c.tolist()):
+            if math.isnan(x) or math.isnan(y):
+                assert math.isnan(z)
+                continue
+            if math.isinf(x) or math.isinf(y):
+                with np.errstate(invalid="ignore", over="ignore"):
+                    want = float(f(np.float64(x), np.float64(y)))
+                assert (math.isnan(z) and math.isnan(want)) or z == want, (x, y, z)
+                continue
+            exact = f(Fraction(x), Fraction(y))
+            want = _round_to_binary32(exact)
+            if want == 0.0:
+                if op is ok.vecadd_f32:
+                    neg = _bits(x) == _bits(-0.0) and _bits(y) == _bits(-0.0)
+                else:
+                    neg = (math.copysign(1.0, x) * math.copysign(1.0, y)) < 0
+                assert _bits(z) == (_bits(-0.0) if neg else 0), (x, y, z)
+            else:
+                assert _bits(z) == _bits(want), (x, y, z, want)
 
 
 def test_vecadd_special_values():
