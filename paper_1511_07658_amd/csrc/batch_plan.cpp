@@ -1,10 +1,10 @@
 #include "batch_plan.hpp"
 
-#include "gvm.h"
-
 #include <algorithm>
 #include <map>
 #include <utility>
+
+#include "gvm.h"
 
 namespace gvm {
 
@@ -35,15 +35,16 @@ std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstream
   return out;
 }
 
-BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool capture) {
+BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool graph) {
   BatchPlan p;
   p.groups = plan_groups(jobs, 2);
   p.stream_of.assign(jobs.size(), kPlanC0);
   for (const PlanGroup& g : p.groups)
     for (int j : g.jobs) p.stream_of[static_cast<size_t>(j)] = g.stream == 0 ? kPlanC0 : kPlanC1;
 
+  std::vector<PlanOp>* list = &p.ops;
   auto op = [&](int kind, int stream, int ev = -1, int job = -1, int group = -1) {
-    p.ops.push_back(PlanOp{kind, stream, ev, job, group});
+    list->push_back(PlanOp{kind, stream, ev, job, group});
   };
   auto record = [&](int stream) {
     const int e = p.events++;
@@ -51,8 +52,15 @@ BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool capture) {
     return e;
   };
 
-  if (capture) {  // fork: the other streams join the capture through C0
-    const int fork = record(kPlanC0);
+  bool any_pieces = false;
+  for (const PlanJob& j : jobs) any_pieces |= j.copy_in && j.pieces;
+  if (graph) {
+    if (any_pieces) {  // eager, before the launch: the graph starts after the input pieces
+      list = &p.pre;
+      op(kOpWait, kPlanC0, record(kPlanH2D));
+      list = &p.ops;
+    }
+    const int fork = record(kPlanC0);  // the other streams join the capture through C0
     for (int s : {kPlanH2D, kPlanD2H, kPlanC1}) op(kOpWait, s, fork);
   }
 
@@ -62,9 +70,15 @@ BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool capture) {
   for (size_t i = 0; i < jobs.size(); ++i) {
     const PlanJob& j = jobs[i];
     if (!j.copy_in) continue;
-    if (j.local) local_in = true;
-    else fifo_in = true;
-    if (!j.pieces) op(kOpCopyIn, j.local ? kPlanC0 : kPlanH2D, -1, static_cast<int>(i));
+    if (j.local) {
+      local_in = true;
+      op(kOpCopyIn, kPlanC0, -1, static_cast<int>(i));
+    } else if (!j.pieces) {
+      fifo_in = true;
+      op(kOpCopyIn, kPlanH2D, -1, static_cast<int>(i));
+    } else if (!graph) {
+      fifo_in = true;  // the wait below covers the pieces queued earlier
+    }
   }
   if (local_in && p.groups.size() > 1) op(kOpWait, kPlanC1, record(kPlanC0));  // C1's kernels may read C0's copies
   if (fifo_in) {
@@ -86,31 +100,53 @@ BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool capture) {
     if (last[c] >= 0) kend[c] = p.ops[static_cast<size_t>(last[c])].ev = p.events++;
 
   // copy-outs in job order: small ones on the stream that computed them, the
-  // rest on the D2H FIFO after that stream's kernels
+  // rest on the D2H FIFO after that stream's kernels (piecewise ones after
+  // the graph when there is one)
   int waited = -1;
   for (size_t i = 0; i < jobs.size(); ++i) {
     const PlanJob& j = jobs[i];
     const int ks = p.stream_of[i];
     const int job = static_cast<int>(i);
     if (!j.copy_out) {
-      if (!capture) op(kOpDone, ks, kend[ks], job);
+      if (!graph) op(kOpDone, ks, kend[ks], job);
       continue;
     }
     if (j.local) {
       op(kOpCopyOut, ks, -1, job);
-      if (!capture) op(kOpDone, ks, -1, job);
+      if (!graph) op(kOpDone, ks, -1, job);
       continue;
     }
+    if (graph && j.out_pieces) continue;
     if (waited != ks) {
       op(kOpWait, kPlanD2H, kend[ks]);
       waited = ks;
     }
     op(kOpCopyOut, kPlanD2H, -1, job);
-    if (!capture) op(kOpDone, kPlanD2H, -1, job);
+    if (!graph) op(kOpDone, kPlanD2H, -1, job);
   }
+  if (!graph) return p;
 
-  if (capture) {  // join: every forked stream ends in C0 after its last operation
-    for (int s : {kPlanC1, kPlanH2D, kPlanD2H}) op(kOpWait, kPlanC0, record(s));
+  // join: every forked stream ends in C0 after its last operation
+  for (int s : {kPlanC1, kPlanH2D, kPlanD2H}) op(kOpWait, kPlanC0, record(s));
+
+  // eager, after the launch on C0: the piecewise copy-outs, and the
+  // completion of every job
+  list = &p.post;
+  const int after = record(kPlanC0);
+  bool d2h_waits = false;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const PlanJob& j = jobs[i];
+    const int job = static_cast<int>(i);
+    if (j.copy_out && !j.local && j.out_pieces) {
+      if (!d2h_waits) {
+        op(kOpWait, kPlanD2H, after);
+        d2h_waits = true;
+      }
+      op(kOpCopyOut, kPlanD2H, -1, job);
+      op(kOpDone, kPlanD2H, -1, job);
+    } else {
+      op(kOpDone, kPlanC0, after, job);
+    }
   }
   return p;
 }

@@ -39,12 +39,13 @@ struct PlanOp {
 // What the schedule needs to know of one request.
 struct PlanJob {
   int kernel_id;
-  int cls;        // class within the kernel id: the SGEMM k depth BK, else 0
+  int cls;          // class within the kernel id: the SGEMM k depth BK, else 0
   uint64_t n;
   bool copy_in;
   bool copy_out;
-  bool local;     // copies small enough to stay on the kernel's own stream
-  bool pieces;    // input already queued piecewise on the H2D FIFO before the batch
+  bool local;       // copies small enough to stay on the kernel's own stream
+  bool pieces;      // input already queued piecewise on the H2D FIFO before the batch
+  bool out_pieces;  // output leaves piecewise on the D2H FIFO, an event after each piece
 };
 
 // One grouped launch: requests of one kernel id and class, at most
@@ -58,8 +59,14 @@ struct PlanGroup {
 
 constexpr int kPlanMaxGroup = 32;
 
+// Eager batch: everything is in `ops`.  Graph batch: `pre` runs eagerly
+// before the graph is launched on C0, `ops` is what the graph holds (captured
+// once, replayed after), and `post` runs eagerly after the launch.  Event ids
+// are shared by the three lists.
 struct BatchPlan {
+  std::vector<PlanOp> pre;
   std::vector<PlanOp> ops;
+  std::vector<PlanOp> post;
   std::vector<PlanGroup> groups;
   std::vector<int> stream_of;  // per job: the compute stream of its kernel
   int events = 0;              // event ids 0 .. events-1
@@ -73,9 +80,12 @@ std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstream
 // on the H2D FIFO), the grouped launches on C0 and C1 after the inputs they
 // read, copy-outs (local ones on the launch's own stream, the rest on the
 // D2H FIFO after the launch that computed them) and one completion per job.
-// With `capture`: the batch forks from C0 into the other three streams first
-// and every one of them joins C0 again after its last operation; no
-// completions (the replayed graph completes as a whole); no piecewise inputs.
-BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool capture);
+// With `graph`: the graph forks from C0 into the other three streams and
+// every one of them joins C0 again after its last operation.  Piecewise
+// copies stay outside the graph, since the host stages them piece by piece:
+// before the launch C0 waits for the H2D FIFO that holds the input pieces,
+// and after it the output pieces leave on the D2H FIFO.  The completions
+// follow the launch.
+BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool graph);
 
 }  // namespace gvm

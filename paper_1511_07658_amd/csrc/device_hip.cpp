@@ -627,7 +627,7 @@ class HipDevice final : public Device {
   static PlanJob plan_job(const Job* j) {
     const int k = static_cast<int>(j->req.kernel_id);
     return PlanJob{k, k == GVM_K_SGEMM ? gemm_config(gemm_config_for(j->req.n)).bk : 0, j->req.n,
-                   j->copy_in, j->copy_out, j->local, j->pieces};
+                   j->copy_in, j->copy_out, j->local, j->pieces && j->copy_in, j->out_pieces > 0};
   }
 
   // One grouped launch per kernel id (per k depth class for SGEMM), at most
@@ -740,24 +740,35 @@ class HipDevice final : public Device {
   }
 
   // Grouped policy: the batch plan (copy-ins, grouped launches on the two
-  // compute streams, copy-outs, completions), executed eagerly, or captured
-  // once per batch template (ranks, kernels, sizes, copies, buffers) and
-  // replayed as a graph with use_graphs.
+  // compute streams, copy-outs, completions), executed eagerly, or with
+  // use_graphs captured once per batch template (ranks, kernels, sizes,
+  // copies, buffers) and replayed, with the piecewise copies around it.
   int launch_grouped(Batch* b) {
     std::vector<Job*>& jobs = b->jobs;
-    hipStream_t c0 = compute_streams_[0];
-    if (!cfg_.use_graphs) return enqueue_grouped(b, false);
+    std::vector<PlanJob> pj;
+    for (const Job* j : jobs) pj.push_back(plan_job(j));
+    hipStream_t st[kPlanStreams] = {compute_streams_[0], compute_streams_[1], h2d_, d2h_};
+    if (jobs[0]->part >= 0 && part_streams_.size() == 2)
+      st[kPlanC0] = st[kPlanC1] = part_streams_[static_cast<size_t>(jobs[0]->part)];
+    if (!cfg_.use_graphs) {
+      const BatchPlan p = plan_grouped(pj, false);
+      PlanEvents ev(p);
+      return run_ops(p.ops, p, st, b, true, ev);
+    }
 
+    hipStream_t c0 = compute_streams_[0];
+    const BatchPlan p = plan_grouped(pj, true);
+    PlanEvents ev(p);
+    int rc = run_ops(p.pre, p, st, b, false, ev);
+    if (rc != GVM_OK) return rc;
     std::string key = graph_key(jobs);
     auto it = graphs_.find(key);
     if (it == graphs_.end()) {
       if (graphs_.size() >= kMaxGraphs) evict_graph();
-      for (Job* j : jobs)
-        if (j->pieces) return fail(GVM_EINVAL, "a piecewise input cannot be part of a captured batch");
       HIPCHK(hipStreamBeginCapture(c0, hipStreamCaptureModeThreadLocal));
       capturing_ = true;
       capture_events_.clear();
-      int rc = enqueue_grouped(b, true);
+      rc = run_ops(p.ops, p, st, b, false, ev);
       capturing_ = false;
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(c0, &g);
@@ -809,28 +820,23 @@ class HipDevice final : public Device {
     HIPCHK(hipEventRecord(t.e1, c0));
     b->timed.push_back(t);
     ++graph_launches_;
-    hipEvent_t done = sync_event(b);
-    if (!done) return GVM_EDEVICE;
-    HIPCHK(hipEventRecord(done, c0));
-    track(b, done, c0);
-    for (size_t i = 0; i < jobs.size(); ++i) b->done[i] = done;
-    return GVM_OK;
+    return run_ops(p.post, p, st, b, false, ev);
   }
 
-  // Execute the batch plan of a grouped batch.  `capture`: inside a stream
-  // capture on compute stream 0 (untimed; the plan forks from and joins
-  // back into it, and has no per-job completions).
-  int enqueue_grouped(Batch* b, bool capture) {
+  // Device events of a plan's event ids, and the stream each was recorded on.
+  struct PlanEvents {
+    explicit PlanEvents(const BatchPlan& p)
+        : ev(static_cast<size_t>(p.events), nullptr), stream(static_cast<size_t>(p.events), nullptr) {}
+    std::vector<hipEvent_t> ev;
+    std::vector<hipStream_t> stream;
+  };
+
+  // Execute plan operations on the streams `st` (indexed by PlanStream).
+  // `timed`: launches are bracketed by timing events (eager batches only).
+  int run_ops(const std::vector<PlanOp>& ops, const BatchPlan& p, const hipStream_t* st, Batch* b, bool timed,
+              PlanEvents& pe) {
     std::vector<Job*>& jobs = b->jobs;
-    hipStream_t st[kPlanStreams] = {compute_streams_[0], compute_streams_[1], h2d_, d2h_};
-    if (jobs[0]->part >= 0 && part_streams_.size() == 2)
-      st[kPlanC0] = st[kPlanC1] = part_streams_[static_cast<size_t>(jobs[0]->part)];
-    std::vector<PlanJob> pj;
-    for (const Job* j : jobs) pj.push_back(plan_job(j));
-    const BatchPlan p = plan_grouped(pj, capture);
-    std::vector<hipEvent_t> ev(static_cast<size_t>(p.events), nullptr);
-    std::vector<hipStream_t> ev_stream(static_cast<size_t>(p.events), nullptr);
-    for (const PlanOp& o : p.ops) {
+    for (const PlanOp& o : ops) {
       hipStream_t s = st[o.stream];
       int rc = GVM_OK;
       switch (o.kind) {
@@ -838,12 +844,12 @@ class HipDevice final : public Device {
           hipEvent_t e = sync_event(b);
           if (!e) return GVM_EDEVICE;
           HIPCHK(hipEventRecord(e, s));
-          ev[static_cast<size_t>(o.ev)] = e;
-          ev_stream[static_cast<size_t>(o.ev)] = s;
+          pe.ev[static_cast<size_t>(o.ev)] = e;
+          pe.stream[static_cast<size_t>(o.ev)] = s;
           break;
         }
         case kOpWait:
-          HIPCHK(hipStreamWaitEvent(s, ev[static_cast<size_t>(o.ev)], 0));
+          HIPCHK(hipStreamWaitEvent(s, pe.ev[static_cast<size_t>(o.ev)], 0));
           break;
         case kOpCopyIn:
           rc = enqueue_in(jobs[static_cast<size_t>(o.job)], s);
@@ -853,22 +859,22 @@ class HipDevice final : public Device {
           break;
         case kOpLaunch: {
           hipEvent_t end = nullptr;
-          rc = launch_group(p.groups[static_cast<size_t>(o.group)], jobs, s, b, !capture, &end);
+          rc = launch_group(p.groups[static_cast<size_t>(o.group)], jobs, s, b, timed, &end);
           if (rc == GVM_OK && o.ev >= 0) {
             if (!end) {  // untimed: a marker of its own
               end = sync_event(b);
               if (!end) return GVM_EDEVICE;
               HIPCHK(hipEventRecord(end, s));
             }
-            ev[static_cast<size_t>(o.ev)] = end;
-            ev_stream[static_cast<size_t>(o.ev)] = s;
+            pe.ev[static_cast<size_t>(o.ev)] = end;
+            pe.stream[static_cast<size_t>(o.ev)] = s;
           }
           break;
         }
         case kOpDone:
           if (o.ev >= 0) {
-            b->done[static_cast<size_t>(o.job)] = ev[static_cast<size_t>(o.ev)];
-            track(b, ev[static_cast<size_t>(o.ev)], ev_stream[static_cast<size_t>(o.ev)]);
+            b->done[static_cast<size_t>(o.job)] = pe.ev[static_cast<size_t>(o.ev)];
+            track(b, pe.ev[static_cast<size_t>(o.ev)], pe.stream[static_cast<size_t>(o.ev)]);
           } else {
             rc = record_done(b, static_cast<size_t>(o.job), s);
           }

@@ -605,10 +605,10 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   j->copy_out = copy_out;
   j->t_admit_ns = now_ns();
   // small copies stay with the kernel; whole copies where a batch's device
-  // phase is timed as one span, or captured into a graph (a piece is
-  // enqueued when it lands, outside any capture); pieces otherwise
+  // phase is timed as one span; pieces otherwise (each piece is enqueued when
+  // it lands, outside any graph)
   j->local = (copy_in ? lay.in_bytes : 0) + (copy_out ? lay.out_bytes : 0) <= kLocalCopyBytes;
-  j->pieces = !j->local && !(cfg_.batch_timing && cfg_.mode == GVM_MODE_BATCH) && !cfg_.use_graphs;
+  j->pieces = !j->local && !(cfg_.batch_timing && cfg_.mode == GVM_MODE_BATCH);
   if (j->pieces && copy_out) j->out_pieces = piece_count(lay.out_bytes);
   if (copy_in) {
     j->stage = kStageCopyIn;

@@ -69,21 +69,122 @@ struct Sim {
   }
 };
 
-const char* check(const BatchPlan& p, const std::vector<PlanJob>& jobs, bool capture, std::string* why) {
+// Replays one operation list.  `capture`: the list is being captured.
+struct Replay {
+  const BatchPlan& p;
+  const std::vector<PlanJob>& jobs;
   Sim sim;
-  sim.ev.resize(static_cast<size_t>(p.events));
-  sim.joined_at.assign(kPlanStreams, -1);
   int pieces_node = -1;
-  bool any_pieces = false;
-  for (const PlanJob& j : jobs) any_pieces |= j.pieces && j.copy_in;
-  if (any_pieces) {
-    if (capture) return "a piecewise input in a captured batch";
-    pieces_node = sim.add_node(kPlanH2D);
+  std::vector<int> in_node, out_node, launch_node, launched, done;
+  std::string* why;
+
+  Replay(const BatchPlan& plan, const std::vector<PlanJob>& js, std::string* w)
+      : p(plan), jobs(js), in_node(js.size(), -1), out_node(js.size(), -1), launch_node(js.size(), -1),
+        launched(js.size(), 0), done(js.size(), 0), why(w) {
+    sim.ev.resize(static_cast<size_t>(p.events));
+    sim.joined_at.assign(kPlanStreams, -1);
   }
-  if (capture) sim.capturing[kPlanC0] = true;
-  std::vector<int> in_node(jobs.size(), -1), out_node(jobs.size(), -1), launch_node(jobs.size(), -1);
-  std::vector<int> launched(jobs.size(), 0), done(jobs.size(), 0);
-  std::vector<std::set<int>> done_set(jobs.size());
+
+  const char* run(const std::vector<PlanOp>& ops, bool capture) {
+    for (const PlanOp& o : ops) {
+      if (o.stream < 0 || o.stream >= kPlanStreams) return "bad stream";
+      const bool joins = o.kind == kOpWait && o.ev >= 0 && o.ev < p.events && sim.ev[static_cast<size_t>(o.ev)].captured;
+      if (capture && !sim.capturing[o.stream] && !joins) {
+        *why = "operation kind " + std::to_string(o.kind) + " on stream " + std::to_string(o.stream);
+        return "operation on a stream outside the capture";
+      }
+      sim.position[o.stream]++;
+      switch (o.kind) {
+        case kOpRecord: {
+          if (o.ev < 0 || o.ev >= p.events || sim.ev[static_cast<size_t>(o.ev)].recorded) return "event recorded twice or out of range";
+          sim.ev[static_cast<size_t>(o.ev)] = Sim::Ev{sim.frontier[o.stream], o.stream, sim.position[o.stream], sim.capturing[o.stream], true};
+          break;
+        }
+        case kOpWait: {
+          if (o.ev < 0 || o.ev >= p.events || !sim.ev[static_cast<size_t>(o.ev)].recorded) return "wait for an event not yet recorded";
+          const Sim::Ev& e = sim.ev[static_cast<size_t>(o.ev)];
+          if (capture && !sim.capturing[o.stream]) {
+            // joining a capture: what the stream ran eagerly before is no
+            // dependency of its captured work
+            sim.frontier[o.stream] = e.nodes;
+            sim.capturing[o.stream] = true;
+          } else {
+            if (capture != e.captured) return "a wait across the boundary of the capture";
+            sim.frontier[o.stream].insert(e.nodes.begin(), e.nodes.end());
+          }
+          if (o.stream == kPlanC0) sim.joined_at[static_cast<size_t>(e.stream)] = e.position;
+          break;
+        }
+        case kOpCopyIn: {
+          const size_t j = static_cast<size_t>(o.job);
+          if (o.job < 0 || j >= jobs.size() || !jobs[j].copy_in || jobs[j].pieces || in_node[j] >= 0) return "bad copy-in";
+          in_node[j] = sim.add_node(o.stream);
+          break;
+        }
+        case kOpLaunch: {
+          if (o.group < 0 || static_cast<size_t>(o.group) >= p.groups.size()) return "bad group";
+          const int id = sim.add_node(o.stream);
+          for (int j : p.groups[static_cast<size_t>(o.group)].jobs) {
+            const size_t u = static_cast<size_t>(j);
+            launch_node[u] = id;
+            launched[u]++;
+            const PlanJob& pj = jobs[u];
+            if (pj.copy_in && !pj.pieces && (in_node[u] < 0 || !sim.ancestor(in_node[u], id))) {
+              *why = "job " + std::to_string(j);
+              return "a launch does not wait for its copy-in";
+            }
+            if (pj.copy_in && pj.pieces && !sim.ancestor(pieces_node, id)) {
+              *why = "job " + std::to_string(j);
+              return "a launch does not wait for its piecewise input";
+            }
+          }
+          if (o.ev >= 0) {
+            if (o.ev >= p.events || sim.ev[static_cast<size_t>(o.ev)].recorded) return "launch marker recorded twice";
+            sim.ev[static_cast<size_t>(o.ev)] = Sim::Ev{sim.frontier[o.stream], o.stream, sim.position[o.stream],
+                                                       sim.capturing[o.stream], true};
+          }
+          break;
+        }
+        case kOpCopyOut: {
+          const size_t j = static_cast<size_t>(o.job);
+          if (o.job < 0 || j >= jobs.size() || !jobs[j].copy_out || out_node[j] >= 0) return "bad copy-out";
+          out_node[j] = sim.add_node(o.stream);
+          if (launch_node[j] < 0 || !sim.ancestor(launch_node[j], out_node[j])) {
+            *why = "job " + std::to_string(j);
+            return "a copy-out does not wait for its launch";
+          }
+          break;
+        }
+        case kOpDone: {
+          const size_t j = static_cast<size_t>(o.job);
+          if (capture) return "a per-job completion inside a capture";
+          if (o.job < 0 || j >= jobs.size()) return "bad completion";
+          done[j]++;
+          std::set<int> at;
+          if (o.ev >= 0) {
+            if (o.ev >= p.events || !sim.ev[static_cast<size_t>(o.ev)].recorded) return "completion on an unrecorded event";
+            at = sim.ev[static_cast<size_t>(o.ev)].nodes;
+          } else {
+            at = sim.frontier[o.stream];
+          }
+          const int last = jobs[j].copy_out ? out_node[j] : launch_node[j];
+          if (last < 0 || !sim.covered(last, at)) {
+            *why = "job " + std::to_string(j);
+            return "a completion does not follow the job's last operation";
+          }
+          break;
+        }
+        default:
+          return "unknown operation";
+      }
+    }
+    return nullptr;
+  }
+};
+
+const char* check(const BatchPlan& p, const std::vector<PlanJob>& jobs, bool graph, std::string* why) {
+  Replay R(p, jobs, why);
+  Sim& sim = R.sim;
   for (size_t g = 0; g < p.groups.size(); ++g) {
     const PlanGroup& G = p.groups[g];
     if (G.jobs.empty() || G.jobs.size() > static_cast<size_t>(kPlanMaxGroup)) return "group size out of range";
@@ -94,103 +195,49 @@ const char* check(const BatchPlan& p, const std::vector<PlanJob>& jobs, bool cap
         return "SGEMM group not largest first";
     }
   }
-  for (const PlanOp& o : p.ops) {
-    if (o.stream < 0 || o.stream >= kPlanStreams) return "bad stream";
-    const bool joins = o.kind == kOpWait && o.ev >= 0 && o.ev < p.events && sim.ev[static_cast<size_t>(o.ev)].captured;
-    if (capture && !sim.capturing[o.stream] && !joins) {
-      *why = "operation kind " + std::to_string(o.kind) + " on stream " + std::to_string(o.stream);
-      return "operation on a stream outside the capture";
-    }
-    sim.position[o.stream]++;
-    switch (o.kind) {
-      case kOpRecord: {
-        if (o.ev < 0 || o.ev >= p.events || sim.ev[static_cast<size_t>(o.ev)].recorded) return "event recorded twice or out of range";
-        Sim::Ev& e = sim.ev[static_cast<size_t>(o.ev)];
-        e = Sim::Ev{sim.frontier[o.stream], o.stream, sim.position[o.stream], sim.capturing[o.stream], true};
-        break;
-      }
-      case kOpWait: {
-        if (o.ev < 0 || o.ev >= p.events || !sim.ev[static_cast<size_t>(o.ev)].recorded) return "wait for an event not yet recorded";
-        const Sim::Ev& e = sim.ev[static_cast<size_t>(o.ev)];
-        sim.frontier[o.stream].insert(e.nodes.begin(), e.nodes.end());
-        if (e.captured) sim.capturing[o.stream] = true;
-        if (o.stream == kPlanC0) sim.joined_at[static_cast<size_t>(e.stream)] = e.position;
-        break;
-      }
-      case kOpCopyIn:
-        if (o.job < 0 || static_cast<size_t>(o.job) >= jobs.size() || !jobs[static_cast<size_t>(o.job)].copy_in ||
-            in_node[static_cast<size_t>(o.job)] >= 0)
-          return "bad copy-in";
-        in_node[static_cast<size_t>(o.job)] = sim.add_node(o.stream);
-        break;
-      case kOpLaunch: {
-        if (o.group < 0 || static_cast<size_t>(o.group) >= p.groups.size()) return "bad group";
-        const int id = sim.add_node(o.stream);
-        for (int j : p.groups[static_cast<size_t>(o.group)].jobs) {
-          launch_node[static_cast<size_t>(j)] = id;
-          launched[static_cast<size_t>(j)]++;
-          const PlanJob& pj = jobs[static_cast<size_t>(j)];
-          if (pj.copy_in && !pj.pieces && (in_node[static_cast<size_t>(j)] < 0 || !sim.ancestor(in_node[static_cast<size_t>(j)], id))) {
-            *why = "job " + std::to_string(j);
-            return "a launch does not wait for its copy-in";
-          }
-          if (pj.copy_in && pj.pieces && !sim.ancestor(pieces_node, id)) return "a launch does not wait for its piecewise input";
-        }
-        if (o.ev >= 0) {
-          if (o.ev >= p.events || sim.ev[static_cast<size_t>(o.ev)].recorded) return "launch marker recorded twice";
-          sim.ev[static_cast<size_t>(o.ev)] = Sim::Ev{sim.frontier[o.stream], o.stream, sim.position[o.stream],
-                                                     sim.capturing[o.stream], true};
-        }
-        break;
-      }
-      case kOpCopyOut: {
-        const size_t j = static_cast<size_t>(o.job);
-        if (o.job < 0 || j >= jobs.size() || !jobs[j].copy_out || out_node[j] >= 0) return "bad copy-out";
-        out_node[j] = sim.add_node(o.stream);
-        if (launch_node[j] < 0 || !sim.ancestor(launch_node[j], out_node[j])) {
-          *why = "job " + std::to_string(j);
-          return "a copy-out does not wait for its launch";
-        }
-        break;
-      }
-      case kOpDone: {
-        const size_t j = static_cast<size_t>(o.job);
-        if (capture) return "a per-job completion inside a capture";
-        if (o.job < 0 || j >= jobs.size()) return "bad completion";
-        done[j]++;
-        std::set<int> at;
-        if (o.ev >= 0) {
-          if (o.ev >= p.events || !sim.ev[static_cast<size_t>(o.ev)].recorded) return "completion on an unrecorded event";
-          at = sim.ev[static_cast<size_t>(o.ev)].nodes;
-        } else {
-          at = sim.frontier[o.stream];
-        }
-        const int last = jobs[j].copy_out ? out_node[j] : launch_node[j];
-        if (last < 0 || !sim.covered(last, at)) {
-          *why = "job " + std::to_string(j);
-          return "a completion does not follow the job's last operation";
-        }
-        break;
-      }
-      default:
-        return "unknown operation";
-    }
-  }
-  for (size_t j = 0; j < jobs.size(); ++j) {
-    if (launched[j] != 1) return "a job is not launched exactly once";
-    if (jobs[j].copy_out && out_node[j] < 0) return "a copy-out is missing";
-    if (jobs[j].copy_in && !jobs[j].pieces && in_node[j] < 0) return "a copy-in is missing";
-    if (!capture && done[j] != 1) return "a job has no single completion";
-  }
-  if (capture) {
+  bool any_pieces = false;
+  for (const PlanJob& j : jobs) any_pieces |= j.pieces && j.copy_in;
+  if (any_pieces) R.pieces_node = sim.add_node(kPlanH2D);  // queued before the batch
+  const char* err = nullptr;
+  if (!graph) {
+    if (!p.pre.empty() || !p.post.empty()) return "an eager batch with pre or post operations";
+    err = R.run(p.ops, false);
+  } else {
+    err = R.run(p.pre, false);
+    if (err) return err;
+    // the capture: C0 starts it; captured work is on no stream afterwards
+    std::set<int> saved[kPlanStreams];
+    for (int s = 0; s < kPlanStreams; ++s) saved[s] = sim.frontier[s];
+    const size_t first = sim.nodes.size();
+    const int pos0[kPlanStreams] = {sim.position[0], sim.position[1], sim.position[2], sim.position[3]};
+    sim.capturing[kPlanC0] = true;
+    err = R.run(p.ops, true);
+    if (err) return err;
     for (int s = 1; s < kPlanStreams; ++s) {
-      if (!sim.capturing[s]) continue;
+      if (!sim.capturing[s] || sim.position[s] == pos0[s]) continue;
       if (sim.joined_at[static_cast<size_t>(s)] != sim.position[s]) {
-        *why = "stream " + std::to_string(s) + " has " + std::to_string(sim.position[s]) + " operations, joined after " +
-               std::to_string(sim.joined_at[static_cast<size_t>(s)]);
+        *why = "stream " + std::to_string(s) + " has " + std::to_string(sim.position[s] - pos0[s]) +
+               " captured operations, joined after " + std::to_string(sim.joined_at[static_cast<size_t>(s)] - pos0[s]);
         return "a stream forked into the capture is not joined after its last operation";
       }
     }
+    for (int s = 0; s < kPlanStreams; ++s) {
+      sim.capturing[s] = false;
+      sim.frontier[s] = saved[s];
+    }
+    // the graph launch on C0: after C0's eager work, and containing every captured node
+    std::set<int> deps = saved[kPlanC0];
+    for (size_t x = first; x < sim.nodes.size(); ++x) deps.insert(static_cast<int>(x));
+    sim.nodes.push_back(Sim::Node{deps});
+    sim.frontier[kPlanC0] = {static_cast<int>(sim.nodes.size() - 1)};
+    err = R.run(p.post, false);
+  }
+  if (err) return err;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    if (R.launched[j] != 1) return "a job is not launched exactly once";
+    if (jobs[j].copy_out && R.out_node[j] < 0) return "a copy-out is missing";
+    if (jobs[j].copy_in && !jobs[j].pieces && R.in_node[j] < 0) return "a copy-in is missing";
+    if (R.done[j] != 1) return "a job has no single completion";
   }
   return nullptr;
 }
@@ -205,18 +252,18 @@ PlanJob job(int k, uint64_t n, bool in, bool out, bool pieces = false) {
   }
   const bool local = (in ? in_b : 0) + (out ? out_b : 0) <= (1u << 20);
   const int cls = k == GVM_K_SGEMM ? (n <= 768 ? 16 : (n % 256 == 0 ? 32 : 16)) : 0;
-  return PlanJob{k, cls, n, in, out, local, pieces && in && !local};
+  return PlanJob{k, cls, n, in, out, local, pieces && in && !local, pieces && out && !local};
 }
 
 int failures = 0;
 
-void expect_ok(const char* name, const std::vector<PlanJob>& jobs, bool capture) {
+void expect_ok(const char* name, const std::vector<PlanJob>& jobs, bool graph) {
   std::string why;
-  const BatchPlan p = plan_grouped(jobs, capture);
-  const char* err = check(p, jobs, capture, &why);
+  const BatchPlan p = plan_grouped(jobs, graph);
+  const char* err = check(p, jobs, graph, &why);
   if (err) {
     if (++failures > 20) return;
-    printf("FAIL %s (%s): %s %s\n", name, capture ? "capture" : "eager", err, why.c_str());
+    printf("FAIL %s (%s): %s %s\n", name, graph ? "graph" : "eager", err, why.c_str());
   }
 }
 
@@ -310,9 +357,34 @@ int main() {
       jobs.push_back(job(k, n, in, out, rng() % 2 == 0));
     }
     std::vector<PlanJob> whole = jobs;
-    for (auto& j : whole) j.pieces = false;
-    expect_ok("random", whole, true);
-    expect_ok("random", jobs, false);
+    for (auto& j : whole) j.pieces = j.out_pieces = false;
+    expect_ok("random whole copies", whole, true);
+    expect_ok("random whole copies", whole, false);
+    expect_ok("random pieces", jobs, true);
+    expect_ok("random pieces", jobs, false);
+  }
+  // the 32-rank uneven batch: 16 vector adds and 16 SGEMMs, copies in pieces
+  {
+    const uint64_t vec[] = {13474670, 2746283, 151966, 260220, 877892, 302835, 14520833, 11550894,
+                            76752, 324147, 9554722, 72333, 11775798, 1539844, 174914, 491127};
+    const uint64_t gemm[] = {704, 1280, 960, 384, 1728, 1216, 1216, 1920, 704, 448, 832, 1408, 704, 1664, 832, 1280};
+    std::vector<PlanJob> c4;
+    for (uint64_t n : vec) c4.push_back(job(GVM_K_VECADD, n, true, true, true));
+    for (uint64_t n : gemm) c4.push_back(job(GVM_K_SGEMM, n, true, true, true));
+    expect_ok("uneven 32-rank batch", c4, true);
+    expect_ok("uneven 32-rank batch", c4, false);
+    // a graph launched without first waiting for the input pieces
+    BatchPlan bad = plan_grouped(c4, true);
+    const size_t had = bad.pre.size();
+    bad.pre.clear();
+    std::string why;
+    const char* err = check(bad, c4, true, &why);
+    if (had == 0 || !err || std::string(err).find("piecewise input") == std::string::npos) {
+      ++failures;
+      printf("FAIL: a graph that does not wait for the input pieces was not detected (%s)\n", err ? err : "accepted");
+    } else {
+      printf("graph without the input wait detected: %s (%s)\n", err, why.c_str());
+    }
   }
   // one kernel kind only (one group, compute stream 1 idle), and 33 requests of one class (two groups)
   expect_ok("single", {job(GVM_K_SGEMM, 1024, true, true)}, true);

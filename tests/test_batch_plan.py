@@ -7,9 +7,10 @@ dependencies per request (copy-in, launch, copy-out, completion), every
 operation of a capture on a capturing stream, and every stream forked into a
 capture joined back into the origin after its last operation.  It also
 replays the earlier capture schedule, which joined compute stream 1 right
-after its kernels and before the small copy-outs queued behind them, and a
-schedule with a missing wait for the host-to-device FIFO: the check must
-reject both.
+after its kernels and before the small copy-outs queued behind them, a
+schedule with a missing wait for the host-to-device FIFO, and a graph
+launched without first waiting for its input pieces: the check must reject
+all three.
 """
 
 import os
@@ -31,4 +32,5 @@ def test_batch_plan_dependencies_and_capture_joins(tmp_path):
     assert p.returncode == 0, p.stdout
     assert "early join detected: a stream forked into the capture is not joined" in p.stdout, p.stdout
     assert "missing input wait detected" in p.stdout, p.stdout
+    assert "graph without the input wait detected" in p.stdout, p.stdout
     assert p.stdout.strip().endswith("ok: 0 failures"), p.stdout
