@@ -23,7 +23,8 @@ void Arena::init(uint64_t bytes) {
   free_.clear();
   total_ = bytes / 4096 * 4096;
   if (total_) free_[0] = total_;
-  used_ = peak_ = 0;
+  used_ = 0;
+  peak_.store(0, std::memory_order_relaxed);
 }
 
 bool Arena::alloc(uint64_t bytes, uint64_t* off) {
@@ -36,7 +37,7 @@ bool Arena::alloc(uint64_t bytes, uint64_t* off) {
       free_.erase(it);
       if (rest) free_[at] = rest;
       used_ += bytes;
-      peak_ = std::max(peak_, used_);
+      if (used_ > peak_.load(std::memory_order_relaxed)) peak_.store(used_, std::memory_order_relaxed);
       return true;
     }
   }
@@ -553,8 +554,8 @@ bool Manager::launch_ready() {
 
 Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   RankRt& rt = ranks_[r];
-  const Queued& q = rt.queue.front();
-  const Request& m = q.req;
+  // a copy: the queue entry is popped below, before the last reads of the request
+  const Request m = rt.queue.front().req;
   Layout lay;
   request_layout(static_cast<int>(m.kernel_id), m.n, &lay);
   const uint64_t need = slot_bytes(lay);
@@ -759,7 +760,10 @@ int Manager::stats_json(std::string* out) {
     flush_req_.store(true, std::memory_order_release);
     ctl_->bell.fetch_add(1, std::memory_order_seq_cst);
     futex_wake_all(&ctl_->bell);
-    flush_cv_.wait_for(fl, std::chrono::milliseconds(200),
+    // bounded by the wall clock: a wait on the system clock is a plain timed
+    // condition wait, which thread checkers follow (a steady-clock wait is
+    // not followed by some of them and reads as a lock held across it)
+    flush_cv_.wait_until(fl, std::chrono::system_clock::now() + std::chrono::milliseconds(200),
                        [&] { return flush_done_ != gen || stop_.load(std::memory_order_acquire); });
   }
   std::lock_guard<std::mutex> lk(stats_mu_);

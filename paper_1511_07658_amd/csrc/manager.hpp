@@ -29,13 +29,15 @@ class Arena {
   void release(uint64_t off, uint64_t bytes);
   uint64_t total() const { return total_; }
   uint64_t used() const { return used_; }
-  uint64_t peak() const { return peak_; }
-  void reset_peak() { peak_ = used_; }
+  // the peak is also read by statistics readers on other threads
+  uint64_t peak() const { return peak_.load(std::memory_order_relaxed); }
+  void reset_peak() { peak_.store(used_, std::memory_order_relaxed); }
   static uint64_t round(uint64_t bytes) { return (bytes + 4095) / 4096 * 4096; }
 
  private:
   std::map<uint64_t, uint64_t> free_;  // offset -> bytes
-  uint64_t total_ = 0, used_ = 0, peak_ = 0;
+  uint64_t total_ = 0, used_ = 0;
+  std::atomic<uint64_t> peak_{0};
 };
 
 class Manager {
