@@ -1,17 +1,30 @@
 """Benchmark of the GVM hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sgemm8|vecadd4|vecadd16|bs16|ep8|mixed32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mixed32|sgemm8|vecadd4|vecadd16|bs16|ep8]
 
-Default workload (the configuration the headline metric is quoted on): 8 SPMD
-rank processes, each an FP32 square GEMM C = A B with 1024 x 1024 A, B ~ N(0,1)
-seeded by rank, served by one GVM manager on device 0.  One step = every rank
-submits its request through the shared-memory rings, the manager gathers the
-batch at its request barrier, runs one grouped persistent MFMA launch over all
-eight GEMMs, and every rank receives its completion.  The inputs are resident
-in HBM when the timed region starts (submitted once before it, then re-used
-with GVM_F_IN_RESIDENT | GVM_F_OUT_RESIDENT), so ``value`` is whole-job device
-throughput plus the manager round trip; the PCIe-inclusive rate and the plain
-per-process baseline (Eq. 1 path) are reported beside it.
+Default workload: 32 SPMD rank processes with uneven sizes, served by one GVM
+manager on device 0 -- 16 FP32 vector adds with n = floor(2^U[16,24]) and 16
+FP32 SGEMMs with n drawn from {256, ..., 2048} step 64, seeded by rank.  One
+step is every row of the method's hot path: each rank submits its request
+through the shared-memory rings (its input already built in its
+shared-memory space), the manager gathers the batch at its request barrier,
+copies every input to HBM, runs one grouped launch per kernel class, copies
+every result back, and every rank receives its completion with the result in
+its shared memory.  ``value`` is the SGEMM GFLOP/s of those whole steps,
+copies included (the vector adds' GB/s go beside it).
+
+Beside it:
+* ``device_phase`` / ``roofline``: the same requests with inputs and results
+  left resident in HBM (GVM_F_IN_RESIDENT | GVM_F_OUT_RESIDENT), so a step is
+  the manager round trip plus the kernels; the dominant kernel's roofline
+  fraction comes from device events around its launches;
+* ``plain*``: the plain per-process method (own context, pageable copies,
+  allocate / free per request; Eq. 1 path) in three variants; above 16 ranks
+  the ranks are dealt round robin onto 16 processes, each running its ranks'
+  requests one after another;
+* ``serving``: a short run of the serving configuration (64 open-loop ranks,
+  Poisson arrivals at 2000 requests/s) with its p50 / p99 latency;
+* ``cpu_baseline``: the oracle on the host cores over a bounded sample.
 
 Prints ONE JSON line.
 """
@@ -19,10 +32,13 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
+import math
 import os
 import platform
 import sys
+import threading
 import time
 
 import numpy as np
@@ -36,15 +52,24 @@ from paper_1511_07658_amd import spmd  # noqa: E402
 from paper_1511_07658_amd import workloads as wl  # noqa: E402
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
-# EP-like kernel: VALU issue bound.  A SIMD issues one wave64 VALU
-# instruction per 4 cycles (16 lanes); the compiled unit loop of
-# csrc/ep_kernels.hip issues 602 VALU instructions per Philox block, i.e.
-# per 2 pairs of each of the 64 lanes (both pairs accepted; the rejected path
-# is a subset): 4 * 602 / 128 = 18.8 SIMD cycles per pair, and 256 CUs x 4
-# SIMDs x 2.4 GHz / 18.8 = 130.6 Gpairs/s.
+MAX_GPU_PROCESSES = 16
+
+# EP-like kernel.  Its roofline counts the method's binary64 operations per
+# generated pair (the definition in include/gvm.h, each of log, sqrt and
+# divide as one operation): scaling both words to [0, 1) (2), x = 2u - 1 and
+# y = 2v - 1 (4), t = x^2 + y^2 (3); for an accepted pair (probability pi/4):
+# ln t, -2 ln t / t, the square root, X and Y, the two sums and max(|X|, |Y|)
+# (9).  Against the chip's binary64 vector peak; the counter-based generator's
+# 64-bit integer products, which dominate the kernel, are not in the count.
+EP_FP64_OPS_PER_PAIR = 9.0 + math.pi / 4.0 * 9.0
+# VALU issue utilisation of the compiled kernel (a diagnostic of the code,
+# not a roofline): the unit loop of csrc/ep_kernels.hip issues 602 wave64
+# VALU instructions per Philox block (2 pairs per lane, both accepted), one
+# per 4 cycles per SIMD: 4 * 602 / 128 SIMD cycles per pair.
 EP_SIMD_CYCLES_PER_PAIR = 4.0 * 602 / 128
-PEAK_EP_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
+EP_ISSUE_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
@@ -82,16 +107,18 @@ def measured_traffic(workload):
         return None
     return round((m["fetch_kib"] * m["fetch_factor"] + m["write_kib"] * m["write_factor"]) * 1024)
 
+
 WORKLOADS = {
-    "sgemm8": "8 ranks via GVM, FP32 SGEMM 1024x1024 each, grouped MFMA launch, inputs resident in HBM",
-    "vecadd4": "4 ranks via GVM, FP32 vector add n=2^20 each, inputs resident in HBM",
+    "mixed32": "32 ranks via GVM with uneven sizes: 16 FP32 vector adds n=floor(2^U[16,24]) and 16 FP32 SGEMMs "
+               "n in {256..2048 step 64}, tuned tiles, one grouped launch per kernel class per step; "
+               "inputs from the ranks' shared memory, copies to and from HBM in every step",
+    "sgemm8": "8 ranks via GVM, FP32 SGEMM 1024x1024 each, grouped MFMA launch; copies in every step",
+    "vecadd4": "4 ranks via GVM, FP32 vector add n=2^20 each; copies in every step",
     "vecadd16": "16 ranks via GVM, FP32 vector add n=2^24 each (3.2 GB per step, beyond the memory-side cache), "
-                "one grouped launch, inputs resident in HBM",
-    "bs16": "16 ranks via GVM, FP32 Black-Scholes 4M options each, one fused launch, inputs resident in HBM",
-    "mixed32": "32 ranks via GVM with uneven sizes: 16 vector adds n=floor(2^U[16,24]) and 16 SGEMMs "
-               "n in {256..2048 step 64}, tuned tiles, one grouped launch per kernel per step, inputs resident in HBM",
+                "one grouped launch; copies in every step",
+    "bs16": "16 ranks via GVM, FP32 Black-Scholes 4M options each, one fused launch; copies in every step",
     "ep8": "8 ranks via GVM, EP-like Gaussian-pair tally of 2^24 pairs each (the size of the paper's EP(M24)), "
-           "one grouped launch plus a per-request reduction, keys and results resident in HBM",
+           "one grouped launch plus a per-request reduction",
 }
 
 
@@ -128,79 +155,86 @@ def work_of(kernel_id, n):
     return float(n), 12.0 * n
 
 
+def pct(v, p):
+    if not len(v):
+        return None
+    v = sorted(v)
+    return v[max(1, int(math.ceil(p / 100.0 * len(v)))) - 1]
+
+
 # ----------------------------------------------------------------- rank side
 
-def bench_rank(ns, rank, kernel_id, n, cfg_idx, warmup, steps, e2e_steps, barrier):
-    """One SPMD rank process: attach, upload once, then timed resident steps,
-    then a few PCIe-inclusive steps.  Returns CLOCK_MONOTONIC stamps."""
+def bench_rank(ns, rank, kernel_id, n, cfg_idx, warmup, steps, res_warmup, res_steps, barrier):
+    """One SPMD rank process.  Its input is built once in its shared-memory
+    space; then warm-up and timed steps with every copy (the manager moves
+    the input to HBM and the result back into shared memory), then steps on
+    the inputs left resident in HBM.  Returns CLOCK_MONOTONIC stamps."""
     x = spmd.make_input(kernel_id, cfg_idx, rank, n)
-    out = np.empty(G.out_elems(kernel_id, n), np.float32)
+    nout = G.out_elems(kernel_id, n)
     G.check(G.gvm_attach_ns(ns, rank), "attach")
-    t = G.check(G.gvm_submit(rank, kernel_id, x, out, n), "upload")
-    G.check(G.gvm_wait(rank, t, 120_000_000_000), "upload wait")
-    first = spmd.digest(out)
-    flags = G.GVM_F_IN_RESIDENT | G.GVM_F_OUT_RESIDENT
-    barrier.wait()                       # 1: uploads done
-    for _ in range(warmup):
-        t = G.check(G.gvm_submit_ex(rank, kernel_id, None, None, n, flags), "warmup")
-        G.check(G.gvm_wait(rank, t, 120_000_000_000), "warmup wait")
-    barrier.wait()                       # 2: warm-up done
-    barrier.wait()                       # 3: statistics reset, go
-    import ctypes
-
-    clock = time.clock_gettime_ns
-    mono = time.CLOCK_MONOTONIC
+    view = G.gvm_rank_buffer(rank, (x.size + nout) * 4)
+    if view is None:
+        raise RuntimeError(f"rank {rank}: no zero-copy space: {G.gvm_last_error()}")
+    xin, oview = view[:x.size], view[x.size:x.size + nout]
+    xin[:] = x
     lib = G.lib()
     submit_ex, wait_timed = lib.gvm_submit_ex, lib.gvm_wait_timed
     ts = (ctypes.c_uint64 * 5)()
-    parts = [0, 0, 0, 0, 0, 0]
-    stamps = []                          # per step: submit, admit, posted, seen (ns)
-    t0 = clock(mono)
-    seen = t0
-    for _ in range(steps):
-        t = submit_ex(rank, kernel_id, None, None, n, flags)
-        if t < 0:
-            G.check(t, "step")
-        st = wait_timed(rank, t, 120_000_000_000, ts)
-        if st != 0:
-            G.check(st, "step wait")
-        now = clock(mono)
-        # submit->admit, admit->launch, launch->device done, device->posted, posted->seen, seen->next submit
-        parts[0] += ts[1] - ts[0]
-        parts[1] += ts[2] - ts[1]
-        parts[2] += ts[3] - ts[2]
-        parts[3] += ts[4] - ts[3]
-        parts[4] += now - ts[4]
-        parts[5] += ts[0] - seen
-        stamps.append((ts[0], ts[1], ts[4], now))
-        seen = now
-    t1 = clock(mono)
+    clock, mono = time.clock_gettime_ns, time.CLOCK_MONOTONIC
+    barrier.wait()                       # 1: attached, inputs in place
+    for _ in range(max(warmup, 1)):
+        t = G.check(G.gvm_submit(rank, kernel_id, xin, oview, n), "warm-up")
+        G.check(G.gvm_wait(rank, t, 120_000_000_000), "warm-up wait")
+    first = spmd.digest(oview)
+    barrier.wait()                       # 2: warm-up done
+    barrier.wait()                       # 3: statistics reset, go
+
+    def timed(nsteps, flags, inp, outp):
+        parts = [0, 0, 0, 0, 0, 0]
+        stamps = []                      # per step: submit, admit, posted, seen (ns)
+        t0 = clock(mono)
+        seen = t0
+        for _ in range(nsteps):
+            t = submit_ex(rank, kernel_id, inp, outp, n, flags)
+            if t < 0:
+                G.check(t, "step")
+            st = wait_timed(rank, t, 120_000_000_000, ts)
+            if st != 0:
+                G.check(st, "step wait")
+            now = clock(mono)
+            # submit->admit, admit->launch, launch->device done, device->posted, posted->seen, seen->next submit
+            parts[0] += ts[1] - ts[0]
+            parts[1] += ts[2] - ts[1]
+            parts[2] += ts[3] - ts[2]
+            parts[3] += ts[4] - ts[3]
+            parts[4] += now - ts[4]
+            parts[5] += ts[0] - seen
+            stamps.append((ts[0], ts[1], ts[4], now))
+            seen = now
+        return {"t0": t0, "t1": clock(mono), "parts_ns": [p / max(nsteps, 1) for p in parts], "stamps": stamps}
+
+    e2e = timed(steps, 0, xin.ctypes.data, oview.ctypes.data)
+    same = spmd.digest(oview) == first
     barrier.wait()                       # 4: timed steps done
-    # PCIe-inclusive steps: the input sits in the rank's shared memory
-    # (zero-copy region), the manager moves it to HBM and the result back
-    view = G.gvm_rank_buffer(rank, (x.size + out.size) * 4)
-    if view is None:
-        raise RuntimeError(f"rank {rank}: no zero-copy space: {G.gvm_last_error()}")
-    xin, oview = view[:x.size], view[x.size:x.size + out.size]
-    xin[:] = x
-    barrier.wait()                       # 5: statistics read, go
-    e0 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
-    for _ in range(e2e_steps):
-        t = G.check(G.gvm_submit(rank, kernel_id, xin, oview, n), "e2e step")
-        G.check(G.gvm_wait(rank, t, 120_000_000_000), "e2e wait")
-    e1 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
-    same = spmd.digest(oview if e2e_steps else out) == first
+    barrier.wait()                       # 5: statistics read
+    flags = G.GVM_F_IN_RESIDENT | G.GVM_F_OUT_RESIDENT
+    for _ in range(res_warmup):
+        t = G.check(G.gvm_submit_ex(rank, kernel_id, None, None, n, flags), "resident warm-up")
+        G.check(G.gvm_wait(rank, t, 120_000_000_000), "resident warm-up wait")
+    barrier.wait()                       # 6: resident warm-up done
+    barrier.wait()                       # 7: statistics reset, go
+    res = timed(res_steps, flags, None, None)
+    barrier.wait()                       # 8: resident steps done
     G.gvm_detach(rank)
-    return {"t0": t0, "t1": t1, "e0": e0, "e1": e1, "same_bytes": same, "digest": first,
-            "parts_ns": [x / max(steps, 1) for x in parts], "stamps": stamps}
+    return {"e2e": e2e, "resident": res, "same_bytes": same, "digest": first}
 
 
-def step_detail(rr):
+def step_detail(runs):
     """Across ranks, per timed step: spread of the submit times, spread of
     the completion posts, and the gap from the previous step's last post to
     this step's first submit (means, us), plus how often each rank submitted
     last (the one the request barrier waits for)."""
-    st = np.array([r["stamps"] for r in rr], dtype=np.float64)   # ranks x steps x 4
+    st = np.array([r["stamps"] for r in runs], dtype=np.float64)   # ranks x steps x 4
     if st.ndim != 3 or st.shape[1] < 2:
         return None
     sub, post = st[:, :, 0], st[:, :, 2]
@@ -212,54 +246,78 @@ def step_detail(rr):
             "last_submitter_counts": last.tolist()}
 
 
+def leg_summary(runs, steps):
+    """Whole-job time of a leg (first start to last end over the ranks), the
+    request latency percentiles (submit to seen, us) and the mean stage
+    breakdown."""
+    elapsed = (max(r["t1"] for r in runs) - min(r["t0"] for r in runs)) * 1e-9
+    lat = [(s[3] - s[0]) * 1e-3 for r in runs for s in r["stamps"]]
+    return elapsed, {
+        "ms_per_step": round(elapsed / max(steps, 1) * 1e3, 4),
+        "latency_us": {"p50": round(pct(lat, 50), 2), "p99": round(pct(lat, 99), 2), "count": len(lat)},
+        "step_breakdown_us": dict(zip(
+            ["barrier_and_drain", "admit_to_launch", "launch_to_device_done", "device_done_to_posted",
+             "posted_to_seen", "rank_loop"],
+            [round(float(x) * 1e-3, 2) for x in np.mean([r["parts_ns"] for r in runs], axis=0)])),
+        "step_detail_us": step_detail(runs),
+    }
+
+
 PLAIN_WARM_N = {G.GVM_K_VECADD: 4096, G.GVM_K_VECMUL: 4096, G.GVM_K_BLACKSCHOLES: 4096, G.GVM_K_SGEMM: 64,
                 G.GVM_K_EP: 4096}
 
 
-def plain_rank(kernel_id, n, cfg_idx, rank, barrier, warm=False, baton=None):
+def plain_proc(jobs, barrier, warm=False, baton=None):
     """One process of the plain method (no virtualization): its own device
-    context, pageable copies, the same kernel code object (Section 4.1).
+    context, pageable copies, the same kernel code objects (Section 4.1).
+    `jobs` = [(rank, kernel id, n, config index)], run one after another.
 
     Variants of the baseline:
-    * cold (default): the context is created inside the timed region, as in
-      the paper's turnaround (T_init included);
-    * ``warm``: a small request of the same kernel runs before the start
-      barrier, so context creation and code-object loading fall outside it;
-    * ``baton`` (a shared turn counter and its condition): the processes run
-      their GPU phases one after another in rank order, the sequential
-      execution that Eq. 1 models, instead of letting the device's
-      scheduler interleave them."""
-    x = spmd.make_input(kernel_id, cfg_idx, rank, n)
-    out = np.empty(G.out_elems(kernel_id, n), np.float32)
+    * cold (default): the context is created inside the timed region, by the
+      process's first request, as in the paper's turnaround (T_init included);
+    * ``warm``: a small request of the first job's kernel runs before the
+      start barrier, so context creation and code-object loading fall outside;
+    * ``baton`` (a shared turn counter and its condition): the GPU phases run
+      one after another in rank order, the sequential execution that Eq. 1
+      models, instead of letting the device's scheduler interleave them."""
+    inputs = {r: spmd.make_input(k, c, r, n) for r, k, n, c in jobs}
     G.lib()
     args = (float(np.float32(wl.BS_RATE)), float(np.float32(wl.BS_VOLATILITY)))
     if warm:
-        m = PLAIN_WARM_N[kernel_id]
-        wx = spmd.make_input(kernel_id, cfg_idx, rank, m)
-        wo = np.empty(G.out_elems(kernel_id, m), np.float32)
-        rc, _ = G.gvm_plain_run(kernel_id, wx, wo, m, *args)
+        r0, k0, _, c0 = jobs[0]
+        m = PLAIN_WARM_N[k0]
+        wx = spmd.make_input(k0, c0, r0, m)
+        wo = np.empty(G.out_elems(k0, m), np.float32)
+        rc, _ = G.gvm_plain_run(k0, wx, wo, m, *args)
         if rc != 0:
-            return {"rc": rc, "t0": 0, "t1": 0, "stages": [0.0] * 6, "digest": ""}
+            return {"rc": rc, "t0": 0, "t1": 0, "stages": [], "digests": {}}
     barrier.wait()
     t0 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
-    if baton is not None:
-        turn, cond = baton
-        with cond:
-            cond.wait_for(lambda: turn.value == rank)
-    rc, stages = G.gvm_plain_run(kernel_id, x, out, n, *args)
-    if baton is not None:
-        with cond:
-            turn.value += 1
-            cond.notify_all()
+    stages, digests, worst = [], {}, 0
+    for r, k, n, c in jobs:
+        out = np.empty(G.out_elems(k, n), np.float32)
+        if baton is not None:
+            turn, cond = baton
+            with cond:
+                cond.wait_for(lambda: turn.value == r)
+        rc, st = G.gvm_plain_run(k, inputs[r], out, n, *args)
+        if baton is not None:
+            with cond:
+                turn.value += 1
+                cond.notify_all()
+        worst = worst or rc
+        stages.append(st)
+        digests[r] = spmd.digest(out)
     t1 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
-    return {"rc": rc, "t0": t0, "t1": t1, "stages": stages, "digest": spmd.digest(out)}
+    return {"rc": worst, "t0": t0, "t1": t1, "stages": stages, "digests": digests}
 
 
 # ----------------------------------------------------------------- main
 
-def cpu_baseline(kernel_id, nranks, n, cfg_idx, budget_s=10.0):
+def cpu_baseline(specs, main_kernel, budget_s=10.0):
     """The oracle as it stands, on this host's cores, over a bounded sample of
-    the same workload (whole passes over the ranks' requests, ~budget_s)."""
+    the same workload: the workload's requests of its main kernel, cycled,
+    for about `budget_s` seconds."""
     from oracle import ep as oe
     from oracle import kernels as ok
 
@@ -269,59 +327,110 @@ def cpu_baseline(kernel_id, nranks, n, cfg_idx, budget_s=10.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = 1
-    if kernel_id == G.GVM_K_EP:
-        sample = min(n, 1 << 20)   # a bounded slice of each rank's pair stream
+    reqs = [(r, n, c) for r, (k, n, c) in enumerate(specs) if k == main_kernel]
+    if main_kernel == G.GVM_K_EP:
+        sample = min(reqs[0][1], 1 << 20)   # a bounded slice of each rank's pair stream
         done = 0
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < budget_s:
-            oe.ep_reference(wl.ep_key(cfg_idx, done % nranks), sample)
+            r, _, c = reqs[done % len(reqs)]
+            oe.ep_reference(wl.ep_key(c, r), sample)
             done += 1
         el = time.perf_counter() - t0
         return {"value": round(done * sample / el / 1e9, 6), "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
                 "sample": f"{done} slices of {sample} pairs through oracle.ep.ep_reference in {el:.1f} s "
                           f"(the first {sample} pairs of the ranks' keys, cycled)"}
-    inputs = []
-    for r in range(min(nranks, 4)):
-        if kernel_id == G.GVM_K_SGEMM:
-            inputs.append(wl.sgemm_inputs(cfg_idx, r, n))
-        elif kernel_id == G.GVM_K_BLACKSCHOLES:
-            inputs.append(wl.bs_inputs(cfg_idx, r, n))
-        else:
-            inputs.append(wl.vecadd_inputs(cfg_idx, r, n))
-    done = 0
+    cache = {}
+    done = flop = byts = 0.0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        args = inputs[done % len(inputs)]
-        if kernel_id == G.GVM_K_SGEMM:
+        r, n, c = reqs[int(done) % len(reqs)]
+        if (r, n) not in cache and len(cache) < 8:
+            if main_kernel == G.GVM_K_SGEMM:
+                cache[(r, n)] = wl.sgemm_inputs(c, r, n)
+            elif main_kernel == G.GVM_K_BLACKSCHOLES:
+                cache[(r, n)] = wl.bs_inputs(c, r, n)
+            else:
+                cache[(r, n)] = wl.vecadd_inputs(c, r, n)
+        args = cache.get((r, n))
+        if args is None:   # beyond the input cache: reuse the first request's inputs at its own size
+            r, n, c = reqs[0]
+            args = cache[(r, n)]
+        if main_kernel == G.GVM_K_SGEMM:
             ok.sgemm_f64(*args)
-        elif kernel_id == G.GVM_K_BLACKSCHOLES:
+        elif main_kernel == G.GVM_K_BLACKSCHOLES:
             ok.black_scholes_f64(*args, wl.BS_RATE, wl.BS_VOLATILITY)
         else:
             ok.vecadd_f32(*args)
+        f, b = work_of(main_kernel, n)
+        flop += f
+        byts += b
         done += 1
     el = time.perf_counter() - t0
-    flop, byts = work_of(kernel_id, n)
-    if kernel_id == G.GVM_K_SGEMM:
-        value, unit = done * flop / el / 1e9, "GFLOP/s"
+    if main_kernel == G.GVM_K_SGEMM:
+        value, unit = flop / el / 1e9, "GFLOP/s"
     else:
-        value, unit = done * byts / el / 1e9, "GB/s"
-    kname = {1: "vecadd_f32", 2: "black_scholes_f64", 3: "sgemm_f64"}[kernel_id]
+        value, unit = byts / el / 1e9, "GB/s"
+    kname = {1: "vecadd_f32", 2: "black_scholes_f64", 3: "sgemm_f64"}[main_kernel]
     return {"value": round(value, 3), "unit": unit, "cores": threads, "kind": "oracle",
-            "sample": f"{done} requests of n={n} through oracle.kernels.{kname} in {el:.1f} s "
-                      f"(the workload's {nranks} requests, cycled)"}
+            "sample": f"{int(done)} requests through oracle.kernels.{kname} in {el:.1f} s (the workload's "
+                      f"{len(reqs)} requests of this kernel, sizes {sorted({n for _, n, _ in reqs})}, cycled)"}
+
+
+def run_plain(ctx, specs, warm=False, seq=False, flop_total=0.0, bytes_total=0.0, unit="GFLOP/s"):
+    nranks = len(specs)
+    nproc = min(nranks, MAX_GPU_PROCESSES)
+    groups = [[(r, k, n, c) for r, (k, n, c) in enumerate(specs) if r % nproc == p] for p in range(nproc)]
+    bar = ctx.Barrier(nproc)
+    baton = (ctx.Value("i", 0), ctx.Condition()) if seq else None
+    res = spmd.run_processes(plain_proc, [(g, bar, warm, baton) for g in groups], timeout_s=600)
+    bad = [r for r in res if r["rc"] != 0]
+    if bad:
+        raise SystemExit(f"plain baseline failed: {bad}")
+    turn = (max(r["t1"] for r in res) - min(r["t0"] for r in res)) * 1e-9
+    stages = np.array([s for r in res for s in r["stages"]])
+    digests = {}
+    for r in res:
+        digests.update(r["digests"])
+    work = flop_total if unit == "GFLOP/s" else bytes_total
+    return {"processes": nproc, "ranks_per_process": [len(g) for g in groups][:1] + ([] if nranks % nproc == 0 else
+                                                                                     [len(g) for g in groups][-1:]),
+            "turnaround_s": round(turn, 6), "value": round(work / turn / 1e9, 3), "unit": unit,
+            "mean_stage_s": dict(zip(["init", "alloc", "copy_in", "kernel", "copy_out", "free"],
+                                     [round(float(v), 6) for v in stages.mean(axis=0)])),
+            "digests": [digests[r] for r in range(nranks)]}
+
+
+def serving_leg(seconds, copy_threads):
+    """A short run of the serving configuration through the load generator."""
+    from paper_1511_07658_amd import loadgen
+
+    warm = 0.5
+    a = loadgen.parse_args(["--ranks", "64", "--rate", "2000", "--duration", str(seconds + warm), "--warmup", str(warm),
+                            "--no-plain", "--copy-threads", str(copy_threads)])
+    res, _ = loadgen.run(a)
+    g = res["gvm"]
+    return {"ranks": 64, "rate_req_s": 2000, "measured_s": seconds, "requests": g["requests"], "ok": g["ok"],
+            "failed": g["failed"], "p50_ms": g["p50_ms"], "p99_ms": g["p99_ms"], "max_ms": g["max_ms"],
+            "throughput_req_s": g["throughput_req_s"], "gemm_GFLOPs": g["gemm_GFLOPs"],
+            "algorithmic_GBs": g["algorithmic_GBs"], "per_kernel": g["per_kernel"],
+            "budget_GiB": 64, "command": "python -m paper_1511_07658_amd.loadgen --ranks 64 --rate 2000 "
+                                         f"--duration {seconds + warm} --warmup {warm} --no-plain"}
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="sgemm8", choices=sorted(WORKLOADS))
-    ap.add_argument("--e2e-steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mixed32", choices=sorted(WORKLOADS))
+    ap.add_argument("--resident-steps", type=int, default=30, help="steps of the device-phase (resident) leg")
+    ap.add_argument("--serving-seconds", type=float, default=3.0,
+                    help="measured seconds of the serving leg (64 ranks, 2000 req/s); 0 skips it")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--graphs", type=int, default=None, help="replay repeated batches as HIP graphs (switched off in this build)")
+    ap.add_argument("--graphs", type=int, default=0, help="replay repeated batches as HIP graphs")
     ap.add_argument("--rank-threads", action="store_true",
                     help="run the ranks as threads of this process (for profilers that cannot follow forks)")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
@@ -332,14 +441,14 @@ def main(argv=None):
               f"with no exchange step).", file=sys.stderr)
         return 2
     specs = rank_specs(a.workload)
-    if a.graphs is None:
-        a.graphs = 0  # graph replay is switched off in the library
     nranks = len(specs)
     kinds = sorted({k for k, _, _ in specs})
     main_kernel = G.GVM_K_SGEMM if G.GVM_K_SGEMM in kinds else kinds[0]
-    flop_total = sum(work_of(k, n)[0] for k, n, _ in specs)
-    bytes_total = sum(work_of(k, n)[1] for k, n, _ in specs)
-    import threading
+    flop_total = sum(work_of(k, n)[0] for k, n, _ in specs if k == main_kernel)
+    bytes_total = sum(work_of(k, n)[1] for k, n, _ in specs if k == main_kernel)
+    pairs_total = sum(n for k, n, _ in specs if k == G.GVM_K_EP)
+    unit = {G.GVM_K_SGEMM: "GFLOP/s", G.GVM_K_EP: "Gpairs/s"}.get(main_kernel, "GB/s")
+    work_total = {G.GVM_K_SGEMM: flop_total, G.GVM_K_EP: pairs_total}.get(main_kernel, bytes_total)
 
     if a.rank_threads:
         a.no_plain = True
@@ -353,45 +462,29 @@ def main(argv=None):
     # (contexts created before the start), and cold with the GPU phases run
     # one rank after another (Eq. 1)
     plain = plain_warm = plain_seq = None
-
-    def run_plain(warm=False, seq=False):
-        bar = ctx.Barrier(nranks)
-        baton = (ctx.Value("i", 0), ctx.Condition()) if seq else None
-        res = spmd.run_processes(plain_rank, [(k, n, c, r, bar, warm, baton) for r, (k, n, c) in enumerate(specs)],
-                                 timeout_s=300)
-        bad = [r for r in res if r["rc"] != 0]
-        if bad:
-            raise SystemExit(f"plain baseline failed: {bad}")
-        turn = (max(r["t1"] for r in res) - min(r["t0"] for r in res)) * 1e-9
-        stages = np.array([r["stages"] for r in res])
-        return {"turnaround_s": round(turn, 6),
-                "value": round((flop_total if main_kernel == G.GVM_K_SGEMM else
-                                sum(n for _, n, _ in specs) if main_kernel == G.GVM_K_EP else bytes_total)
-                               / turn / 1e9, 3),
-                "mean_stage_s": dict(zip(["init", "alloc", "copy_in", "kernel", "copy_out", "free"],
-                                         [round(float(v), 6) for v in stages.mean(axis=0)])),
-                "digests": [r["digest"] for r in res]}
-
-    if not a.no_plain and not a.loopback and nranks <= 16:
-        log(f"plain baseline: {nranks} processes, each its own context (cold, warm, sequential)")
-        plain = run_plain()
-        plain_warm = run_plain(warm=True)
-        plain_seq = run_plain(seq=True)
+    if not a.no_plain and not a.loopback:
+        log(f"plain baseline: {nranks} ranks on {min(nranks, MAX_GPU_PROCESSES)} processes (cold, warm, sequential)")
+        kw = dict(flop_total=flop_total, bytes_total=bytes_total if main_kernel != G.GVM_K_EP else pairs_total,
+                  unit="GFLOP/s" if main_kernel == G.GVM_K_SGEMM else unit)
+        plain = run_plain(ctx, specs, **kw)
+        plain_warm = run_plain(ctx, specs, warm=True, **kw)
+        plain_seq = run_plain(ctx, specs, seq=True, **kw)
 
     # 2. the GVM manager in this process, ranks in forked processes
     ns = f"gvm.bench.{os.getpid()}"
     space = max((G.in_elems(k, n) + G.out_elems(k, n)) * 4 for k, n, _ in specs) + (1 << 20)
+    copy_threads = 8
     cfg = G.gvm_config_default(nranks=nranks, shm_bytes_per_rank=space,
                                hbm_budget_bytes=max(2 << 30, 2 * nranks * space),
                                mode=G.GVM_MODE_BATCH, policy=G.GVM_POLICY_AUTO, batch_window_us=5_000_000,
-                               use_graphs=1 if a.graphs else 0, copy_threads=8, name=ns,
+                               use_graphs=1 if a.graphs else 0, copy_threads=copy_threads, name=ns,
                                backend=G.GVM_BACKEND_LOOPBACK if a.loopback else G.GVM_BACKEND_HIP)
     log(f"GVM: {nranks} ranks, {a.workload}")
     G.check(G.gvm_init(cfg), "gvm_init")
     try:
         bar = threading.Barrier(nranks + 1) if a.rank_threads else ctx.Barrier(nranks + 1)
         results = {}
-        args = [(ns, r, k, n, c, a.warmup, a.steps, a.e2e_steps, bar) for r, (k, n, c) in enumerate(specs)]
+        args = [(ns, r, k, n, c, a.warmup, a.steps, 3, a.resident_steps, bar) for r, (k, n, c) in enumerate(specs)]
 
         def runner():
             if a.rank_threads:
@@ -407,72 +500,88 @@ def main(argv=None):
                     t.join()
                 results["r"] = out
             else:
-                results["r"] = spmd.run_processes(bench_rank, args, timeout_s=600)
+                results["r"] = spmd.run_processes(bench_rank, args, timeout_s=900)
 
         th = threading.Thread(target=runner)
         th.start()
-        bar.wait()                      # 1: uploads done
+        bar.wait()                      # 1: attached
         bar.wait()                      # 2: warm-up done
         G.gvm_stats_reset()
-        bar.wait()                      # 3: go
+        bar.wait()                      # 3: go (timed steps with copies)
         bar.wait()                      # 4: timed steps done
+        e2e_stats = G.gvm_stats_json()
+        bar.wait()                      # 5: resident warm-up
+        bar.wait()                      # 6: resident warm-up done
+        G.gvm_stats_reset()
+        bar.wait()                      # 7: go (resident steps)
+        bar.wait()                      # 8: resident steps done
         stats = G.gvm_stats_json()
-        bar.wait()                      # 5: PCIe-inclusive steps start
         th.join()
         rr = results["r"]
     finally:
         G.gvm_shutdown()
-    elapsed = (max(r["t1"] for r in rr) - min(r["t0"] for r in rr)) * 1e-9
-    e2e = (max(r["e1"] for r in rr) - min(r["e0"] for r in rr)) * 1e-9
+    elapsed, e2e = leg_summary([r["e2e"] for r in rr], a.steps)
+    res_elapsed, dev = leg_summary([r["resident"] for r in rr], a.resident_steps)
+    value = a.steps * work_total / elapsed / 1e9
+    dev_value = a.resident_steps * work_total / res_elapsed / 1e9
+
+    # roofline of the dominant kernel, from the resident leg's launch events
     knames = {0: "mixed_graph", 1: "vecadd", 2: "blackscholes", 3: "sgemm", 4: "vecmul", 5: "ep"}
     kname = "mixed_graph" if (mixed and a.graphs and "mixed_graph" in stats["kernels"]) else knames[main_kernel]
     ks = stats["kernels"][kname]
     launches = max(ks["launches"], 1)
     avg_launch_s = max(ks["device_ms"] / launches * 1e-3, 1e-12)
-    # the launch of the dominant kernel covers every request of its kind in a step
-    main_specs = [(k, n) for k, n, _ in specs if k == main_kernel]
-    main_flop = sum(work_of(k, n)[0] for k, n in main_specs)
-    main_bytes = sum(work_of(k, n)[1] for k, n in main_specs)
     dev_s = max(ks["device_ms"] * 1e-3, 1e-12)
+    per_step_launches = launches / max(a.resident_steps, 1)
     if main_kernel == G.GVM_K_SGEMM:
-        value = a.steps * main_flop / elapsed / 1e9
-        unit = "GFLOP/s"
-        # algorithmic FLOP of every timed launch / their summed device time
-        achieved = (ks["work_flop"] if kname != "mixed_graph" else a.steps * main_flop) / dev_s / 1e12
+        achieved = (ks["work_flop"] if kname != "mixed_graph" else a.resident_steps * flop_total) / dev_s / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": measured_traffic(a.workload)}
-        e2e_value = a.e2e_steps * main_flop / e2e / 1e9
     elif main_kernel == G.GVM_K_EP:
-        pairs = sum(n for k, n in main_specs)
-        value = a.steps * pairs / elapsed / 1e9
-        unit = "Gpairs/s"
-        achieved = ks["requests"] / len(main_specs) * pairs / dev_s / 1e9
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_EP_GPAIRS, 1), "unit": "Gpairs/s",
-                "frac": round(achieved / PEAK_EP_GPAIRS, 4), "traffic": None}
-        e2e_value = a.e2e_steps * pairs / e2e / 1e9
+        pairs_s = ks["requests"] / max(sum(1 for k, _, _ in specs if k == G.GVM_K_EP), 1) * pairs_total / dev_s
+        achieved = pairs_s * EP_FP64_OPS_PER_PAIR / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": None,
+                "ops_per_pair": round(EP_FP64_OPS_PER_PAIR, 3), "Gpairs_per_s": round(pairs_s / 1e9, 2),
+                "valu_issue_utilisation": round(pairs_s / 1e9 / EP_ISSUE_GPAIRS, 4)}
     else:
-        value = a.steps * main_bytes / elapsed / 1e9
-        unit = "GB/s"
-        achieved = (ks["work_bytes"] if kname != "mixed_graph" else a.steps * main_bytes) / dev_s / 1e9
+        achieved = (ks["work_bytes"] if kname != "mixed_graph" else a.resident_steps * bytes_total) / dev_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(a.workload)}
-        e2e_value = a.e2e_steps * main_bytes / e2e / 1e9
     roof["kernel"] = f"{kname}: {ks['requests']} requests in {ks['launches']} grouped launches"
     roof["avg_launch_us"] = round(avg_launch_s * 1e6, 3)
     roof["launches"] = ks["launches"]
+    roof["launches_per_step"] = round(per_step_launches, 3)
     roof["algorithmic_bytes"] = round(ks["work_bytes"] / launches)
+    roof["algorithmic_flop"] = round(ks["work_flop"] / launches)
+    if per_step_launches > 1.0:
+        # several launches of the kernel per step run concurrently on the two
+        # compute streams: each launch's own FLOP / duration shares the device
+        roof["note"] = "launches of one step overlap; step_achieved is the kernel's work per resident step"
+        roof["step_achieved"] = round((flop_total if main_kernel == G.GVM_K_SGEMM else bytes_total)
+                                      / (res_elapsed / max(a.resident_steps, 1)) /
+                                      (1e12 if main_kernel == G.GVM_K_SGEMM else 1e9), 3)
+
     extra = {}
     if mixed:
-        extra["vecadd_GBps"] = round(a.steps * sum(work_of(k, n)[1] for k, n, _ in specs if k == G.GVM_K_VECADD)
-                                     / elapsed / 1e9, 3)
+        vbytes = sum(work_of(k, n)[1] for k, n, _ in specs if k == G.GVM_K_VECADD)
+        extra["vecadd_GBps"] = round(a.steps * vbytes / elapsed / 1e9, 3)
         extra["sizes"] = [[k, n] for k, n, _ in specs]
+        extra["work_per_step"] = {"sgemm_GFLOP": round(flop_total / 1e9, 4), "vecadd_MB": round(vbytes / 1e6, 3)}
+    # bytes crossing PCIe per step: every input in, every result out
+    pcie_bytes = sum((G.in_elems(k, n) + G.out_elems(k, n)) * 4 for k, n, _ in specs)
 
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        k0, n0, c0 = next(sp for sp in specs if sp[0] == main_kernel)
-        cpu = cpu_baseline(k0, len(main_specs), n0, c0, a.cpu_seconds)
+        cpu = cpu_baseline(specs, main_kernel, a.cpu_seconds)
 
+    serving = None
+    if a.serving_seconds > 0 and not a.loopback and not a.rank_threads:
+        log(f"serving leg: 64 ranks, 2000 req/s, {a.serving_seconds} s")
+        serving = serving_leg(a.serving_seconds, 16)
+
+    ms_step = elapsed / a.steps * 1e3
     line = {
         "metric": "aggregate GB/s & GFLOP/s, N ranks on 1 GPU, GVM vs plain; p50/p99 req latency",
         "value": round(value, 3),
@@ -480,36 +589,34 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(elapsed / a.steps * 1e3, 6),
+        "ms_per_step": round(ms_step, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded by rank)",
         "config": {"workload": WORKLOADS[a.workload], "name": a.workload,
-                   "ranks": nranks, "mode": "batch", "policy": "auto (grouped when resident)",
-                   "graphs": bool(a.graphs),
-                   "rank_kind": "threads" if a.rank_threads else "processes"},
+                   "ranks": nranks, "mode": "batch", "policy": "auto", "graphs": bool(a.graphs),
+                   "timed": "every step: shared memory -> HBM copies, kernels, HBM -> shared memory copies, "
+                            "completions", "rank_kind": "threads" if a.rank_threads else "processes"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "latency_us": {"p50": ks["latency_us"]["p50"], "p99": ks["latency_us"]["p99"], "count": ks["latency_us"]["count"]},
-        "step_breakdown_us": dict(zip(
-            ["barrier_and_drain", "admit_to_launch", "launch_to_device_done", "device_done_to_posted",
-             "posted_to_seen", "rank_loop"],
-            [round(float(x) * 1e-3, 2) for x in np.mean([r["parts_ns"] for r in rr], axis=0)])),
-        "step_detail_us": step_detail(rr),
+        "latency_us": e2e["latency_us"],
+        "step_breakdown_us": e2e["step_breakdown_us"],
+        "step_detail_us": e2e["step_detail_us"],
+        "pcie_GBps": round(a.steps * pcie_bytes / elapsed / 1e9, 3),
+        "device_phase": {"value": round(dev_value, 3), "unit": unit, "steps": a.resident_steps, **dev},
         "manager_us": {"ring": stats.get("ring_us"), "batch_admit_lag": stats.get("batch_admit_lag_us"),
                        "busy_iteration": stats.get("busy_iteration_us")},
-        "e2e_pcie": {"value": round(e2e_value, 3), "unit": unit, "steps": a.e2e_steps,
-                     "ms_per_step": round(e2e / max(a.e2e_steps, 1) * 1e3, 3)},
         "plain": None if plain is None else {k: v for k, v in plain.items() if k != "digests"},
         "plain_warm": None if plain_warm is None else {k: v for k, v in plain_warm.items() if k != "digests"},
         "plain_sequential": None if plain_seq is None else {k: v for k, v in plain_seq.items() if k != "digests"},
-        "gvm_vs_plain_turnaround": None if plain is None else round(plain["turnaround_s"] / (e2e / max(a.e2e_steps, 1)), 3),
+        "gvm_vs_plain_turnaround": None if plain is None else round(plain["turnaround_s"] * 1e3 / ms_step, 3),
         "gvm_vs_plain_warm_turnaround": None if plain_warm is None else round(
-            plain_warm["turnaround_s"] / (e2e / max(a.e2e_steps, 1)), 3),
+            plain_warm["turnaround_s"] * 1e3 / ms_step, 3),
         "gvm_vs_plain_sequential_turnaround": None if plain_seq is None else round(
-            plain_seq["turnaround_s"] / (e2e / max(a.e2e_steps, 1)), 3),
+            plain_seq["turnaround_s"] * 1e3 / ms_step, 3),
+        "serving": serving,
         **extra,
         "results_unchanged_by_virtualization": all(r["same_bytes"] for r in rr) and all(
             p is None or [r["digest"] for r in rr] == p["digests"] for p in (plain, plain_warm, plain_seq)),

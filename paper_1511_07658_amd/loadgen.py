@@ -87,9 +87,21 @@ def _work(k, n):
     return float(n), 12.0 * n
 
 
-def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot_bytes=0, nslots=2):
-    """One open-loop rank against the manager; returns per-request records
-    (arrival offset s, kernel, n, latency s, status).
+def sampled(rank, index, k, n, every):
+    """Whether request `index` of `rank` keeps a copy of its result for a
+    later check: every `every`-th request of the rank (offset by the rank),
+    when its result is at most 8 MiB."""
+    return every > 0 and (index + rank) % every == 0 and out_bytes(k, n) <= (8 << 20)
+
+
+def out_bytes(k, n):
+    return G.out_elems(k, n) * 4
+
+
+def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot_bytes=0, nslots=2, sample_every=0):
+    """One open-loop rank against the manager; returns {"records": per-request
+    (arrival offset s, kernel, n, latency s, status, stages), "samples":
+    [(request index, kernel, n, result)] for the requests `sampled` picks}.
 
     With `zero_copy` the rank builds each input directly in its shared-memory
     space (`nslots` request slots of `slot_bytes` from gvm_rank_buffer) and
@@ -109,6 +121,7 @@ def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot
     t0 = start_box.value
     pending = {}
     out = []
+    samples = []
     i = 0
     while i < len(trace) or pending:
         now = _now()
@@ -129,7 +142,7 @@ def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot
                 if slot is not None:
                     free_slots.append(slot)
             else:
-                pending[t] = (ta, k, n, slot)
+                pending[t] = (ta, k, n, slot, i, o)
             i += 1
             continue
         if not pending:
@@ -146,7 +159,9 @@ def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot
         if rc == G.GVM_ETIMEDOUT:
             continue
         if t in pending:
-            ta, k, n, slot = pending.pop(t)
+            ta, k, n, slot, idx, o = pending.pop(t)
+            if rc == 0 and sampled(rank, idx, k, n, sample_every):
+                samples.append((idx, k, n, np.array(o, copy=True)))
             arrive = t0 + int(ta * 1e9)
             # arrival->submit (rank queue), submit->admit, admit->launch (copy-in),
             # launch->device done, device done->posted (copy-out)
@@ -157,7 +172,7 @@ def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot
         elif rc < 0:
             raise RuntimeError(f"rank {rank}: wait failed {rc}: {G.gvm_last_error()}")
     G.gvm_detach(rank)
-    return out
+    return {"records": out, "samples": samples}
 
 
 def plain_proc(traces, start_box, barrier, rate_r, rate_v):
@@ -212,7 +227,7 @@ def summarize(records, warmup_s, duration_s):
             "per_kernel": per_kernel, "mean_stage_ms": stage_ms}
 
 
-def main(argv=None):
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--ranks", type=int, default=64)
     ap.add_argument("--rate", type=float, default=2000.0, help="total requests per second")
@@ -224,8 +239,15 @@ def main(argv=None):
     ap.add_argument("--copy-threads", type=int, default=16, help="manager threads for shm <-> pinned staging copies")
     ap.add_argument("--copy-api", action="store_true",
                     help="ranks pass private buffers (the API copies them) instead of building in shared memory")
+    ap.add_argument("--sample-every", type=int, default=0,
+                    help="keep every k-th result of each rank (up to 8 MiB each) for a check after the run")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
-    a = ap.parse_args(argv)
+    return ap.parse_args(argv)
+
+
+def run(a):
+    """Replay the trace against the plain method (unless a.no_plain) and the
+    GVM; returns (the result record, the sampled results per rank)."""
     if a.loopback:
         a.no_plain = True
     traces = wl.poisson_trace(CONFIG, a.ranks, a.rate, a.duration)
@@ -274,7 +296,8 @@ def main(argv=None):
 
         def run_gvm():
             res["r"] = spmd.run_processes(
-                gvm_rank, [(ns, r, traces[r], start, a.warmup, bar, not a.copy_api, slot, 2) for r in range(a.ranks)],
+                gvm_rank, [(ns, r, traces[r], start, a.warmup, bar, not a.copy_api, slot, 2, a.sample_every)
+                           for r in range(a.ranks)],
                 timeout_s=a.duration * 20 + 300)
 
         th = threading.Thread(target=run_gvm)
@@ -289,7 +312,8 @@ def main(argv=None):
         stats = G.gvm_stats_json()
     finally:
         G.gvm_shutdown()
-    recs = [x for part in res["r"] for x in part]
+    recs = [x for part in res["r"] for x in part["records"]]
+    samples = {r: part["samples"] for r, part in enumerate(res["r"])}
     result["gvm"] = {**summarize(recs, a.warmup, a.duration), "peak_device_bytes": stats["peak_device_bytes"],
                      "admit_wait_us": stats["admit_wait_us"],
                      "device_ms": {k: v["device_ms"] for k, v in stats["kernels"].items()},
@@ -302,6 +326,12 @@ def main(argv=None):
         result["p99_plain_over_gvm"] = round(result["plain"]["p99_ms"] / result["gvm"]["p99_ms"], 3)
         result["throughput_gvm_over_plain"] = round(result["gvm"]["throughput_req_s"] /
                                                     max(result["plain"]["throughput_req_s"], 1e-9), 3)
+    result["gvm"]["sampled_results"] = sum(len(v) for v in samples.values())
+    return result, samples
+
+
+def main(argv=None):
+    result, _ = run(parse_args(argv))
     print(json.dumps(result), flush=True)
     return 0
 
