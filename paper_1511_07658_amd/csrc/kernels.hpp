@@ -58,10 +58,18 @@ struct GemmDesc {
   uint32_t units;    // tiles of this request
 };
 
+constexpr int kGroupXcds = 8;  // MI355X: workgroup w is dispatched to XCD w % 8
+
 struct GemmGroup {
   uint32_t count;
   uint32_t total_units;
   GemmDesc d[kMaxGroup];
+  // Balanced launch (mixed sizes, one workgroup per tile): XCD x computes the
+  // units [xcd_begin[x], xcd_begin[x + 1]), a contiguous run whose k-steps
+  // add up to an eighth of the launch's.  Filled by finalize_gemm_group.
+  uint32_t xcd_begin[kGroupXcds + 1];
+  uint32_t balanced;
+  uint32_t pad;
 };
 
 struct EpDesc {
@@ -106,6 +114,9 @@ constexpr uint64_t kBsUnit = 4096;    // options per Black-Scholes work unit (th
 hipError_t launch_vecadd_group(const VecGroup& g, hipStream_t s, int grid_cap = 0);
 hipError_t launch_vecmul_group(const VecGroup& g, hipStream_t s, int grid_cap = 0);
 hipError_t launch_bs_group(const BsGroup& g, hipStream_t s, int grid_cap = 0);
+// grid_cap >= total_units asks for one workgroup per tile; for a group of
+// mixed sizes the tiles are then spread over the XCDs by their k-steps
+// (GemmGroup.xcd_begin) instead of by count.
 hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap = 0);
 // EP-like tally: one launch over the work units of every request (partials),
 // then one workgroup per request sums its partials.

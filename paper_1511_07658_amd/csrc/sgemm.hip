@@ -5,6 +5,7 @@
 // held in the kernel arguments; a tile is always computed by the same code in
 // the same order, whatever else is in the group, so a rank's C is
 // bit-identical alone and in the mix.
+#include "gemm_balance.hpp"
 #include "group_device.hpp"
 
 #include <algorithm>
@@ -51,6 +52,13 @@ namespace {
 // Persistent grid, XCD-aware: the units (tiles, requests in order, tiles of a
 // request row-major) are dealt to the 8 XCDs in contiguous blocks, so that
 // tiles sharing rows of A and columns of B share an L2.
+//
+// Balanced grid (mixed sizes, one workgroup per tile): the blocks are cut by
+// work instead of by count.  The requests come largest first, so equal
+// counts would give the first XCD the longest tiles and the last one the
+// shortest; each XCD instead takes a contiguous run of units whose k-steps
+// add up to an eighth of the launch's, and the grid holds as many
+// workgroups per XCD as the longest run has units (the rest exit at once).
 
 template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH, bool VEC, bool PIPE>
 __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) {
@@ -85,7 +93,14 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
   uint32_t v = blockIdx.x;
   if (G % kXcds == 0) v = (blockIdx.x % kXcds) * (G / kXcds) + blockIdx.x / kXcds;
 
-  for (uint32_t u = v; u < U; u += G) {
+  uint32_t u0 = v, uend = U, ustep = G;
+  if (g.balanced) {
+    const uint32_t x = blockIdx.x % kXcds;
+    u0 = g.xcd_begin[x] + blockIdx.x / kXcds;
+    uend = g.xcd_begin[x + 1];
+    ustep = G / kXcds;
+  }
+  for (uint32_t u = u0; u < uend; u += ustep) {
     const int q = find_request(g, u);
     const GemmDesc& d = g.d[q];
     const int n = static_cast<int>(d.n);
@@ -459,6 +474,11 @@ hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap)
   int cap = grid_cap > 0 ? grid_cap : 256 * 2;
   int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
   if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
+  if (g.balanced) {  // one workgroup per unit of the longest XCD run
+    uint32_t most = 0;
+    for (int x = 0; x < kXcds; ++x) most = std::max(most, g.xcd_begin[x + 1] - g.xcd_begin[x]);
+    grid = static_cast<int>(most) * kXcds;
+  }
   return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, true, PIPE>, grid, NT, s, g)
              : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, false, PIPE>, grid, NT, s, g);
 }
@@ -492,8 +512,20 @@ void finalize_gemm_group(GemmGroup& g, int config_idx) {
     u += tm * tn;
   }
   g.total_units = u;
+  uint32_t units[kMaxGroup], ksteps[kMaxGroup];
+  for (uint32_t i = 0; i < g.count; ++i) {
+    units[i] = g.d[i].units;
+    ksteps[i] = (g.d[i].n + c.bk - 1) / c.bk;
+  }
+  balance_xcd_runs(g.count, units, ksteps, g.xcd_begin);
+  g.balanced = 0;
 }
-hipError_t launch_sgemm_group(const GemmGroup& g, int config_idx, hipStream_t s, int grid_cap) {
+hipError_t launch_sgemm_group(const GemmGroup& g_in, int config_idx, hipStream_t s, int grid_cap) {
+  GemmGroup g = g_in;
+  g.balanced = 0;
+  if (grid_cap > 0 && static_cast<uint32_t>(grid_cap) >= g.total_units && g.count > 1) {
+    for (uint32_t i = 1; i < g.count; ++i) g.balanced |= g.d[i].n != g.d[0].n;
+  }
   bool vec = true;
   for (uint32_t i = 0; i < g.count; ++i)
     if ((g.d[i].n % 4) != 0 || (reinterpret_cast<uintptr_t>(g.d[i].A) & 15) ||
