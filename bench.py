@@ -24,7 +24,9 @@ Beside it:
   requests one after another;
 * ``serving``: a short run of the serving configuration (64 open-loop ranks,
   Poisson arrivals at 2000 requests/s) with its p50 / p99 latency;
-* ``cpu_baseline``: the oracle on the host cores over a bounded sample.
+* ``cpu_baseline``: the plain C oracle run SPMD on the host cores (one
+  process per rank, at most 16) over a bounded sample; ``cpu_baseline_python``
+  the Python oracle (a float64 library matmul) on one process.
 
 Prints ONE JSON line.
 """
@@ -377,6 +379,58 @@ def cpu_baseline(specs, main_kernel, budget_s=10.0):
                       f"{len(reqs)} requests of this kernel, sizes {sorted({n for _, n, _ in reqs})}, cycled)"}
 
 
+def c_oracle_rank(kernel_id, cfg_idx, rank, n, budget_s):
+    """One SPMD process of the C oracle's CPU baseline: the plain C oracle
+    (oracle/liboracle.so) on this rank's request, repeated (SGEMM: eight rows
+    of C at a time, cycling over the rows) for about `budget_s` seconds.
+    Returns the algorithmic work done and the time taken."""
+    from oracle import c_oracle as co
+
+    lib = co.load()
+    t0 = time.perf_counter()
+    flop = byts = 0.0
+    if kernel_id == G.GVM_K_SGEMM:
+        A, B = wl.sgemm_inputs(cfg_idx, rank, n)
+        row = 0
+        while time.perf_counter() - t0 < budget_s:
+            rows = min(8, n - row)
+            co.sgemm_rows_f64(A, B, row, rows, lib=lib)
+            flop += 2.0 * rows * n * n
+            row = (row + rows) % n
+    elif kernel_id == G.GVM_K_BLACKSCHOLES:
+        S, K, T = wl.bs_inputs(cfg_idx, rank, n)
+        while time.perf_counter() - t0 < budget_s:
+            co.black_scholes_f64(S, K, T, wl.BS_RATE, wl.BS_VOLATILITY, lib=lib)
+            byts += 20.0 * n
+    else:
+        a, b = wl.vecadd_inputs(cfg_idx, rank, n)
+        while time.perf_counter() - t0 < budget_s:
+            co.vecadd_f32(a, b, lib=lib)
+            byts += 12.0 * n
+    return {"flop": flop, "bytes": byts, "elapsed": time.perf_counter() - t0}
+
+
+def cpu_baseline_c(ctx, specs, main_kernel, budget_s=10.0):
+    """The plain C oracle run SPMD on the host's cores, as the paper runs its
+    SPMD programs: one process per rank of the main kernel (at most 16, the
+    host share of the box), each repeating its own request (SGEMM: a slice of
+    rows of C) for about `budget_s` seconds."""
+    reqs = [(r, n, c) for r, (k, n, c) in enumerate(specs) if k == main_kernel]
+    procs = min(len(reqs), MAX_GPU_PROCESSES, os.cpu_count() or 1)
+    res = spmd.run_processes(c_oracle_rank, [(main_kernel, c, r, n, budget_s) for r, n, c in reqs[:procs]],
+                             timeout_s=budget_s * 4 + 120)
+    el = max(x["elapsed"] for x in res)
+    if main_kernel == G.GVM_K_SGEMM:
+        value, unit, what = sum(x["flop"] for x in res) / el / 1e9, "GFLOP/s", "rows of C through ref_sgemm_rows_f64"
+    else:
+        value, unit = sum(x["bytes"] for x in res) / el / 1e9, "GB/s"
+        what = "whole requests through " + ("ref_bs_f64" if main_kernel == G.GVM_K_BLACKSCHOLES else "ref_vecadd_f32")
+    return {"value": round(value, 3), "unit": unit, "cores": procs, "kind": "oracle",
+            "sample": f"plain C oracle (oracle/liboracle.so, gcc -O2), SPMD: {procs} processes, one per rank of the "
+                      f"workload's {len(reqs)} requests of this kernel, each repeating its own request ({what}) for "
+                      f"{budget_s:.0f} s; sizes {sorted(n for _, n, _ in reqs[:procs])}"}
+
+
 def run_plain(ctx, specs, warm=False, seq=False, flop_total=0.0, bytes_total=0.0, unit="GFLOP/s"):
     nranks = len(specs)
     nproc = min(nranks, MAX_GPU_PROCESSES)
@@ -571,10 +625,14 @@ def main(argv=None):
     # bytes crossing PCIe per step: every input in, every result out
     pcie_bytes = sum((G.in_elems(k, n) + G.out_elems(k, n)) * 4 for k, n, _ in specs)
 
-    cpu = None
+    cpu = cpu_py = None
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(specs, main_kernel, a.cpu_seconds)
+        if main_kernel != G.GVM_K_EP and not a.rank_threads:
+            cpu = cpu_baseline_c(ctx, specs, main_kernel, a.cpu_seconds)
+            cpu_py = cpu_baseline(specs, main_kernel, a.cpu_seconds / 2)
+        else:
+            cpu = cpu_baseline(specs, main_kernel, a.cpu_seconds)
 
     serving = None
     if a.serving_seconds > 0 and not a.loopback and not a.rank_threads:
@@ -601,6 +659,7 @@ def main(argv=None):
                             "completions", "rank_kind": "threads" if a.rank_threads else "processes"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_baseline_python": cpu_py,
         "latency_us": e2e["latency_us"],
         "step_breakdown_us": e2e["step_breakdown_us"],
         "step_detail_us": e2e["step_detail_us"],
