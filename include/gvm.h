@@ -251,6 +251,29 @@ const char* gvm_last_error(void);
 int gvm_plain_run(int kernel_id, const void* in, void* out, uint64_t n,
                   float bs_rate, float bs_volatility, double* t);
 
+/* Allocation-free variant of gvm_plain_run, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It enqueues the same kernel code objects on
+ * caller-owned device buffers and returns without waiting:
+ *   d_in    device memory of the current device holding the packed input of
+ *           the request (layouts above); 16-byte alignment gives the
+ *           vectorised SGEMM loads;
+ *   d_out   device memory receiving the packed output;
+ *   stream  a hipStream_t of the current device (NULL: the null stream).
+ * The caller owns both buffers and synchronises the stream before reading
+ * d_out.  It calls no hipMalloc, hipFree or allocating routine.  The EP-like
+ * kernel's per-unit partial records (96 bytes per 2^15 pairs) go to a static
+ * device array of GVM_NOALLOC_SCRATCH_BYTES per GPU, held until the process
+ * ends; an EP request needing more (n > 357,892,096 pairs) returns
+ * GVM_ENOMEM before anything is enqueued.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (different streams or threads) race
+ * and must be serialised by the caller.  GVM_EINVAL for a bad kernel id,
+ * size or NULL buffer; GVM_EDEVICE for a device that is not a gfx950 or a
+ * failed launch. */
+#define GVM_NOALLOC_SCRATCH_BYTES (1u << 20)
+int gvm_plain_run_noalloc(int kernel_id, const void* d_in, void* d_out, uint64_t n,
+                          float bs_rate, float bs_volatility, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

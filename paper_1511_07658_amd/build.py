@@ -43,6 +43,7 @@ LIB_SOURCES = [
     ("ep_kernels.hip", "hip"),
     ("device_hip.cpp", "hip"),
     ("plain.cpp", "hip"),
+    ("plain_noalloc.hip", "hip"),
     ("batch_plan.cpp", "host"),
     ("device_loopback.cpp", "host"),
     ("manager.cpp", "host"),

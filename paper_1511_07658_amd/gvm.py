@@ -126,6 +126,8 @@ def lib():
         L.gvm_last_error.restype = ctypes.c_char_p
         L.gvm_plain_run.argtypes = [i32, vp, vp, u64, ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]
         L.gvm_plain_run.restype = i32
+        L.gvm_plain_run_noalloc.argtypes = [i32, vp, vp, u64, ctypes.c_float, ctypes.c_float, vp]
+        L.gvm_plain_run_noalloc.restype = i32
         _lib = L
     return _lib
 
@@ -246,6 +248,11 @@ def gvm_plain_run(kernel_id, in_buf, out_buf, n, bs_rate=0.02, bs_volatility=0.3
     t = (ctypes.c_double * 6)()
     rc = lib().gvm_plain_run(kernel_id, _ptr(in_buf), _ptr(out_buf), n, bs_rate, bs_volatility, t)
     return rc, list(t)
+
+
+def gvm_plain_run_noalloc(kernel_id, d_in, d_out, n, bs_rate=0.02, bs_volatility=0.30, stream=None):
+    """d_in, d_out: device addresses (int); stream: a hipStream_t as int, or None."""
+    return lib().gvm_plain_run_noalloc(kernel_id, d_in, d_out, n, bs_rate, bs_volatility, stream)
 
 
 class GvmError(RuntimeError):
