@@ -156,11 +156,21 @@ typedef struct gvm_config {
                                    one for compute units.  Both partitions hold CUs of every
                                    XCD.  GVM_EINVAL for other values, in batch mode, or on a
                                    device without 256 CUs (gvm_init). */
+  uint32_t small_request_bytes; /* serving mode: a request whose input and output total at
+                                   most this many bytes is small.  Admission stays first-come
+                                   first-served; after it a small request's staging copies
+                                   (shared memory <-> pinned) go ahead of every larger
+                                   request's queued ones on the copy threads.  The copies to
+                                   and from HBM keep one FIFO per direction for every class
+                                   (two concurrent streams in one direction cut the link's
+                                   duplex rate).  0: one class, first-come first-served
+                                   throughout.  Default 8 MiB */
   char name[GVM_NAME_MAX];      /* shared-memory namespace; "" = "gvm.<uid>" */
 } gvm_config;
 
 /* Fill `cfg` with defaults (nranks 8, 64 MiB per rank, budget 16 GiB, batch mode,
- * AUTO policy, window 2000 us, HIP backend, r 0.02, sigma 0.30). */
+ * AUTO policy, window 2000 us, HIP backend, r 0.02, sigma 0.30, small requests up
+ * to 8 MiB). */
 void gvm_config_default(gvm_config* cfg);
 
 /* The CU masks the manager uses for gvm_config.latency_cus (extension; no
@@ -235,8 +245,19 @@ void* gvm_rank_buffer(int rank, uint64_t bytes);
  * admission waits, peak device bytes.  Returns the JSON length, or a
  * negative status; the text is truncated to cap-1 bytes. */
 int gvm_stats_json(char* buf, uint64_t cap);
-/* Reset the manager's statistics counters. */
+/* Reset the manager's statistics counters (and the request trace). */
 int gvm_stats_reset(void);
+
+/* Write the manager's per-request trace to the file `path` as Chrome
+ * trace-event JSON (opened by Perfetto and chrome://tracing): one track per
+ * rank, and per request four slices from the manager's timestamps --
+ * "queued" (submitted -> admitted: ring, request barrier, admission),
+ * "copy-in" (admitted -> device work enqueued), "device" (enqueued -> seen
+ * complete: copies to and from HBM and the kernel) and "copy-out" (-> result
+ * posted), each with the ticket, n and status.  Covers the last 2^20
+ * requests answered since gvm_init or gvm_stats_reset.  GVM_ESTATE without a
+ * manager in this process, GVM_ESYS if the file cannot be written. */
+int gvm_trace_dump(const char* path);
 
 /* Text of the calling thread's last error ("" if none). */
 const char* gvm_last_error(void);

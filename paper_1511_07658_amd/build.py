@@ -88,7 +88,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"compilation failed:\n{msg}")
     objs = [o for *_, o in results]
     tmp = LIB + ".tmp"
-    rc, out = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lrt", "-lpthread"])
+    rc, out = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lrt", "-lpthread", "-ldl"])
     if rc != 0:
         raise RuntimeError(f"link failed:\n{out}")
     os.replace(tmp, LIB)

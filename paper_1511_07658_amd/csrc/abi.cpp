@@ -33,6 +33,7 @@ void gvm_config_default(gvm_config* cfg) {
   cfg->copy_threads = 4;
   cfg->bs_rate = 0.02f;
   cfg->bs_volatility = 0.30f;
+  cfg->small_request_bytes = 8u << 20;
   cfg->name[0] = 0;
 }
 
@@ -144,6 +145,13 @@ int gvm_stats_reset(void) {
   if (!g_mgr) return gvm::fail(GVM_ESTATE, "no manager runs in this process");
   g_mgr->reset_stats();
   return GVM_OK;
+}
+
+int gvm_trace_dump(const char* path) {
+  gvm::clear_error();
+  std::lock_guard<std::mutex> lk(g_mgr_mu);
+  if (!g_mgr) return gvm::fail(GVM_ESTATE, "no manager runs in this process");
+  return g_mgr->trace_dump(path);
 }
 
 const char* gvm_last_error(void) { return gvm::last_error_text(); }

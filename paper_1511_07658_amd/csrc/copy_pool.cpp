@@ -85,11 +85,13 @@ void CopyEngine::stop() {
   for (auto& t : threads_) t.join();
   threads_.clear();
   // anything still queued is copied here so that no waiter is left behind
-  for (Chunk& c : queue_) {
-    copy(c.dst, c.src, c.bytes);
-    c.pending->fetch_sub(1, std::memory_order_acq_rel);
+  for (auto* q : {&urgent_, &queue_}) {
+    for (Chunk& c : *q) {
+      copy(c.dst, c.src, c.bytes);
+      c.pending->fetch_sub(1, std::memory_order_acq_rel);
+    }
+    q->clear();
   }
-  queue_.clear();
 }
 
 void CopyEngine::worker() {
@@ -101,17 +103,18 @@ void CopyEngine::worker() {
     Chunk c;
     {
       std::unique_lock<std::mutex> lk(mu_);
-      cv_.wait(lk, [&] { return stopping_ || !queue_.empty(); });
-      if (queue_.empty()) return;  // stopping and drained
-      c = queue_.front();
-      queue_.pop_front();
+      cv_.wait(lk, [&] { return stopping_ || !queue_.empty() || !urgent_.empty(); });
+      std::deque<Chunk>& q = urgent_.empty() ? queue_ : urgent_;
+      if (q.empty()) return;  // stopping and drained
+      c = q.front();
+      q.pop_front();
     }
     copy(c.dst, c.src, c.bytes);
     c.pending->fetch_sub(1, std::memory_order_acq_rel);
   }
 }
 
-void CopyEngine::submit(void* dst, const void* src, size_t bytes, std::atomic<int>* pending) {
+void CopyEngine::submit(void* dst, const void* src, size_t bytes, std::atomic<int>* pending, bool urgent) {
   if (bytes == 0) return;
   if (threads_.empty()) {
     copy(static_cast<char*>(dst), static_cast<const char*>(src), bytes);
@@ -121,12 +124,13 @@ void CopyEngine::submit(void* dst, const void* src, size_t bytes, std::atomic<in
   pending->fetch_add(static_cast<int>(n), std::memory_order_acq_rel);
   {
     std::lock_guard<std::mutex> lk(mu_);
+    std::deque<Chunk>& q = urgent ? urgent_ : queue_;
     for (size_t i = 0; i < n; ++i) {
       const size_t off = i * kChunk;
       const size_t len = (off + kChunk <= bytes) ? kChunk : bytes - off;
-      queue_.push_back(Chunk{static_cast<char*>(dst) + off, static_cast<const char*>(src) + off, len, pending});
+      q.push_back(Chunk{static_cast<char*>(dst) + off, static_cast<const char*>(src) + off, len, pending});
     }
-    if (queue_.size() > max_queue_) max_queue_ = queue_.size();
+    if (queue_.size() + urgent_.size() > max_queue_) max_queue_ = queue_.size() + urgent_.size();
   }
   if (n == 1) cv_.notify_one(); else cv_.notify_all();
 }

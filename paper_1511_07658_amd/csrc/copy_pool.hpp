@@ -24,7 +24,9 @@ class CopyEngine {
   // the workers in parallel.  `pending` is incremented by the number of
   // chunks now and decremented as each chunk lands; the copy is complete
   // when it reads 0 (acquire).  Without workers the copy runs inline.
-  void submit(void* dst, const void* src, size_t bytes, std::atomic<int>* pending);
+  // `urgent` chunks (a small request's) go ahead of every queued ordinary
+  // chunk; each of the two queues is first-in first-out.
+  void submit(void* dst, const void* src, size_t bytes, std::atomic<int>* pending, bool urgent = false);
   int threads() const { return static_cast<int>(threads_.size()); }
 
   // Bytes moved, summed time the workers spent copying, and the deepest
@@ -50,6 +52,7 @@ class CopyEngine {
   std::mutex mu_;
   std::condition_variable cv_;
   std::deque<Chunk> queue_;
+  std::deque<Chunk> urgent_;
   bool stopping_ = false;
   size_t max_queue_ = 0;
   std::atomic<uint64_t> bytes_{0}, busy_ns_{0};

@@ -46,6 +46,7 @@ struct Job {
   std::unique_ptr<std::atomic<int>[]> in_pending;      // host copy chunks in flight per input piece
   uint32_t out_pieces = 0, out_taken = 0;              // output pieces; those handed to the host copy
   int part = -1;                 // CU partition of its kernel (latency_cus): 0 latency class, 1 the rest
+  bool small = false;            // serving: a small request (small_request_bytes), staging copies first
 };
 
 struct KernelStats {

@@ -1,5 +1,6 @@
 #include "manager.hpp"
 
+#include <dlfcn.h>
 #include <immintrin.h>
 #include <sched.h>
 #include <pthread.h>
@@ -9,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <future>
 #include <new>
@@ -16,6 +18,43 @@
 #include "common.hpp"
 
 namespace gvm {
+
+namespace {
+
+// ROCTx ranges around the service loop's stages (GVM_ROCTX=1), so that a
+// rocprofv3 marker trace shows the manager's host work beside the kernels:
+// "gvm:drain" (rings), "gvm:complete" (completions and answers),
+// "gvm:schedule" (barrier and admission), "gvm:launch" (enqueue).  The
+// library is opened at run time; without the variable, or without the
+// library, the ranges cost one branch.
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+  Roctx() {
+    const char* e = getenv("GVM_ROCTX");
+    if (!e || e[0] != '1') return;
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!push || !pop) push = nullptr, pop = nullptr;
+  }
+};
+const Roctx& roctx() {
+  static const Roctx r;
+  return r;
+}
+struct RoctxRange {
+  explicit RoctxRange(const char* what) : on(roctx().push != nullptr) {
+    if (on) roctx().push(what);
+  }
+  ~RoctxRange() {
+    if (on) roctx().pop();
+  }
+  bool on;
+};
+
+}  // namespace
 
 // ---------------------------------------------------------------- Arena
 
@@ -182,14 +221,29 @@ void Manager::service(std::promise<int>* ready) {
       flush_cv_.notify_all();
     }
     const uint64_t t_it = now_ns();
-    bool progress = drain_rings();
-    const bool done = complete_jobs();
+    bool progress;
+    bool done;
+    {
+      RoctxRange rr("gvm:drain");
+      progress = drain_rings();
+    }
+    {
+      RoctxRange rr("gvm:complete");
+      done = complete_jobs();
+    }
     wake_group();
     const uint64_t t_done = now_ns();
     progress |= done;
     check_liveness();
-    progress |= schedule();
-    const bool launched = launch_ready();
+    bool launched;
+    {
+      RoctxRange rr("gvm:schedule");
+      progress |= schedule();
+    }
+    {
+      RoctxRange rr("gvm:launch");
+      launched = launch_ready();
+    }
     progress |= launched;
     wake_group();  // answers given while scheduling or launching
     if (progress) {
@@ -371,6 +425,15 @@ void Manager::respond(int r, uint64_t ticket, uint32_t kernel_id, int status, co
   else if (sleep == kSleepGroupBell) group_wake_ = true;  // woken with the rest by wake_group()
   if (kernel_id >= GVM_K_VECADD && kernel_id <= GVM_K_EP) {
     std::lock_guard<std::mutex> lk(stats_mu_);
+    const TraceRec tr{r, kernel_id, status, 0, j ? j->req.n : 0, ticket, t_submit, resp.t_admit_ns,
+                      resp.t_launch_ns, resp.t_device_ns, resp.t_done_ns};
+    if (trace_.size() < kTraceMax) {
+      trace_.push_back(tr);
+    } else {
+      trace_[trace_next_] = tr;
+      trace_next_ = (trace_next_ + 1) % kTraceMax;
+    }
+    ++n_traced_;
     if (status == GVM_OK) {
       ++n_done_;
       auto& v = lat_us_[kernel_id];
@@ -441,7 +504,7 @@ bool Manager::complete_jobs() {
         for (; j->out_taken < static_cast<uint32_t>(n); ++j->out_taken) {
           const uint64_t off = static_cast<uint64_t>(j->out_taken) * piece_bytes();
           copy_.submit(j->shm + j->req.off_out + off, j->pin + out_off + off,
-                       std::min<uint64_t>(piece_bytes(), j->lay.out_bytes - off), &j->copies);
+                       std::min<uint64_t>(piece_bytes(), j->lay.out_bytes - off), &j->copies, j->small);
           any = true;
         }
         if (j->out_taken < j->out_pieces) continue;
@@ -451,7 +514,7 @@ bool Manager::complete_jobs() {
     device_done.push_back(j);
     any = true;
     if (j->status == GVM_OK && j->copy_out && !j->out_pieces)
-      copy_.submit(j->shm + j->req.off_out, j->pin + out_off, j->lay.out_bytes, &j->copies);
+      copy_.submit(j->shm + j->req.off_out, j->pin + out_off, j->lay.out_bytes, &j->copies, j->small);
     j->stage = kStageCopyOut;
   }
   // 2. answer every rank whose result is in place, before any bookkeeping
@@ -609,6 +672,9 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   // phase is timed as one span; pieces otherwise (each piece is enqueued when
   // it lands, outside any graph)
   j->local = (copy_in ? lay.in_bytes : 0) + (copy_out ? lay.out_bytes : 0) <= kLocalCopyBytes;
+  // serving: small requests take the copy threads first
+  j->small = cfg_.mode == GVM_MODE_SERVING && cfg_.small_request_bytes &&
+             lay.in_bytes + lay.out_bytes <= cfg_.small_request_bytes;
   j->pieces = !j->local && !(cfg_.batch_timing && cfg_.mode == GVM_MODE_BATCH);
   if (j->pieces && copy_out) j->out_pieces = piece_count(lay.out_bytes);
   if (copy_in) {
@@ -620,10 +686,10 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
         const uint64_t off = static_cast<uint64_t>(i) * piece_bytes();
         const uint64_t len = std::min<uint64_t>(piece_bytes(), lay.in_bytes - off);
         j->in_pending[i].store(0, std::memory_order_relaxed);
-        copy_.submit(j->pin + off, j->shm + m.off_in + off, len, &j->in_pending[i]);
+        copy_.submit(j->pin + off, j->shm + m.off_in + off, len, &j->in_pending[i], j->small);
       }
     } else {
-      copy_.submit(j->pin, j->shm + m.off_in, lay.in_bytes, &j->copies);
+      copy_.submit(j->pin, j->shm + m.off_in, lay.in_bytes, &j->copies, j->small);
     }
   } else {
     j->stage = kStageReady;
@@ -834,12 +900,69 @@ void Manager::reset_stats() {
   iter_done_us_.clear();
   for (auto& k : kstats_) k = KernelStats{};
   peak_bytes_ = 0;
+  trace_.clear();
+  trace_next_ = 0;
+  n_traced_ = 0;
   timing_json_ = "{}";
   copy_.reset_stats();
   stats_t0_ns_ = now_ns();
   stats_cpu0_ns_ = service_cpu_ns();
   // the device counters are reset on the service thread's next completion
   reset_pending_.store(true);
+}
+
+// Chrome trace-event JSON (read by Perfetto and chrome://tracing): process 1
+// is the manager, one thread track per rank; each request is four complete
+// ("X") slices on its rank's track, times in microseconds from the earliest
+// submit in the file:
+//   queued    submit -> admitted (ring, barrier or admission wait)
+//   copy-in   admitted -> device work enqueued (shared memory -> pinned)
+//   device    enqueued -> device work seen complete (H2D, kernel, D2H)
+//   copy-out  device done -> result posted (pinned -> shared memory)
+// A stage whose timestamps are missing (a rejected request) is left out.
+int Manager::trace_dump(const char* path) {
+  if (!started_) return fail(GVM_ESTATE, "no manager runs in this process");
+  if (!path || !*path) return fail(GVM_EINVAL, "trace path is empty");
+  std::vector<TraceRec> recs;
+  uint64_t total = 0;
+  {
+    std::lock_guard<std::mutex> lk(stats_mu_);
+    recs.reserve(trace_.size());
+    for (size_t i = 0; i < trace_.size(); ++i) recs.push_back(trace_[(trace_next_ + i) % trace_.size()]);
+    total = n_traced_;
+  }
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(GVM_ESYS, "cannot open %s for writing", path);
+  uint64_t t0 = UINT64_MAX;
+  for (const TraceRec& t : recs)
+    if (t.t_submit && t.t_submit < t0) t0 = t.t_submit;
+  if (t0 == UINT64_MAX) t0 = 0;
+  fprintf(f, "{\"displayTimeUnit\":\"ns\",\"otherData\":{\"requests_traced\":%llu,\"requests_in_file\":%zu},"
+             "\"traceEvents\":[\n", (unsigned long long)total, recs.size());
+  fprintf(f, "{\"ph\":\"M\",\"pid\":1,\"name\":\"process_name\",\"args\":{\"name\":\"gvm manager %s\"}}", ns_.c_str());
+  std::vector<int> named(cfg_.nranks, 0);
+  for (const TraceRec& t : recs) {
+    if (t.rank >= 0 && t.rank < static_cast<int>(cfg_.nranks) && !named[static_cast<size_t>(t.rank)]) {
+      named[static_cast<size_t>(t.rank)] = 1;
+      fprintf(f, ",\n{\"ph\":\"M\",\"pid\":1,\"tid\":%d,\"name\":\"thread_name\",\"args\":{\"name\":\"rank %d\"}}",
+              t.rank, t.rank);
+    }
+    const uint64_t st[5] = {t.t_submit, t.t_admit, t.t_launch, t.t_device, t.t_done};
+    static const char* const names[4] = {"queued", "copy-in", "device", "copy-out"};
+    for (int k = 0; k < 4; ++k) {
+      if (!st[k] || !st[k + 1] || st[k + 1] < st[k]) continue;
+      fprintf(f,
+              ",\n{\"ph\":\"X\",\"pid\":1,\"tid\":%d,\"name\":\"%s\",\"cat\":\"%s\",\"ts\":%.3f,\"dur\":%.3f,"
+              "\"args\":{\"ticket\":%llu,\"n\":%llu,\"status\":%d}}",
+              t.rank, names[k], t.kernel_id >= 1 && t.kernel_id <= 5 ? kernel_name(static_cast<int>(t.kernel_id)) : "?",
+              (st[k] - t0) * 1e-3, (st[k + 1] - st[k]) * 1e-3, (unsigned long long)t.ticket, (unsigned long long)t.n,
+              t.status);
+    }
+  }
+  fprintf(f, "\n]}\n");
+  const bool ok = !ferror(f);
+  fclose(f);
+  return ok ? GVM_OK : fail(GVM_ESYS, "write to %s failed", path);
 }
 
 }  // namespace gvm

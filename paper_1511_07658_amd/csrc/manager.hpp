@@ -46,6 +46,9 @@ class Manager {
   int shutdown();
   int stats_json(std::string* out);
   void reset_stats();
+  // Per-request trace (the last kTraceMax requests since the start or the
+  // last reset) as a Chrome trace-event JSON file.
+  int trace_dump(const char* path);
   bool running() const { return started_; }
 
  private:
@@ -128,6 +131,19 @@ class Manager {
   std::vector<double> iter_done_us_;   // their complete_jobs part
   KernelStats kstats_[kNumKernelIds];
   uint64_t peak_bytes_ = 0;
+  // per-request trace records, a ring of the last kTraceMax
+  struct TraceRec {
+    int32_t rank;
+    uint32_t kernel_id;
+    int32_t status;
+    uint32_t pad;
+    uint64_t n, ticket;
+    uint64_t t_submit, t_admit, t_launch, t_device, t_done;
+  };
+  static constexpr size_t kTraceMax = 1u << 20;
+  std::vector<TraceRec> trace_;
+  size_t trace_next_ = 0;          // next slot of the ring once it is full
+  uint64_t n_traced_ = 0;
   std::string timing_json_ = "{}";
 };
 

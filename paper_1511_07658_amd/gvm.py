@@ -75,6 +75,7 @@ class gvm_config(ctypes.Structure):
         ("bs_volatility", ctypes.c_float),
         ("batch_timing", ctypes.c_uint32),
         ("latency_cus", ctypes.c_uint32),
+        ("small_request_bytes", ctypes.c_uint32),
         ("name", ctypes.c_char * GVM_NAME_MAX),
     ]
 
@@ -122,6 +123,8 @@ def lib():
         L.gvm_stats_json.restype = i32
         L.gvm_stats_reset.argtypes = []
         L.gvm_stats_reset.restype = i32
+        L.gvm_trace_dump.argtypes = [ctypes.c_char_p]
+        L.gvm_trace_dump.restype = i32
         L.gvm_last_error.argtypes = []
         L.gvm_last_error.restype = ctypes.c_char_p
         L.gvm_plain_run.argtypes = [i32, vp, vp, u64, ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]
@@ -253,6 +256,10 @@ def gvm_plain_run(kernel_id, in_buf, out_buf, n, bs_rate=0.02, bs_volatility=0.3
 def gvm_plain_run_noalloc(kernel_id, d_in, d_out, n, bs_rate=0.02, bs_volatility=0.30, stream=None):
     """d_in, d_out: device addresses (int); stream: a hipStream_t as int, or None."""
     return lib().gvm_plain_run_noalloc(kernel_id, d_in, d_out, n, bs_rate, bs_volatility, stream)
+
+
+def gvm_trace_dump(path) -> int:
+    return lib().gvm_trace_dump(path.encode() if isinstance(path, str) else path)
 
 
 class GvmError(RuntimeError):

@@ -98,6 +98,14 @@ def out_bytes(k, n):
     return G.out_elems(k, n) * 4
 
 
+SMALL_BYTES = 8 << 20
+
+
+def request_bytes(k, n):
+    """Input and output bytes of a request (the manager's size classes)."""
+    return (G.in_elems(k, n) + G.out_elems(k, n)) * 4
+
+
 def gvm_rank(ns, rank, trace, start_box, warmup_s, barrier, zero_copy=True, slot_bytes=0, nslots=2, sample_every=0):
     """One open-loop rank against the manager; returns {"records": per-request
     (arrival offset s, kernel, n, latency s, status, stages), "samples":
@@ -220,11 +228,16 @@ def summarize(records, warmup_s, duration_s):
     for name, kid in (("vecadd", 1), ("blackscholes", 2), ("sgemm", 3)):
         lk = sorted(x[3] for x in ok if x[1] == kid)
         per_kernel[name] = {"count": len(lk), "p50_ms": pct(lk, 50), "p99_ms": pct(lk, 99)}
+    # by size class: input and output together at most 8 MiB, or more
+    per_size = {}
+    for name, keep in (("small_le_8MiB", lambda b: b <= SMALL_BYTES), ("large", lambda b: b > SMALL_BYTES)):
+        ls = sorted(x[3] for x in ok if keep(request_bytes(x[1], x[2])))
+        per_size[name] = {"count": len(ls), "p50_ms": pct(ls, 50), "p99_ms": pct(ls, 99)}
     return {"requests": len(recs), "ok": len(ok), "failed": len(recs) - len(ok),
             "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": pct(lat, 100),
             "throughput_req_s": round(len(ok) / window, 2),
             "gemm_GFLOPs": round(flop / window / 1e9, 2), "algorithmic_GBs": round(byts / window / 1e9, 2),
-            "per_kernel": per_kernel, "mean_stage_ms": stage_ms}
+            "per_kernel": per_kernel, "per_size": per_size, "mean_stage_ms": stage_ms}
 
 
 def parse_args(argv=None):
@@ -239,6 +252,9 @@ def parse_args(argv=None):
     ap.add_argument("--copy-threads", type=int, default=16, help="manager threads for shm <-> pinned staging copies")
     ap.add_argument("--copy-api", action="store_true",
                     help="ranks pass private buffers (the API copies them) instead of building in shared memory")
+    ap.add_argument("--small-mib", type=int, default=8,
+                    help="requests of at most this many MiB (input + output) form the manager's small class; "
+                         "0: one class, first-come first-served throughout")
     ap.add_argument("--sample-every", type=int, default=0,
                     help="keep every k-th result of each rank (up to 8 MiB each) for a check after the run")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
@@ -254,7 +270,7 @@ def run(a):
     spmd.prestart()
     ctx = spmd.context()
     r32, v32 = float(np.float32(wl.BS_RATE)), float(np.float32(wl.BS_VOLATILITY))
-    result = {"config": {"ranks": a.ranks, "rank_buffers": "copied by the API" if a.copy_api else "zero-copy in shm", "rate_req_s": a.rate, "duration_s": a.duration, "warmup_s": a.warmup,
+    result = {"config": {"small_class_MiB": a.small_mib, "ranks": a.ranks, "rank_buffers": "copied by the API" if a.copy_api else "zero-copy in shm", "rate_req_s": a.rate, "duration_s": a.duration, "warmup_s": a.warmup,
                          "budget_GiB": a.budget_gib, "copy_threads": a.copy_threads, "kernels": "vecadd n<=2^24, Black-Scholes n<=4M, SGEMM n<=2048",
                          "requests_in_trace": sum(len(t) for t in traces)}}
 
@@ -287,6 +303,7 @@ def run(a):
     cfg = G.gvm_config_default(nranks=a.ranks, shm_bytes_per_rank=space, staging_bytes=(3 * MAX_VEC) * 4 + (1 << 20),
                                hbm_budget_bytes=int(a.budget_gib * (1 << 30)), mode=G.GVM_MODE_SERVING,
                                policy=G.GVM_POLICY_AUTO, max_inflight=a.ranks, copy_threads=a.copy_threads, name=ns,
+                               small_request_bytes=a.small_mib << 20,
                                backend=G.GVM_BACKEND_LOOPBACK if a.loopback else G.GVM_BACKEND_HIP)
     start = ctx.Value("q", 0)
     bar = ctx.Barrier(a.ranks + 1)

@@ -57,7 +57,7 @@ def build(tmp_path, kind):
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 2)) as ex:
         objs = list(ex.map(compile_one, srcs))
     exe = str(out / "host_stress")
-    subprocess.run(["g++", *flags, *objs, "-o", exe, "-lrt", "-lpthread"], check=True)
+    subprocess.run(["g++", *flags, *objs, "-o", exe, "-lrt", "-lpthread", "-ldl"], check=True)
     return exe
 
 
