@@ -467,7 +467,8 @@ def serving_leg(seconds, copy_threads):
     return {"ranks": 64, "rate_req_s": 2000, "measured_s": seconds, "requests": g["requests"], "ok": g["ok"],
             "failed": g["failed"], "p50_ms": g["p50_ms"], "p99_ms": g["p99_ms"], "max_ms": g["max_ms"],
             "throughput_req_s": g["throughput_req_s"], "gemm_GFLOPs": g["gemm_GFLOPs"],
-            "algorithmic_GBs": g["algorithmic_GBs"], "per_kernel": g["per_kernel"],
+            "algorithmic_GBs": g["algorithmic_GBs"], "per_kernel": g["per_kernel"], "per_size": g["per_size"],
+            "mean_stage_ms": g["mean_stage_ms"],
             "budget_GiB": 64, "command": "python -m paper_1511_07658_amd.loadgen --ranks 64 --rate 2000 "
                                          f"--duration {seconds + warm} --warmup {warm} --no-plain"}
 
