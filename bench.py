@@ -486,6 +486,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--graphs", type=int, default=0, help="replay repeated batches as HIP graphs")
+    ap.add_argument("--copy-threads", type=int, default=8, help="manager threads for shared memory <-> pinned copies")
     ap.add_argument("--rank-threads", action="store_true",
                     help="run the ranks as threads of this process (for profilers that cannot follow forks)")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
@@ -528,7 +529,7 @@ def main(argv=None):
     # 2. the GVM manager in this process, ranks in forked processes
     ns = f"gvm.bench.{os.getpid()}"
     space = max((G.in_elems(k, n) + G.out_elems(k, n)) * 4 for k, n, _ in specs) + (1 << 20)
-    copy_threads = 8
+    copy_threads = a.copy_threads
     cfg = G.gvm_config_default(nranks=nranks, shm_bytes_per_rank=space,
                                hbm_budget_bytes=max(2 << 30, 2 * nranks * space),
                                mode=G.GVM_MODE_BATCH, policy=G.GVM_POLICY_AUTO, batch_window_us=5_000_000,
@@ -656,6 +657,7 @@ def main(argv=None):
         "data": "synthetic (seeded by rank)",
         "config": {"workload": WORKLOADS[a.workload], "name": a.workload,
                    "ranks": nranks, "mode": "batch", "policy": "auto", "graphs": bool(a.graphs),
+                   "copy_threads": copy_threads,
                    "timed": "every step: shared memory -> HBM copies, kernels, HBM -> shared memory copies, "
                             "completions", "rank_kind": "threads" if a.rank_threads else "processes"},
         "roofline": roof,
