@@ -89,7 +89,8 @@ enum gvm_mode {
   GVM_MODE_BATCH = 0,   /* request barrier of Section 5: wait until every attached rank
                            has a request (or batch_window_us expires), run them together */
   GVM_MODE_SERVING = 1  /* continuous admission: run requests as soon as device memory
-                           (hbm_budget_bytes) and in-flight slots allow */
+                           (hbm_budget_bytes) and in-flight slots allow; up to two
+                           requests of a rank in flight (see gvm_submit) */
 };
 
 /* Enqueue policy for a set of requests run together (Section 4.2.1):
@@ -114,7 +115,9 @@ enum gvm_backend { GVM_BACKEND_HIP = 0, GVM_BACKEND_LOOPBACK = 1 };
 /* Submit flags (gvm_submit_ex). */
 enum gvm_submit_flags {
   GVM_F_IN_RESIDENT = 1u,   /* the input is the one left on the device by this rank's previous
-                               request with the same kernel id and n; no copy-in, `in` may be NULL */
+                               request with the same kernel id and n; no copy-in, `in` may be NULL.
+                               Serving mode: when the previous request overlapped an earlier
+                               one and finished first, its input is gone (GVM_ESTATE) */
   GVM_F_OUT_RESIDENT = 2u,  /* leave the result on the device; no copy-out, `out` may be NULL */
   GVM_F_NONBLOCK = 4u       /* return GVM_EAGAIN instead of waiting when the ring is full */
 };
@@ -132,7 +135,8 @@ typedef struct gvm_config {
   uint32_t mode;                /* gvm_mode */
   uint32_t policy;              /* gvm_policy */
   uint32_t batch_window_us;     /* batch mode: longest wait for the barrier after the first request */
-  uint32_t max_inflight;        /* serving mode: requests on the device at once (0 = nranks) */
+  uint32_t max_inflight;        /* serving mode: requests on the device at once (0 = two per
+                                   rank) */
   uint32_t nstreams;            /* HIP streams for per-rank work (0 = min(nranks, 8)) */
   uint32_t use_graphs;          /* 1: grouped batches are captured once per template (ranks,
                                    kernels, sizes, copy flags, buffers) into a HIP graph and
@@ -201,7 +205,13 @@ int gvm_attach_ns(const char* name, int rank);
  * the rank's space (gvm_rank_buffer), which is then used in place.  `out`
  * must stay valid until gvm_wait returns for this ticket; if it points
  * inside the rank's space the result is left there.  Returns a ticket >= 0
- * or a negative gvm_status.  Requests of one rank run in submission order. */
+ * or a negative gvm_status.  Requests of one rank are admitted in submission
+ * order.  In batch mode a rank has one request in flight at a time; in
+ * serving mode a second plain request (no resident flags) may be admitted
+ * while the first is still in flight, so that its copies overlap the first's
+ * device work, and the two may finish in either order (wait by ticket or
+ * with gvm_wait_any).  A request with resident flags waits until the rank
+ * has nothing in flight. */
 int64_t gvm_submit(int rank, int kernel_id, const void* in, void* out, uint64_t n);
 int64_t gvm_submit_ex(int rank, int kernel_id, const void* in, void* out, uint64_t n, uint32_t flags);
 

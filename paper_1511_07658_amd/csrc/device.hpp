@@ -47,6 +47,11 @@ struct Job {
   uint32_t out_pieces = 0, out_taken = 0;              // output pieces; those handed to the host copy
   int part = -1;                 // CU partition of its kernel (latency_cus): 0 latency class, 1 the rest
   bool small = false;            // serving: a small request (small_request_bytes), staging copies first
+  // serving: a rank's second request in flight has a device slot of its own
+  // (freed when it is answered) and the staging region after the first's
+  bool extra_slot = false;
+  uint64_t extra_off = 0, extra_size = 0;
+  uint64_t pin_off = 0, pin_len = 0;  // region of the rank's pinned staging it uses
 };
 
 struct KernelStats {

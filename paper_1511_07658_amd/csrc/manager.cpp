@@ -119,7 +119,8 @@ int Manager::init(const gvm_config& cfg_in) {
   if (cfg.latency_cus && (cfg.mode != GVM_MODE_SERVING || cfg.latency_cus % 32 || cfg.latency_cus >= 256))
     return fail(GVM_EINVAL, "latency_cus must be 0, or in serving mode a multiple of 32 below 256");
   cfg.shm_bytes_per_rank = (cfg.shm_bytes_per_rank + 4095) / 4096 * 4096;
-  if (cfg.max_inflight == 0) cfg.max_inflight = cfg.nranks;
+  if (const char* e = getenv("GVM_RANK_DEPTH")) rank_depth_ = (e[0] == '1') ? 1 : kRankDepth;
+  if (cfg.max_inflight == 0) cfg.max_inflight = cfg.nranks * static_cast<uint32_t>(rank_depth_);
   spin_ns_ = spin_env_ns("GVM_MANAGER_SPIN_US", 200);
   cfg.name[GVM_NAME_MAX - 1] = 0;
   cfg_ = cfg;
@@ -458,7 +459,7 @@ void Manager::release_slot(int r) {
 void Manager::reap_rank(int r) {
   RankRt& rt = ranks_[r];
   rt.queue.clear();
-  if (rt.running) return;  // finish the device work first; complete_jobs calls back
+  if (!rt.running.empty()) return;  // finish the device work first; complete_jobs calls back
   release_slot(r);
   rt = RankRt{};
   RankSlot* s = ctl_slot(ctl_, r);
@@ -485,56 +486,74 @@ void Manager::check_liveness() {
   }
 }
 
-// Device completions and host copy-outs, per rank (one job in flight each).
+// Device completions and host copy-outs, per rank (up to kRankDepth jobs in
+// flight each).
 bool Manager::complete_jobs() {
   bool any = false;
   dev_->begin_poll();
   // 1. device work that finished: start the result's copy-out
   std::vector<Job*> device_done;
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
-    Job* j = ranks_[r].running;
-    if (!j || j->stage != kStageDevice) continue;
-    const uint64_t out_off = slot_out_offset(j->lay);
-    if (j->out_pieces && j->status == GVM_OK) {
-      // hand each output piece to the host copy as soon as it is staged
-      const int n = dev_->out_pieces_done(j);
-      if (n < 0) {
-        j->status = n;
-      } else {
-        for (; j->out_taken < static_cast<uint32_t>(n); ++j->out_taken) {
-          const uint64_t off = static_cast<uint64_t>(j->out_taken) * piece_bytes();
-          copy_.submit(j->shm + j->req.off_out + off, j->pin + out_off + off,
-                       std::min<uint64_t>(piece_bytes(), j->lay.out_bytes - off), &j->copies, j->small);
-          any = true;
+    for (Job* j : ranks_[r].running) {
+      if (j->stage != kStageDevice) continue;
+      const uint64_t out_off = slot_out_offset(j->lay);
+      if (j->out_pieces && j->status == GVM_OK) {
+        // hand each output piece to the host copy as soon as it is staged
+        const int n = dev_->out_pieces_done(j);
+        if (n < 0) {
+          j->status = n;
+        } else {
+          for (; j->out_taken < static_cast<uint32_t>(n); ++j->out_taken) {
+            const uint64_t off = static_cast<uint64_t>(j->out_taken) * piece_bytes();
+            copy_.submit(j->shm + j->req.off_out + off, j->pin + out_off + off,
+                         std::min<uint64_t>(piece_bytes(), j->lay.out_bytes - off), &j->copies, j->small);
+            any = true;
+          }
+          if (j->out_taken < j->out_pieces) continue;
         }
-        if (j->out_taken < j->out_pieces) continue;
       }
+      if (dev_->query(j) == 0) continue;
+      device_done.push_back(j);
+      any = true;
+      if (j->status == GVM_OK && j->copy_out && !j->out_pieces)
+        copy_.submit(j->shm + j->req.off_out, j->pin + out_off, j->lay.out_bytes, &j->copies, j->small);
+      j->stage = kStageCopyOut;
     }
-    if (dev_->query(j) == 0) continue;
-    device_done.push_back(j);
-    any = true;
-    if (j->status == GVM_OK && j->copy_out && !j->out_pieces)
-      copy_.submit(j->shm + j->req.off_out, j->pin + out_off, j->lay.out_bytes, &j->copies, j->small);
-    j->stage = kStageCopyOut;
   }
-  // 2. answer every rank whose result is in place, before any bookkeeping
-  std::vector<int> answered;
+  // 2. answer every job whose result is in place, before any bookkeeping
+  std::vector<Job*> answered;
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
     RankRt& rt = ranks_[r];
-    Job* j = rt.running;
-    if (!j || j->stage != kStageCopyOut || j->copies.load(std::memory_order_acquire) != 0) continue;
-    if (rt.attached) respond(static_cast<int>(r), j->req.ticket, j->req.kernel_id, j->status, j, j->req.t_submit_ns);
-    answered.push_back(static_cast<int>(r));
+    for (Job* j : rt.running) {
+      if (j->stage != kStageCopyOut || j->copies.load(std::memory_order_acquire) != 0) continue;
+      if (rt.attached) respond(static_cast<int>(r), j->req.ticket, j->req.kernel_id, j->status, j, j->req.t_submit_ns);
+      answered.push_back(j);
+    }
   }
   // 3. release the device bookkeeping (event timings of a retired batch)
   for (Job* j : device_done) dev_->finish(j);
   // 4. retire the answered jobs
-  for (int r : answered) {
+  for (Job* j : answered) {
+    const int r = j->rank;
     RankRt& rt = ranks_[r];
-    Job* j = rt.running;
     const bool alive = rt.attached;
-    if (j->status != GVM_OK) rt.res_valid = false;
-    rt.running = nullptr;
+    if (j->status != GVM_OK && !j->extra_slot) rt.res_valid = false;
+    rt.running.erase(std::find(rt.running.begin(), rt.running.end(), j));
+    if (j->extra_slot) {
+      if (rt.running.empty() && j->req.ticket == rt.last_ticket) {
+        // the rank's latest request finished last: its slot becomes the
+        // rank's resident slot, as if it had run alone
+        release_slot(r);
+        rt.has_slot = true;
+        rt.slot_off = j->extra_off;
+        rt.slot_size = j->extra_size;
+        rt.res_valid = j->status == GVM_OK;
+        rt.res_kernel = j->req.kernel_id;
+        rt.res_n = j->req.n;
+      } else {
+        arena_.release(j->extra_off, j->extra_size);
+      }
+    }
     rt.last_use_ns = now_ns();
     delete j;
     --inflight_;
@@ -622,6 +641,22 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   Layout lay;
   request_layout(static_cast<int>(m.kernel_id), m.n, &lay);
   const uint64_t need = slot_bytes(lay);
+  const bool second = !rt.running.empty();  // pipelined behind the rank's request in flight
+  uint64_t pin_off = 0;
+  if (second) {
+    // rank_can_take() let only plain requests of a serving rank through; the
+    // staging region goes after (or before) the first request's, if it fits
+    const Job* first = rt.running.front();
+    const uint64_t staging = cfg_.staging_bytes ? cfg_.staging_bytes : cfg_.shm_bytes_per_rank;
+    const uint64_t len = Arena::round(need);
+    if (len <= first->pin_off) {
+      pin_off = 0;
+    } else if (Arena::round(first->pin_off + first->pin_len) + len <= staging) {
+      pin_off = Arena::round(first->pin_off + first->pin_len);
+    } else {
+      return kNotNow;  // both do not fit the staging: wait for the first
+    }
+  }
   if (m.flags & GVM_F_IN_RESIDENT) {
     if (!(rt.res_valid && rt.res_kernel == m.kernel_id && rt.res_n == m.n && rt.has_slot)) {
       respond(r, m.ticket, m.kernel_id, fail(GVM_ESTATE, "no resident input for this request"), nullptr, m.t_submit_ns);
@@ -629,20 +664,28 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
       return kRejected;
     }
   }
-  if (!(rt.has_slot && rt.slot_size >= need)) {
-    release_slot(r);
-    uint64_t off = 0;
-    while (!arena_.alloc(need, &off)) {
+  uint64_t extra_off = 0;
+  auto alloc_evicting = [&](uint64_t* off) {
+    while (!arena_.alloc(need, off)) {
       // evict the least recently used idle rank's resident buffer
       int victim = -1;
       for (uint32_t v = 0; v < cfg_.nranks; ++v) {
         const RankRt& o = ranks_[v];
-        if (static_cast<int>(v) == r || !o.has_slot || o.running) continue;
+        if (static_cast<int>(v) == r || !o.has_slot || !o.running.empty()) continue;
         if (victim < 0 || o.last_use_ns < ranks_[victim].last_use_ns) victim = static_cast<int>(v);
       }
-      if (victim < 0) return kWait;
+      if (victim < 0) return false;
       release_slot(victim);
     }
+    return true;
+  };
+  if (second) {
+    // a device slot of its own, freed when the request is answered
+    if (!alloc_evicting(&extra_off)) return kWait;
+  } else if (!(rt.has_slot && rt.slot_size >= need)) {
+    release_slot(r);
+    uint64_t off = 0;
+    if (!alloc_evicting(&off)) return kWait;
     rt.has_slot = true;
     rt.slot_off = off;
     rt.slot_size = Arena::round(need);
@@ -653,17 +696,24 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
   if (copy_in || copy_out) {
     pin = dev_->staging(r);
     if (!pin) {
+      if (second) arena_.release(extra_off, Arena::round(need));
       respond(r, m.ticket, m.kernel_id, GVM_EDEVICE, nullptr, m.t_submit_ns);
       rt.queue.pop_front();
       return kRejected;
     }
+    pin += pin_off;
   }
   Job* j = new Job;
   j->rank = r;
   j->req = m;
   j->lay = lay;
   j->shm = static_cast<uint8_t*>(data_[r]->addr);
-  j->slot = dev_->arena() + rt.slot_off;
+  j->slot = dev_->arena() + (second ? extra_off : rt.slot_off);
+  j->extra_slot = second;
+  j->extra_off = extra_off;
+  j->extra_size = second ? Arena::round(need) : 0;
+  j->pin_off = pin_off;
+  j->pin_len = Arena::round(need);
   j->pin = pin;
   j->copy_in = copy_in;
   j->copy_out = copy_out;
@@ -695,10 +745,17 @@ Manager::Admit Manager::admit(int r, std::vector<Job*>& jobs) {
     j->stage = kStageReady;
   }
   rt.queue.pop_front();
-  rt.running = j;
-  rt.res_valid = true;
-  rt.res_kernel = m.kernel_id;
-  rt.res_n = m.n;
+  rt.running.push_back(j);
+  rt.last_ticket = m.ticket;
+  if (second) {
+    // the rank's slot keeps the first request's input: nothing of the latest
+    // request stays resident
+    rt.res_valid = false;
+  } else {
+    rt.res_valid = true;
+    rt.res_kernel = m.kernel_id;
+    rt.res_n = m.n;
+  }
   ++inflight_;
   jobs.push_back(j);
   return kAdmitted;
@@ -720,18 +777,26 @@ int Manager::resolve_policy(const std::vector<Job*>& jobs) const {
   return large ? GVM_POLICY_PS2 : GVM_POLICY_GROUPED;
 }
 
+bool Manager::rank_can_take(const RankRt& rt) const {
+  if (rt.running.empty()) return true;
+  if (cfg_.mode != GVM_MODE_SERVING || rt.running.size() >= rank_depth_) return false;
+  const Queued& q = rt.queue.front();
+  // error heads and requests that use the rank's resident slot wait for it
+  return q.status == GVM_OK && !(q.req.flags & (GVM_F_IN_RESIDENT | GVM_F_OUT_RESIDENT));
+}
+
 bool Manager::schedule() {
   bool any = false;
   // Heads that were invalid on arrival are answered in order.
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
     RankRt& rt = ranks_[r];
-    while (!rt.running && !rt.queue.empty() && rt.queue.front().status != GVM_OK) {
+    while (rt.running.empty() && !rt.queue.empty() && rt.queue.front().status != GVM_OK) {
       const Queued q = rt.queue.front();
       rt.queue.pop_front();
       respond(static_cast<int>(r), q.req.ticket, q.req.kernel_id, q.status, nullptr, q.req.t_submit_ns);
       any = true;
     }
-    if (rt.detach_pending && rt.queue.empty() && !rt.running) {
+    if (rt.detach_pending && rt.queue.empty() && rt.running.empty()) {
       release_slot(static_cast<int>(r));
       const uint64_t t = rt.detach_ticket;
       rt = RankRt{};
@@ -748,7 +813,7 @@ bool Manager::schedule() {
     const RankRt& rt = ranks_[r];
     if (!rt.attached) continue;
     ++live;
-    if (rt.running || rt.queue.empty()) continue;
+    if (rt.queue.empty() || !rank_can_take(rt)) continue;
     heads.emplace_back(rt.queue.front().seq, static_cast<int>(r));
     oldest = std::min(oldest, rt.queue.front().t_arrive_ns);
     newest = std::max(newest, rt.queue.front().t_arrive_ns);
@@ -768,6 +833,22 @@ bool Manager::schedule() {
       std::lock_guard<std::mutex> lk(stats_mu_);
       if (batch_lag_us_.size() < (1u << 20)) batch_lag_us_.push_back((now_ns() - newest) * 1e-3);
     }
+    // Order of the batch's copies: the requests move host -> device, then
+    // device -> host, each direction one FIFO (the two copy engines of the
+    // execution model, Section 4.2.3), a two-stage flow shop.  Every kernel
+    // here sends back less than it receives (half for vector add and SGEMM,
+    // two thirds for Black-Scholes), and for such jobs the shortest schedule
+    // takes them by decreasing result size (Johnson's rule): the link's
+    // last transfer after the final input is then the smallest result.
+    auto out_bytes = [&](int r) {
+      Layout l;
+      const Request& q = ranks_[r].queue.front().req;
+      if (!request_layout(static_cast<int>(q.kernel_id), q.n, &l)) return uint64_t(0);
+      return (q.flags & GVM_F_OUT_RESIDENT) ? uint64_t(0) : l.out_bytes;
+    };
+    std::stable_sort(heads.begin(), heads.end(), [&](const std::pair<uint64_t, int>& x, const std::pair<uint64_t, int>& y) {
+      return out_bytes(x.second) > out_bytes(y.second);
+    });
     for (auto& h : heads) {
       Admit a = admit(h.second, jobs);
       if (a == kRejected) any = true;
@@ -778,6 +859,8 @@ bool Manager::schedule() {
       Admit a = admit(h.second, jobs);
       if (a == kWait) break;  // first-come first-served: nobody overtakes a waiting head
       if (a == kRejected) any = true;
+      // kNotNow: a second request of a rank that must wait for the rank's
+      // first; it holds up no other rank
     }
   }
   if (jobs.empty()) return any;
@@ -794,10 +877,8 @@ int Manager::shutdown() {
   thread_.join();
   started_ = false;
   for (uint32_t r = 0; r < cfg_.nranks; ++r) {
-    while (ranks_[r].running) {  // not reached: the service loop drained
-      delete ranks_[r].running;
-      ranks_[r].running = nullptr;
-    }
+    for (Job* j : ranks_[r].running) delete j;  // not reached: the service loop drained
+    ranks_[r].running.clear();
   }
   dev_.reset();
   data_.clear();

@@ -62,18 +62,26 @@ class Manager {
     bool attached = false;
     int32_t pid = 0;
     std::deque<Queued> queue;
-    Job* running = nullptr;
+    std::deque<Job*> running;   // on the device or in its copies, in admission order
     bool has_slot = false;
     uint64_t slot_off = 0;
     uint64_t slot_size = 0;
     bool res_valid = false;     // the slot holds the input of (res_kernel, res_n)
+    uint64_t last_ticket = 0;   // ticket of the rank's latest admitted request
     uint32_t res_kernel = 0;
     uint64_t res_n = 0;
     uint64_t last_use_ns = 0;
     bool detach_pending = false;
     uint64_t detach_ticket = 0;
   };
-  enum Admit { kAdmitted, kWait, kRejected };
+  enum Admit { kAdmitted, kWait, kRejected, kNotNow };
+  // Requests of one rank in flight at once: one in batch mode; in serving
+  // mode a second plain request (no resident flags) may be admitted while
+  // the first is still in flight, so that its copy-in overlaps the first's
+  // device work (Section 4.2.1, concurrency types (a) to (c), within a rank).
+  static constexpr size_t kRankDepth = 2;
+  size_t rank_depth_ = kRankDepth;  // GVM_RANK_DEPTH=1 keeps one request per rank (measurement)
+  bool rank_can_take(const RankRt& rt) const;
 
   void service(std::promise<int>* ready);
   bool drain_rings();

@@ -302,7 +302,7 @@ def run(a):
     space = slot * 2 + (1 << 20)                          # two requests in flight per rank
     cfg = G.gvm_config_default(nranks=a.ranks, shm_bytes_per_rank=space, staging_bytes=(3 * MAX_VEC) * 4 + (1 << 20),
                                hbm_budget_bytes=int(a.budget_gib * (1 << 30)), mode=G.GVM_MODE_SERVING,
-                               policy=G.GVM_POLICY_AUTO, max_inflight=a.ranks, copy_threads=a.copy_threads, name=ns,
+                               policy=G.GVM_POLICY_AUTO, max_inflight=0, copy_threads=a.copy_threads, name=ns,
                                small_request_bytes=a.small_mib << 20,
                                backend=G.GVM_BACKEND_LOOPBACK if a.loopback else G.GVM_BACKEND_HIP)
     start = ctx.Value("q", 0)

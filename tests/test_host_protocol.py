@@ -517,3 +517,41 @@ def test_tile_configuration_names_match_the_compiled_table():
         assert 0 <= int(c) < tune.NUM_CONFIGS, (n, c)
     mix = int(re.search(r"constexpr int kMixConfig = (\d+);", open(os.path.join(csrc, "device_hip.cpp")).read()).group(1))
     assert tune.config_bk(mix) == 16
+
+
+def test_serving_pipelines_two_requests_of_a_rank(ns_name):
+    """Serving mode admits a rank's second plain request while its first is
+    still in flight (its copy-in overlaps the first's copies and device
+    work); every result still carries its own bytes, and a resident-input
+    request afterwards either finds the latest request's input or is refused
+    with GVM_ESTATE, never other bytes."""
+    with Manager(ns_name, nranks=1, shm_bytes_per_rank=64 << 20, hbm_budget_bytes=256 << 20,
+                 mode=G.GVM_MODE_SERVING, copy_threads=1):
+        assert G.gvm_attach_ns(ns_name, 0) == 0
+        overlapped = 0
+        n = 2 << 20
+        per = 3 * n                                  # input (2n) and output (n) of one request
+        view = G.gvm_rank_buffer(0, 2 * per * 4)     # both requests zero-copy in the rank's space
+        for rep in range(10):
+            ins, outs = [], []
+            for i in range(2):
+                x = view[i * per: i * per + 2 * n]
+                x[:] = np.arange(2 * n, dtype=np.float32) + 7 * rep + i
+                ins.append(x.copy())
+                outs.append(view[i * per + 2 * n: (i + 1) * per])
+            tk = [G.check(G.gvm_submit(0, G.GVM_K_VECADD, view[i * per: i * per + 2 * n], outs[i], n), "submit")
+                  for i in range(2)]
+            ts = [G.gvm_wait_timed(0, t, 10_000_000_000) for t in tk]
+            for i in range(2):
+                assert ts[i][0] == 0 and np.array_equal(outs[i], ins[i][:n])
+            # the second admitted (ts[1]) before the first was posted (ts[0])
+            overlapped += ts[1][1][1] < ts[0][1][4]
+            o = np.empty(n, np.float32)
+            t = G.gvm_submit_ex(0, G.GVM_K_VECADD, None, o, n, G.GVM_F_IN_RESIDENT)
+            assert t >= 0
+            rc = G.gvm_wait(0, t, 10_000_000_000)
+            assert rc in (0, G.GVM_ESTATE)
+            if rc == 0:
+                assert np.array_equal(o, ins[1][:n])
+        assert overlapped > 0
+        assert G.gvm_detach(0) == 0
