@@ -466,18 +466,26 @@ class HipDevice final : public Device {
   void reset_stats() override {
     for (auto& s : stats_) s = KernelStats{};
     batch_us_.clear();
-    for (int d = 0; d < 2; ++d) copy_ms_[d] = copy_bytes_[d] = 0.0, copy_n_[d] = 0;
+    launch_us_.clear();
+    for (int d = 0; d < 2; ++d) copy_ms_[d] = copy_bytes_[d] = 0.0, copy_n_[d] = 0, copy_us_[d].clear();
   }
 
+  // Batch device phases, copy and launch durations (us, the last 512 of
+  // each; the copies one entry per copy or piece), and copy totals.
   std::string timing_json() const override {
-    std::string s = "{\"batch_device_us\":[";
-    const size_t first = batch_us_.size() > 512 ? batch_us_.size() - 512 : 0;
-    for (size_t i = first; i < batch_us_.size(); ++i) {
-      if (i > first) s += ",";
-      s += std::to_string(batch_us_[i]);
-    }
+    auto list = [](const std::vector<double>& v) {
+      std::string s = "[";
+      const size_t first = v.size() > 512 ? v.size() - 512 : 0;
+      for (size_t i = first; i < v.size(); ++i) {
+        if (i > first) s += ",";
+        s += std::to_string(v[i]);
+      }
+      return s + "]";
+    };
+    std::string s = "{\"batch_device_us\":" + list(batch_us_) + ",\"h2d_us\":" + list(copy_us_[0]) +
+                    ",\"d2h_us\":" + list(copy_us_[1]) + ",\"launch_us\":" + list(launch_us_);
     char buf[256];
-    snprintf(buf, sizeof(buf), "],\"h2d\":{\"count\":%llu,\"ms\":%.6f,\"bytes\":%.0f},\"d2h\":{\"count\":%llu,\"ms\":%.6f,\"bytes\":%.0f}}",
+    snprintf(buf, sizeof(buf), ",\"h2d\":{\"count\":%llu,\"ms\":%.6f,\"bytes\":%.0f},\"d2h\":{\"count\":%llu,\"ms\":%.6f,\"bytes\":%.0f}}",
              (unsigned long long)copy_n_[0], copy_ms_[0], copy_bytes_[0], (unsigned long long)copy_n_[1], copy_ms_[1],
              copy_bytes_[1]);
     return s + buf;
@@ -926,6 +934,7 @@ class HipDevice final : public Device {
         ks.device_ms += ms;
         ks.work_flop += t.flop;
         ks.work_bytes += t.bytes;
+        if (launch_us_.size() < 65536) launch_us_.push_back(ms * 1e3);
       }
       free_timed_.push_back(t.e0);
       free_timed_.push_back(t.e1);
@@ -943,6 +952,7 @@ class HipDevice final : public Device {
         copy_ms_[c.dir] += ms;
         copy_bytes_[c.dir] += static_cast<double>(c.bytes);
         copy_n_[c.dir] += c.first ? 1 : 0;
+        if (copy_us_[c.dir].size() < 65536) copy_us_[c.dir].push_back(ms * 1e3);
       }
       free_timed_.push_back(c.e0);
       free_timed_.push_back(c.e1);
@@ -1011,7 +1021,7 @@ class HipDevice final : public Device {
   bool capturing_ = false;
   std::vector<hipEvent_t> capture_events_;  // events recorded during the capture in progress
   bool broken_ = false;                     // a stream was left capturing: no more device work
-  std::vector<double> batch_us_;
+  std::vector<double> batch_us_, launch_us_, copy_us_[2];
   double copy_ms_[2] = {0, 0}, copy_bytes_[2] = {0, 0};
   uint64_t copy_n_[2] = {0, 0};
   uint8_t* arena_ = nullptr;

@@ -2,7 +2,10 @@
 paper's model-validation experiment of Section 6).
 
 For each kernel and programming style, the per-rank transfer and compute
-times are profiled with one rank, then N = 1..8 ranks run one request each
+times are profiled with one rank (medians over 24 requests after 4 of
+warm-up, each copy and launch timed with device events on the same copy
+FIFOs and kernel streams the batches use), then N = 1..8 ranks run one
+request each
 as one batch, and the device phase of the batch (first copy-in to last
 copy-out, device events) is compared with the closed forms (Eq. 2/4 for
 PS-1, Eq. 3/7 for PS-2) and with the discrete-event schedule under the
@@ -36,6 +39,7 @@ pytestmark = pytest.mark.gpu
 CASES = [("vecadd", G.GVM_K_VECADD, 1 << 22, 5), ("vecmul", G.GVM_K_VECMUL, 1 << 24, 15),
          ("sgemm", G.GVM_K_SGEMM, 1024, 5), ("ep", G.GVM_K_EP, 1 << 15, 5)]
 NS_LIST = [1, 2, 4, 8]
+PROFILE_WARM, PROFILE_REPS = 4, 24
 
 
 def _run(ns, kernel_id, n, nranks, reps):
@@ -78,14 +82,15 @@ def test_execution_model_on_mi355x(ns_name):
                 # one untimed batch over every rank first: the first copy into a
                 # fresh device slot runs several times slower than later ones
                 _run(ns, kid, n, NS_LIST[-1], 1)
-                # profile one rank: T_in, T_out from the timed copies, T_comp from the kernel events
+                # profile one rank: T_in, T_out, T_comp as medians of the timed
+                # copies and launches after a warm-up
                 G.gvm_stats_reset()
-                st = _run(ns, kid, n, 1, reps)
+                st = _run(ns, kid, n, 1, PROFILE_WARM + PROFILE_REPS)
                 tm = st["timing"]
-                t_in = tm["h2d"]["ms"] / tm["h2d"]["count"] * 1e-3
-                t_out = tm["d2h"]["ms"] / tm["d2h"]["count"] * 1e-3
-                ks = st["kernels"][name]
-                t_comp = ks["device_ms"] / ks["launches"] * 1e-3
+                assert len(tm["h2d_us"]) == len(tm["d2h_us"]) == PROFILE_WARM + PROFILE_REPS, tm
+                t_in = statistics.median(tm["h2d_us"][PROFILE_WARM:]) * 1e-6
+                t_out = statistics.median(tm["d2h_us"][PROFILE_WARM:]) * 1e-6
+                t_comp = statistics.median(tm["launch_us"][PROFILE_WARM:]) * 1e-6
                 for N in NS_LIST:
                     G.gvm_stats_reset()
                     st = _run(ns, kid, n, N, reps)
