@@ -610,13 +610,15 @@ def main(argv=None):
     roof["launches_per_step"] = round(per_step_launches, 3)
     roof["algorithmic_bytes"] = round(ks["work_bytes"] / launches)
     roof["algorithmic_flop"] = round(ks["work_flop"] / launches)
+    # the kernel's work per resident step over the whole step (manager round
+    # trip included); with several launches of the kernel per step, which
+    # run concurrently on the two compute streams, each launch's own FLOP
+    # over its duration understates the pair
+    roof["step_achieved"] = round((flop_total if main_kernel == G.GVM_K_SGEMM else bytes_total)
+                                  / (res_elapsed / max(a.resident_steps, 1)) /
+                                  (1e12 if main_kernel == G.GVM_K_SGEMM else 1e9), 3)
     if per_step_launches > 1.0:
-        # several launches of the kernel per step run concurrently on the two
-        # compute streams: each launch's own FLOP / duration shares the device
         roof["note"] = "launches of one step overlap; step_achieved is the kernel's work per resident step"
-        roof["step_achieved"] = round((flop_total if main_kernel == G.GVM_K_SGEMM else bytes_total)
-                                      / (res_elapsed / max(a.resident_steps, 1)) /
-                                      (1e12 if main_kernel == G.GVM_K_SGEMM else 1e9), 3)
 
     extra = {}
     if mixed:

@@ -496,9 +496,20 @@ int gemm_config_for(uint64_t n) {
     const int c = atoi(env);
     if (c >= 0 && c < kNumGemmConfigs) return c;
   }
+  int c = static_cast<int>(kTileTable[sizeof(kTileTable) / sizeof(kTileTable[0]) - 1][1]);
   for (const auto& row : kTileTable)
-    if (n <= row[0]) return static_cast<int>(row[1]);
-  return kTileTable[sizeof(kTileTable) / sizeof(kTileTable[0]) - 1][1];
+    if (n <= row[0]) {
+      c = static_cast<int>(row[1]);
+      break;
+    }
+  // tuning only: GVM_SGEMM_BK32_AS=<index> runs the table's k-depth-32 rows
+  // with that configuration instead (all SGEMMs of a mix then share a class)
+  static const int bk32_as = [] {
+    const char* e = getenv("GVM_SGEMM_BK32_AS");
+    return e ? atoi(e) : -1;
+  }();
+  if (bk32_as >= 0 && bk32_as < kNumGemmConfigs && kGemmConfigs[c].bk == 32) return bk32_as;
+  return c;
 }
 void finalize_gemm_group(GemmGroup& g, int config_idx) {
   const GemmConfig& c = kGemmConfigs[config_idx];
