@@ -79,7 +79,7 @@ EP_ISSUE_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
 # sources they were taken on (sha256 over `sources` in csrc/, in order;
 # profiles/sgemm_grouped_8x1024.md, profiles/blackscholes_grouped_16x4M.md,
 # profiles/vecadd_grouped_16x16M.md).
-SGEMM_SOURCES = ("sgemm.hip", "group_device.hpp", "kernels.hpp", "gemm_tiles.inc")
+SGEMM_SOURCES = ("sgemm.hip", "group_device.hpp", "kernels.hpp", "gemm_tiles.inc", "gemm_balance.hpp")
 STREAM_SOURCES = ("stream_kernels.hip", "group_device.hpp", "kernels.hpp")
 MEASURED_TRAFFIC = {
     "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "452827a72b9d2496626dc6a41bb430ee412892a55e6c23e19a35f4b924dc6957",

@@ -66,15 +66,17 @@ struct Batch {
 // Tile configuration of a BK class of SGEMM requests, sorted by size from
 // the largest down.
 //  * One size: the table's configuration of that size.
-//  * Mixed sizes of BK 16: 64x128x16 tiles with row-major B and a two-deep
-//    fetch (configuration 17), the smallest tiles that still run near full
-//    rate.  Its pipelined sibling (25) needs more registers, holds fewer
-//    workgroups per CU and ran the mixed launch 4 % slower.  They balance the short and the long tiles of a mix over the
+//  * Mixed sizes of BK 16: 64x128x16 tiles with row-major B, a two-deep
+//    fetch and registers held to four waves per SIMD (configuration 29),
+//    the smallest tiles that still run near full rate.  The same tile at
+//    three waves per SIMD (17) ran the 32-rank uneven launch 3.5 % slower
+//    (671-674 against 647-650 us), its pipelined sibling (25) slower again.
+//    Small tiles balance the short and the long tiles of a mix over the
 //    CUs, where 128x128 or larger tiles leave CUs idle at the end.
 //  * Mixed sizes of another BK: the table's configuration of the median size.
 // Every choice has the class's BK.  Tuning override, for mixed classes:
 // GVM_SGEMM_CLASS_CONFIG=<index>, when the index has the class's BK.
-constexpr int kMixConfig = 17;
+constexpr int kMixConfig = 29;
 
 int gemm_class_config(const std::vector<Job*>& v) {
   const int c = gemm_config_for(v[v.size() / 2]->req.n);

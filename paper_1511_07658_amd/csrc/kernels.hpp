@@ -64,12 +64,14 @@ struct GemmGroup {
   uint32_t count;
   uint32_t total_units;
   GemmDesc d[kMaxGroup];
-  // Balanced launch (mixed sizes, one workgroup per tile): XCD x computes the
-  // units [xcd_begin[x], xcd_begin[x + 1]), a contiguous run whose k-steps
-  // add up to an eighth of the launch's.  Filled by finalize_gemm_group.
-  uint32_t xcd_begin[kGroupXcds + 1];
+  // Balanced launch (mixed sizes, one workgroup per tile): the units are cut
+  // into 16 slices of equal k-step work, slice s = [cut[s], cut[s + 1]), and
+  // each XCD takes two of them (csrc/gemm_balance.hpp): balanced = 1 two
+  // neighbouring slices, balanced = 2 one from each end.  Filled by
+  // finalize_gemm_group; set by the launcher.
+  uint32_t cut[2 * kGroupXcds + 1];
   uint32_t balanced;
-  uint32_t pad;
+  uint32_t pad[2];
 };
 
 struct EpDesc {

@@ -56,12 +56,17 @@ namespace {
 // Balanced grid (mixed sizes, one workgroup per tile): the blocks are cut by
 // work instead of by count.  The requests come largest first, so equal
 // counts would give the first XCD the longest tiles and the last one the
-// shortest; each XCD instead takes a contiguous run of units whose k-steps
-// add up to an eighth of the launch's, and the grid holds as many
-// workgroups per XCD as the longest run has units (the rest exit at once).
+// shortest.  The units are cut into 16 contiguous slices of equal k-step
+// work instead, and XCD x takes slice x from the long end and then slice
+// 15 - x from the short end, so every XCD ends on short tiles; the grid
+// holds as many workgroups per XCD as the longest pair has units (the rest
+// exit at once).
 
-template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH, bool VEC, bool PIPE>
-__global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) {
+// MINW: the waves per SIMD the register allocation must leave room for (1:
+// no constraint); the compiler then keeps VGPRs + AGPRs within 512 / MINW.
+template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH, bool VEC, bool PIPE, int MINW>
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(MINW))) void sgemm_group_kernel(
+    GemmGroup g) {
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 32, FN = TN / 32;
@@ -95,10 +100,17 @@ __global__ __launch_bounds__(WM * WN * 64) void sgemm_group_kernel(GemmGroup g) 
 
   uint32_t u0 = v, uend = U, ustep = G;
   if (g.balanced) {
-    const uint32_t x = blockIdx.x % kXcds;
-    u0 = g.xcd_begin[x] + blockIdx.x / kXcds;
-    uend = g.xcd_begin[x + 1];
-    ustep = G / kXcds;
+    // the j-th workgroup of XCD x takes the j-th unit of the XCD's two
+    // slices; the grid holds as many per XCD as the longest pair has units
+    // (the slices of xcd_slices(): 2x and 2x + 1, or x and 15 - x when paired)
+    const int x = static_cast<int>(blockIdx.x % kXcds);
+    const int s0 = g.balanced == 2 ? x : 2 * x;
+    const int s1 = g.balanced == 2 ? kGemmSlices - 1 - x : 2 * x + 1;
+    const uint32_t j = blockIdx.x / kXcds;
+    const uint32_t len0 = g.cut[s0 + 1] - g.cut[s0];
+    u0 = j < len0 ? g.cut[s0] + j : g.cut[s1] + (j - len0);
+    uend = j < len0 ? g.cut[s0 + 1] : g.cut[s1 + 1];
+    ustep = uend;  // one unit per workgroup
   }
   for (uint32_t u = u0; u < uend; u += ustep) {
     const int q = find_request(g, u);
@@ -461,6 +473,8 @@ const GemmConfig kGemmConfigs[] = {
     // larger tiles for large n, two ahead
     {27, 128, 256, 32, 2, 4, false},
     {28, 256, 256, 16, 4, 2, false},
+    // two ahead with registers held to four waves per SIMD (VGPRs + AGPRs <= 128)
+    {29, 64, 128, 16, 2, 2, false},
 };
 constexpr int kNumGemmConfigs = sizeof(kGemmConfigs) / sizeof(kGemmConfigs[0]);
 
@@ -468,19 +482,23 @@ int g_forced_config = -1;
 
 #include "gemm_tiles.inc"   // kTileTable: (n_max, config index) rows written by the tuner
 
-template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH = 1, bool PIPE = false>
+template <int BM, int BN, int BK, int WM, int WN, bool BT, int DEPTH = 1, bool PIPE = false, int MINW = 1>
 hipError_t launch_cfg(const GemmGroup& g, bool vec, hipStream_t s, int grid_cap) {
   constexpr int NT = WM * WN * 64;
   int cap = grid_cap > 0 ? grid_cap : 256 * 2;
   int grid = static_cast<int>(std::min<uint32_t>(g.total_units, static_cast<uint32_t>(cap)));
   if (grid > kXcds) grid -= grid % kXcds;  // whole rounds over the 8 XCDs
-  if (g.balanced) {  // one workgroup per unit of the longest XCD run
+  if (g.balanced) {  // one workgroup per unit of the longest XCD pair of slices
     uint32_t most = 0;
-    for (int x = 0; x < kXcds; ++x) most = std::max(most, g.xcd_begin[x + 1] - g.xcd_begin[x]);
+    for (int x = 0; x < kXcds; ++x) {
+      int s0, s1;
+      xcd_slices(x, g.balanced == 2, &s0, &s1);
+      most = std::max(most, (g.cut[s0 + 1] - g.cut[s0]) + (g.cut[s1 + 1] - g.cut[s1]));
+    }
     grid = static_cast<int>(most) * kXcds;
   }
-  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, true, PIPE>, grid, NT, s, g)
-             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, false, PIPE>, grid, NT, s, g);
+  return vec ? launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, true, PIPE, MINW>, grid, NT, s, g)
+             : launch_group(sgemm_group_kernel<BM, BN, BK, WM, WN, BT, DEPTH, false, PIPE, MINW>, grid, NT, s, g);
 }
 
 }  // namespace
@@ -528,14 +546,21 @@ void finalize_gemm_group(GemmGroup& g, int config_idx) {
     units[i] = g.d[i].units;
     ksteps[i] = (g.d[i].n + c.bk - 1) / c.bk;
   }
-  balance_xcd_runs(g.count, units, ksteps, g.xcd_begin);
+  balance_slices(g.count, units, ksteps, g.cut);
   g.balanced = 0;
 }
 hipError_t launch_sgemm_group(const GemmGroup& g_in, int config_idx, hipStream_t s, int grid_cap) {
   GemmGroup g = g_in;
   g.balanced = 0;
   if (grid_cap > 0 && static_cast<uint32_t>(grid_cap) >= g.total_units && g.count > 1) {
-    for (uint32_t i = 1; i < g.count; ++i) g.balanced |= g.d[i].n != g.d[0].n;
+    bool mixed = false;
+    for (uint32_t i = 1; i < g.count; ++i) mixed |= g.d[i].n != g.d[0].n;
+    // GVM_SGEMM_XCD_PAIRED=0 keeps each XCD on one contiguous run (tuning)
+    static const bool paired = [] {
+      const char* e = getenv("GVM_SGEMM_XCD_PAIRED");
+      return !(e && e[0] == '0');
+    }();
+    if (mixed) g.balanced = paired ? 2 : 1;
   }
   bool vec = true;
   for (uint32_t i = 0; i < g.count; ++i)
@@ -572,6 +597,7 @@ hipError_t launch_sgemm_group(const GemmGroup& g_in, int config_idx, hipStream_t
     case 26: return launch_cfg<256, 128, 16, 4, 2, false, 1, true>(g, vec, s, grid_cap);
     case 27: return launch_cfg<128, 256, 32, 2, 4, false, 2>(g, vec, s, grid_cap);
     case 28: return launch_cfg<256, 256, 16, 4, 2, false, 2>(g, vec, s, grid_cap);
+    case 29: return launch_cfg<64, 128, 16, 2, 2, false, 2, false, 4>(g, vec, s, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }

@@ -31,16 +31,17 @@ from . import workloads as wl
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "gemm_tiles.inc")
-NUM_CONFIGS = 29
+NUM_CONFIGS = 30
 # "T": B staged k-contiguous (transposed) in LDS; "R": B row-major in LDS;
 # "2", "3": k-tiles fetched two or three ahead instead of one; "P": the next
-# k-tile's fragments read from LDS during the current MFMAs
+# k-tile's fragments read from LDS during the current MFMAs; "W4": registers
+# held to four waves per SIMD
 CONFIG_NAMES = ["64x64x16T", "128x64x16T", "128x128x16T", "128x128x32T", "256x128x16T", "128x256x16T",
                 "256x128x32T", "64x128x16T", "128x128x16R", "256x128x16R", "128x256x16R", "256x128x32R",
                 "128x128x32R", "64x128x16R", "256x128x16R2", "128x128x16R2", "256x128x32R2", "64x128x16R2",
                 "128x128x32R2", "256x128x16R3", "256x128x32R3", "128x128x16R3", "256x128x16R2P", "128x128x32R2P",
                 "128x128x16R2P", "64x128x16R2P", "256x128x16RP", "128x256x32R2",
-                "256x256x16R2"]
+                "256x256x16R2", "64x128x16R2W4"]
 
 
 def _time_size(ns, n, group, reps, configs):

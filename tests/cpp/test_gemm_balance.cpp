@@ -1,8 +1,9 @@
 // CPU check of the SGEMM launch's split over XCDs (csrc/gemm_balance.hpp):
-// for random groups of requests, the runs cover every unit once, each run's
-// work is within one tile of an eighth of the total, and the kernel's index
-// walk over the balanced grid (XCD x = workgroup % 8, one workgroup per unit
-// of the longest run) visits every unit exactly once and none beyond.
+// for random groups of requests, the 16 slices cover every unit once, each
+// slice's work is within one tile of a sixteenth of the total, and the
+// kernel's index walk over the balanced grid (XCD x = workgroup % 8, its two
+// slices from xcd_slices, one workgroup per unit of the longest pair) visits
+// every unit exactly once and none beyond, for both slice pairings.
 #include <cstdio>
 #include <random>
 #include <vector>
@@ -21,8 +22,8 @@ static int failures = 0;
 
 static void check_group(const std::vector<uint32_t>& units, const std::vector<uint32_t>& ksteps) {
   const uint32_t count = static_cast<uint32_t>(units.size());
-  uint32_t begin[9];
-  gvm::balance_xcd_runs(count, units.data(), ksteps.data(), begin);
+  uint32_t cut[gvm::kGemmSlices + 1];
+  gvm::balance_slices(count, units.data(), ksteps.data(), cut);
   std::vector<uint64_t> work_at;  // work of the units before unit u
   uint64_t total = 0, wmax = 0;
   for (uint32_t i = 0; i < count; ++i)
@@ -33,27 +34,47 @@ static void check_group(const std::vector<uint32_t>& units, const std::vector<ui
     }
   const uint32_t all = static_cast<uint32_t>(work_at.size());
   work_at.push_back(total);
-  CHECK(begin[0] == 0 && begin[8] == all, "ends %u %u of %u", begin[0], begin[8], all);
-  uint32_t most = 0;
-  for (int x = 0; x < 8; ++x) {
-    CHECK(begin[x] <= begin[x + 1], "run %d decreasing", x);
-    const uint64_t w = work_at[begin[x + 1]] - work_at[begin[x]];
-    const double share = total / 8.0;
-    CHECK(w <= share + wmax + 1 && w + wmax + 1 >= share, "run %d work %llu, eighth %.1f, tile %llu", x,
+  CHECK(cut[0] == 0 && cut[gvm::kGemmSlices] == all, "ends %u %u of %u", cut[0], cut[gvm::kGemmSlices], all);
+  for (int s = 0; s < gvm::kGemmSlices; ++s) {
+    CHECK(cut[s] <= cut[s + 1], "slice %d decreasing", s);
+    const uint64_t w = work_at[cut[s + 1]] - work_at[cut[s]];
+    const double share = total / double(gvm::kGemmSlices);
+    CHECK(w <= share + wmax + 1 && w + wmax + 1 >= share, "slice %d work %llu, share %.1f, tile %llu", s,
           (unsigned long long)w, share, (unsigned long long)wmax);
-    most = std::max(most, begin[x + 1] - begin[x]);
   }
-  // the kernel's walk: grid = 8 * most, u = begin[x] + j, step most
-  std::vector<int> seen(all, 0);
-  const uint32_t grid = 8 * most;
-  for (uint32_t w = 0; w < grid; ++w) {
-    const uint32_t x = w % 8;
-    for (uint32_t u = begin[x] + w / 8; u < begin[x + 1]; u += grid / 8) {
-      CHECK(u < all, "unit %u beyond %u", u, all);
-      if (u < all) ++seen[u];
+  for (int paired = 0; paired < 2; ++paired) {
+    // every slice belongs to exactly one XCD
+    std::vector<int> owner(gvm::kGemmSlices, 0);
+    uint32_t most = 0;
+    for (int x = 0; x < 8; ++x) {
+      int s0, s1;
+      gvm::xcd_slices(x, paired, &s0, &s1);
+      ++owner[s0];
+      ++owner[s1];
+      most = std::max(most, (cut[s0 + 1] - cut[s0]) + (cut[s1 + 1] - cut[s1]));
     }
+    for (int s = 0; s < gvm::kGemmSlices; ++s) CHECK(owner[s] == 1, "slice %d owned %d times", s, owner[s]);
+    // the kernel's walk: grid = 8 * most, one unit per workgroup
+    std::vector<int> seen(all, 0);
+    const uint32_t grid = 8 * most;
+    for (uint32_t w = 0; w < grid; ++w) {
+      const int x = static_cast<int>(w % 8);
+      const int s0 = paired ? x : 2 * x;
+      const int s1 = paired ? gvm::kGemmSlices - 1 - x : 2 * x + 1;
+      int h0, h1;
+      gvm::xcd_slices(x, paired, &h0, &h1);
+      CHECK(h0 == s0 && h1 == s1, "kernel slices differ from xcd_slices at x %d", x);
+      const uint32_t j = w / 8;
+      const uint32_t len0 = cut[s0 + 1] - cut[s0];
+      const uint32_t u0 = j < len0 ? cut[s0] + j : cut[s1] + (j - len0);
+      const uint32_t uend = j < len0 ? cut[s0 + 1] : cut[s1 + 1];
+      for (uint32_t u = u0; u < uend; u += uend) {
+        CHECK(u < all, "unit %u beyond %u", u, all);
+        if (u < all) ++seen[u];
+      }
+    }
+    for (uint32_t u = 0; u < all; ++u) CHECK(seen[u] == 1, "paired %d: unit %u visited %d times", paired, u, seen[u]);
   }
-  for (uint32_t u = 0; u < all; ++u) CHECK(seen[u] == 1, "unit %u visited %d times", u, seen[u]);
 }
 
 int main() {

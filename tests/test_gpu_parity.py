@@ -228,8 +228,9 @@ def test_same_bk_tile_configurations_are_bit_identical():
 
 def test_sgemm_size_mix_matches_plain(ns_name):
     # 12 ranks of SGEMM sizes that the tile table maps to different
-    # configurations of both BK classes, in one batch: each result equals
-    # the plain path's (its size's own configuration) byte for byte
+    # configurations, in one batch (one launch of the mixed class's tiles):
+    # each result equals the plain path's (its size's own configuration)
+    # byte for byte
     sizes = [160, 384, 600, 704, 768, 832, 896, 960, 1024, 1216, 1664, 1792]
     nr = len(sizes)
     jobs = {r: [(3, 53, sizes[r], 0, False)] for r in range(nr)}
