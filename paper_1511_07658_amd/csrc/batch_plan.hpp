@@ -49,7 +49,8 @@ struct PlanJob {
 };
 
 // One grouped launch: requests of one kernel id and class, at most
-// kPlanMaxGroup of them, SGEMM sizes from the largest down.
+// kPlanMaxGroup of them, SGEMM sizes from the largest down.  The launches
+// come longest first (estimated device time), dealt round robin.
 struct PlanGroup {
   int kernel_id;
   int cls;
