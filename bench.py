@@ -77,16 +77,18 @@ EP_ISSUE_GPAIRS = 256 * 4 * 2.4e9 / EP_SIMD_CYCLES_PER_PAIR / 1e9
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # plain 1 GiB copy (fetch x2.000, write x1.000); valid only for the kernel
 # sources they were taken on (sha256 over `sources` in csrc/, in order;
-# profiles/sgemm_grouped_8x1024.md, profiles/blackscholes_grouped_16x4M.md,
-# profiles/vecadd_grouped_16x16M.md).
+# profiles/mixed32_uneven.md, profiles/sgemm_grouped_8x1024.md,
+# profiles/blackscholes_grouped_16x4M.md, profiles/vecadd_grouped_16x16M.md).
 SGEMM_SOURCES = ("sgemm.hip", "group_device.hpp", "kernels.hpp", "gemm_tiles.inc", "gemm_balance.hpp")
 STREAM_SOURCES = ("stream_kernels.hip", "group_device.hpp", "kernels.hpp")
 MEASURED_TRAFFIC = {
-    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "452827a72b9d2496626dc6a41bb430ee412892a55e6c23e19a35f4b924dc6957",
-               "fetch_kib": 32854.9, "fetch_factor": 2.000, "write_kib": 32768.0, "write_factor": 1.000},
-    "bs16": {"sources": STREAM_SOURCES, "kernels_sha256": "b6e37850a81652cdfbfcb6ef5733e38694e16acd5b1e2a7223c8bda01e96637c",
-             "fetch_kib": 393326.6, "fetch_factor": 2.000, "write_kib": 524311.7, "write_factor": 1.000},
-    "vecadd16": {"sources": STREAM_SOURCES, "kernels_sha256": "b6e37850a81652cdfbfcb6ef5733e38694e16acd5b1e2a7223c8bda01e96637c",
+    "mixed32": {"sources": SGEMM_SOURCES, "kernels_sha256": "1c2dcb24a03b83f71fbe572b865de061bd839007b888955a087dcf6850269bf7",
+                "fetch_kib": 495718.8, "fetch_factor": 2.000, "write_kib": 85152.0, "write_factor": 1.000},
+    "sgemm8": {"sources": SGEMM_SOURCES, "kernels_sha256": "1c2dcb24a03b83f71fbe572b865de061bd839007b888955a087dcf6850269bf7",
+               "fetch_kib": 32835.9, "fetch_factor": 2.000, "write_kib": 32768.0, "write_factor": 1.000},
+    "bs16": {"sources": STREAM_SOURCES, "kernels_sha256": "8fe15074feb50f84a1329d139469e3f76e1f9b34fe8eeb59000d99b7b62abbab",
+             "fetch_kib": 393326.6, "fetch_factor": 2.000, "write_kib": 524300.7, "write_factor": 1.000},
+    "vecadd16": {"sources": STREAM_SOURCES, "kernels_sha256": "8fe15074feb50f84a1329d139469e3f76e1f9b34fe8eeb59000d99b7b62abbab",
                  "fetch_kib": 1048597.1, "fetch_factor": 2.000, "write_kib": 1048576.0, "write_factor": 1.000},
 }
 
