@@ -2,7 +2,6 @@
 
 #include <algorithm>
 #include <map>
-#include <utility>
 
 #include "gvm.h"
 
@@ -25,22 +24,19 @@ double job_us(const PlanJob& j) {
 }  // namespace
 
 std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstreams) {
-  // One grouped launch per kernel id; SGEMM requests are grouped by the k
-  // depth BK of their size's tile configuration (a C element's k order
-  // depends on BK alone, so a class may share one launch and every request
-  // still gets the bits it gets alone).
-  std::map<std::pair<int, int>, std::vector<int>> classes;
-  for (size_t i = 0; i < jobs.size(); ++i) classes[{jobs[i].kernel_id, jobs[i].cls}].push_back(static_cast<int>(i));
+  // One grouped launch per kernel id (an SGEMM request gets the same bits
+  // from every tile configuration, so any sizes may share one launch).
+  std::map<int, std::vector<int>> classes;
+  for (size_t i = 0; i < jobs.size(); ++i) classes[jobs[i].kernel_id].push_back(static_cast<int>(i));
   std::vector<PlanGroup> out;
   for (auto& kv : classes) {
     std::vector<int>& v = kv.second;
-    if (kv.first.first == GVM_K_SGEMM) {  // largest first, so the longest tiles start first
+    if (kv.first == GVM_K_SGEMM) {  // largest first, so the longest tiles start first
       std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return jobs[x].n > jobs[y].n; });
     }
     for (size_t base = 0; base < v.size(); base += kPlanMaxGroup) {
       PlanGroup g;
-      g.kernel_id = kv.first.first;
-      g.cls = kv.first.second;
+      g.kernel_id = kv.first;
       const size_t end = std::min(v.size(), base + kPlanMaxGroup);
       g.jobs.assign(v.begin() + static_cast<long>(base), v.begin() + static_cast<long>(end));
       out.push_back(std::move(g));

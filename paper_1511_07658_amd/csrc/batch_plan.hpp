@@ -39,7 +39,6 @@ struct PlanOp {
 // What the schedule needs to know of one request.
 struct PlanJob {
   int kernel_id;
-  int cls;          // class within the kernel id: the SGEMM k depth BK, else 0
   uint64_t n;
   bool copy_in;
   bool copy_out;
@@ -48,12 +47,11 @@ struct PlanJob {
   bool out_pieces;  // output leaves piecewise on the D2H FIFO, an event after each piece
 };
 
-// One grouped launch: requests of one kernel id and class, at most
-// kPlanMaxGroup of them, SGEMM sizes from the largest down.  The launches
-// come longest first (estimated device time), dealt round robin.
+// One grouped launch: requests of one kernel id, at most kPlanMaxGroup of
+// them, SGEMM sizes from the largest down.  The launches come longest first
+// (estimated device time), dealt round robin.
 struct PlanGroup {
   int kernel_id;
-  int cls;
   int stream;               // index into the stream list the groups are dealt to
   std::vector<int> jobs;    // indices into the job list, in launch order
 };
@@ -74,7 +72,7 @@ struct BatchPlan {
 };
 
 // The grouped launches of `jobs` dealt round robin over `nstreams` streams
-// (one group per kernel id and class, split every kPlanMaxGroup requests).
+// (one group per kernel id, split every kPlanMaxGroup requests).
 std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstreams);
 
 // Grouped policy: copy-ins (local ones on C0 ahead of its kernels, the rest

@@ -63,31 +63,27 @@ struct Batch {
   size_t remaining = 0;
 };
 
-// Tile configuration of a BK class of SGEMM requests, sorted by size from
-// the largest down.
+// Tile configuration of one grouped SGEMM launch, its requests sorted by
+// size from the largest down (every configuration gives the same bits, so
+// the choice is about speed alone).
 //  * One size: the table's configuration of that size.
-//  * Mixed sizes of BK 16: 64x128x16 tiles with row-major B, a two-deep
-//    fetch and registers held to four waves per SIMD (configuration 29),
-//    the smallest tiles that still run near full rate.  The same tile at
-//    three waves per SIMD (17) ran the 32-rank uneven launch 3.5 % slower
-//    (671-674 against 647-650 us), its pipelined sibling (25) slower again.
-//    Small tiles balance the short and the long tiles of a mix over the
-//    CUs, where 128x128 or larger tiles leave CUs idle at the end.
-//  * Mixed sizes of another BK: the table's configuration of the median size.
-// Every choice has the class's BK.  Tuning override, for mixed classes:
-// GVM_SGEMM_CLASS_CONFIG=<index>, when the index has the class's BK.
+//  * Mixed sizes: 64x128x16 tiles with row-major B, a two-deep fetch and
+//    registers held to four waves per SIMD (configuration 29), the smallest
+//    tiles that still run near full rate.  The same tile at three waves per
+//    SIMD (17) ran the 32-rank uneven launch 3.5 % slower (671-674 against
+//    647-650 us), its pipelined sibling (25) slower again.  Small tiles
+//    balance the short and the long tiles of a mix over the CUs, where
+//    128x128 or larger tiles leave CUs idle at the end.
+// Tuning override for mixed sizes: GVM_SGEMM_MIX_CONFIG=<index>.
 constexpr int kMixConfig = 29;
 
-int gemm_class_config(const std::vector<Job*>& v) {
-  const int c = gemm_config_for(v[v.size() / 2]->req.n);
-  if (v.front()->req.n == v.back()->req.n) return c;
+int gemm_group_config(const std::vector<Job*>& v) {
+  if (v.front()->req.n == v.back()->req.n) return gemm_config_for(v.front()->req.n);
   static const int env = [] {
-    const char* e = getenv("GVM_SGEMM_CLASS_CONFIG");
+    const char* e = getenv("GVM_SGEMM_MIX_CONFIG");
     return e ? atoi(e) : -1;
   }();
-  const int bk = gemm_config(c).bk;
-  if (env >= 0 && env < gemm_config_count() && gemm_config(env).bk == bk) return env;
-  return gemm_config(kMixConfig).bk == bk ? kMixConfig : c;
+  return env >= 0 && env < gemm_config_count() ? env : kMixConfig;
 }
 
 // Grid cap of an SGEMM launch over mixed sizes: one workgroup per tile, so
@@ -636,13 +632,12 @@ class HipDevice final : public Device {
   // The plan's view of a job.
   static PlanJob plan_job(const Job* j) {
     const int k = static_cast<int>(j->req.kernel_id);
-    return PlanJob{k, k == GVM_K_SGEMM ? gemm_config(gemm_config_for(j->req.n)).bk : 0, j->req.n,
-                   j->copy_in, j->copy_out, j->local, j->pieces && j->copy_in, j->out_pieces > 0};
+    return PlanJob{k, j->req.n, j->copy_in, j->copy_out, j->local, j->pieces && j->copy_in, j->out_pieces > 0};
   }
 
-  // One grouped launch per kernel id (per k depth class for SGEMM), at most
-  // kMaxGroup requests each, dealt round robin to `streams` (PS-1 and PS-2
-  // call it with one job and its own stream).  Each launch is timed.
+  // One grouped launch per kernel id, at most kMaxGroup requests each, dealt
+  // round robin to `streams` (PS-1 and PS-2 call it with one job and its own
+  // stream).  Each launch is timed.
   int enqueue_kernels(const std::vector<Job*>& jobs, const std::vector<hipStream_t>& streams, Batch* b) {
     std::vector<PlanJob> pj;
     for (const Job* j : jobs) pj.push_back(plan_job(j));
@@ -722,7 +717,7 @@ class HipDevice final : public Device {
         gg.d[i].C = reinterpret_cast<float*>(v[i]->slot + slot_out_offset(v[i]->lay));
         gg.d[i].n = static_cast<uint32_t>(n);
       }
-      const int cfgi = gemm_class_config(v);
+      const int cfgi = gemm_group_config(v);
       finalize_gemm_group(gg, cfgi);
       const bool mixed = v.front()->req.n != v.back()->req.n;
       e = launch_sgemm_group(gg, cfgi, s, mixed ? gemm_mix_grid() : 0);

@@ -22,17 +22,26 @@ namespace {
 // (BM/WM) x (BN/WN) block of C as (BM/WM/32) x (BN/WN/32) accumulators of
 // one 32x32 MFMA each.  v_mfma_f32_32x32x2_f32 multiplies a 32x2 slice of A
 // by a 2x32 slice of B; lane l supplies A[l%32][k(l)] and B[k(l)][l%32] and
-// lane group g = l/32 selects which of the two k values it carries.  Within
-// a BK tile, MFMA step s takes k = s for g = 0 and k = BK/2 + s for g = 1.
+// lane group g = l/32 selects which of the two k values it carries.  Each
+// run of four k (4q .. 4q + 3) feeds two MFMA steps, with the k pairs
+// (4q, 4q + 2) and (4q + 1, 4q + 3), g = 0 the smaller k: every C element
+// sums the pairs (0, 2), (1, 3), (4, 6), (5, 7), ... in that order into one
+// accumulator whatever the tile configuration, so all configurations give
+// the same bits and requests of any sizes may share one launch.
 //
-// A sits in LDS as As[m][k] (rows padded by 4 floats), so a lane's A
-// fragments of a whole tile are contiguous and read with 16-byte LDS reads.
-// B has two stagings, chosen per tile configuration by the tuner:
-//  * BT: Bs[n][k], B transposed on the way in (each thread fetches four
+// In LDS the k index of a tile is stored permuted, so that the KH = BK/2
+// values a lane multiplies in the KH steps of a tile sit side by side: k =
+// 4q + 2h + t (h, t in {0, 1}) goes to k' = h * KH + 2q + t.  A sits as
+// As[m][k'] (rows padded by 4 floats), and a lane's A fragments of a whole
+// tile are read with 16-byte LDS reads; a fetched float4 of A (four
+// consecutive k) is written as its two halves.  B has two stagings, chosen
+// per tile configuration by the tuner:
+//  * BT: Bs[n][k'], B transposed on the way in (each thread fetches four
 //    k-rows of one column, coalesced along n); B fragments are then 16-byte
 //    reads like A's;
-//  * row-major: Bs[k][n] from float4 loads along n; B fragments are 4-byte
-//    reads (one per MFMA step and column block).
+//  * row-major: Bs[k'][n] from float4 loads along n (k-row k goes to row
+//    k'); B fragments are 4-byte reads (one per MFMA step and column block),
+//    the two lane groups on rows BK/2 apart.
 // All fragments of a k-step are read before its MFMAs.  Double buffering:
 // the next tile is fetched into registers at the start of a k-step and
 // written to the other LDS buffer half-way through the MFMAs, so one barrier
@@ -186,23 +195,30 @@ __global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(MI
         }
       }
     };
+    // k-permuted LDS layout: k = 4q, 4q + 1 go to k' = 2q, 2q + 1 and
+    // k = 4q + 2, 4q + 3 to KH + 2q, KH + 2q + 1
     auto store_tile = [&](int buf, auto slot_tag) {
       constexpr int SL = decltype(slot_tag)::value;
 #pragma unroll
       for (int i = 0; i < A4; ++i) {
         const int f = tid + i * NT;
-        const int r = f / (BK / 4), c = (f % (BK / 4)) * 4;
-        *reinterpret_cast<f32x4*>(&As[buf][r * AST + c]) = ra[SL][i];
+        const int r = f / (BK / 4), q = f % (BK / 4);
+        const f32x4 x = ra[SL][i];
+        *reinterpret_cast<f32x2*>(&As[buf][r * AST + 2 * q]) = x.xy;
+        *reinterpret_cast<f32x2*>(&As[buf][r * AST + KH + 2 * q]) = x.zw;
       }
 #pragma unroll
       for (int i = 0; i < B4; ++i) {
         const int f = tid + i * NT;
         if (BT) {
           const int c = f % BN, kq = f / BN;
-          *reinterpret_cast<f32x4*>(&Bs[buf][c * BST + 4 * kq]) = rb[SL][i];
+          const f32x4 x = rb[SL][i];
+          *reinterpret_cast<f32x2*>(&Bs[buf][c * BST + 2 * kq]) = x.xy;
+          *reinterpret_cast<f32x2*>(&Bs[buf][c * BST + KH + 2 * kq]) = x.zw;
         } else {
           const int r = f / (BN / 4), c = (f % (BN / 4)) * 4;
-          *reinterpret_cast<f32x4*>(&Bs[buf][r * BST + c]) = rb[SL][i];
+          const int rp = ((r >> 1) & 1) * KH + ((r >> 2) << 1) + (r & 1);
+          *reinterpret_cast<f32x4*>(&Bs[buf][rp * BST + c]) = rb[SL][i];
         }
       }
     };
@@ -520,13 +536,6 @@ int gemm_config_for(uint64_t n) {
       c = static_cast<int>(row[1]);
       break;
     }
-  // tuning only: GVM_SGEMM_BK32_AS=<index> runs the table's k-depth-32 rows
-  // with that configuration instead (all SGEMMs of a mix then share a class)
-  static const int bk32_as = [] {
-    const char* e = getenv("GVM_SGEMM_BK32_AS");
-    return e ? atoi(e) : -1;
-  }();
-  if (bk32_as >= 0 && bk32_as < kNumGemmConfigs && kGemmConfigs[c].bk == 32) return bk32_as;
   return c;
 }
 void finalize_gemm_group(GemmGroup& g, int config_idx) {

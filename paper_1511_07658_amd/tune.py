@@ -10,7 +10,7 @@ so the tile choice stays a pure function of n: a rank's SGEMM result does
 not depend on what it is grouped with.
 
     python -m paper_1511_07658_amd.tune [--sizes 256,512,...] [--group 8] [--reps 10] [--write] [--json out.json]
-    python -m paper_1511_07658_amd.tune --from-json out.json [--bk 16]    # table from a saved sweep
+    python -m paper_1511_07658_amd.tune --from-json out.json    # table from a saved sweep
 
 Timing needs the GPU; rebuild the library after writing the table.
 """
@@ -20,7 +20,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import re
 import sys
 import threading
 
@@ -121,29 +120,12 @@ def tune(sizes, group=8, reps=10, configs=None):
     return results
 
 
-def config_bk(c):
-    """k depth BK of tile configuration `c` (from its name BMxBNxBK...)."""
-    return int(re.match(r"(\d+)x(\d+)x(\d+)", CONFIG_NAMES[c]).group(3))
-
-
-def best_with_bk(entry, bk):
-    """Fastest configuration of one sweep entry among those of k depth `bk`
-    (None: any)."""
-    if bk is None:
-        return entry["best"]
-    us = {CONFIG_NAMES.index(name): t for name, t in entry["us"].items()}
-    cands = [c for c in us if config_bk(c) == bk]
-    return min(cands, key=lambda c: (round(us[c], 1), c))
-
-
-def write_table(results, path=TABLE, bk=None):
-    """The compiled-in table.  With `bk`, only configurations of that k depth
-    are candidates: every size then shares one accumulation order, and the
-    device runs any mix of sizes as one grouped launch (requests of one BK
-    give the same bits under any configuration of that BK)."""
+def write_table(results, path=TABLE):
+    """The compiled-in table (every configuration gives a request the same
+    bits, so the fastest one is taken)."""
     rows = []
     for n in sorted(results):
-        c = best_with_bk(results[n], bk)
+        c = results[n]["best"]
         if rows and rows[-1][1] == c:
             rows[-1][0] = n
         else:
@@ -152,8 +134,7 @@ def write_table(results, path=TABLE, bk=None):
     with open(path, "w") as f:
         f.write("// SGEMM tile table: rows of {largest n, tile configuration index},\n")
         f.write("// written by `python -m paper_1511_07658_amd.tune --write` on an MI355X\n")
-        f.write("// (grouped launches of identical-size requests, fastest mean device time"
-                + (f" among the BK = {bk} configurations).\n" if bk else ").\n"))
+        f.write("// (grouped launches of identical-size requests, fastest mean device time).\n")
         f.write("constexpr uint64_t kTileTable[][2] = {\n")
         for n, c in rows:
             f.write(f"    {{{n}u, {c}}},  // {CONFIG_NAMES[c]}\n")
@@ -168,15 +149,13 @@ def main(argv=None):
     ap.add_argument("--configs", default=None)
     ap.add_argument("--write", action="store_true")
     ap.add_argument("--json", default=None)
-    ap.add_argument("--bk", type=int, default=None,
-                    help="only configurations of this k depth go into the table (16: one class for every size)")
     ap.add_argument("--from-json", default=None,
                     help="write the table from a saved sweep (the --json output of a run on the GPU) without timing")
     a = ap.parse_args(argv)
     if a.from_json:
         with open(a.from_json) as f:
             saved = json.load(f)
-        write_table({int(n): r for n, r in saved.items()}, bk=a.bk)
+        write_table({int(n): r for n, r in saved.items()})
         print(f"wrote {TABLE} from {a.from_json}; rebuild the library", file=sys.stderr)
         return 0
     sizes = [int(s) for s in a.sizes.split(",")] if a.sizes else [64, 128, 192] + list(range(256, 2049, 64))
@@ -186,7 +165,7 @@ def main(argv=None):
         with open(a.json, "w") as f:
             json.dump(res, f, indent=1)
     if a.write:
-        write_table(res, bk=a.bk)
+        write_table(res)
         print(f"wrote {TABLE}; rebuild the library", file=sys.stderr)
     return 0
 

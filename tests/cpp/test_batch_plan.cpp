@@ -190,7 +190,7 @@ const char* check(const BatchPlan& p, const std::vector<PlanJob>& jobs, bool gra
     if (G.jobs.empty() || G.jobs.size() > static_cast<size_t>(kPlanMaxGroup)) return "group size out of range";
     for (size_t i = 0; i < G.jobs.size(); ++i) {
       const PlanJob& j = jobs[static_cast<size_t>(G.jobs[i])];
-      if (j.kernel_id != G.kernel_id || j.cls != G.cls) return "a group mixes kernels or classes";
+      if (j.kernel_id != G.kernel_id) return "a group mixes kernels";
       if (G.kernel_id == GVM_K_SGEMM && i > 0 && jobs[static_cast<size_t>(G.jobs[i - 1])].n < j.n)
         return "SGEMM group not largest first";
     }
@@ -251,8 +251,7 @@ PlanJob job(int k, uint64_t n, bool in, bool out, bool pieces = false) {
     default: in_b = 16; out_b = 96; break;
   }
   const bool local = (in ? in_b : 0) + (out ? out_b : 0) <= (1u << 20);
-  const int cls = k == GVM_K_SGEMM ? (n <= 768 ? 16 : (n % 256 == 0 ? 32 : 16)) : 0;
-  return PlanJob{k, cls, n, in, out, local, pieces && in && !local, pieces && out && !local};
+  return PlanJob{k, n, in, out, local, pieces && in && !local, pieces && out && !local};
 }
 
 int failures = 0;
@@ -386,12 +385,12 @@ int main() {
       printf("graph without the input wait detected: %s (%s)\n", err, why.c_str());
     }
   }
-  // one kernel kind only (one group, compute stream 1 idle), and 33 requests of one class (two groups)
+  // one kernel kind only (one group, compute stream 1 idle), and 33 requests of one kernel (two groups)
   expect_ok("single", {job(GVM_K_SGEMM, 1024, true, true)}, true);
   expect_ok("single", {job(GVM_K_SGEMM, 1024, true, true)}, false);
   std::vector<PlanJob> many(33, job(GVM_K_VECADD, 1 << 20, true, true));
-  expect_ok("33 of one class", many, true);
-  expect_ok("33 of one class", many, false);
+  expect_ok("33 of one kernel", many, true);
+  expect_ok("33 of one kernel", many, false);
   std::vector<PlanJob> resident(8, job(GVM_K_SGEMM, 1024, false, false));
   expect_ok("resident", resident, true);
   expect_ok("resident", resident, false);
