@@ -8,7 +8,6 @@ namespace gvm {
 constexpr int kThreads = 256;   // workgroup size of the streaming kernels
 constexpr int kXcds = kGroupXcds;  // MI355X: workgroup w is dispatched to XCD w % 8
 
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 

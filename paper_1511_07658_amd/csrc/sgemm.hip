@@ -23,19 +23,21 @@ namespace {
 // one 32x32 MFMA each.  v_mfma_f32_32x32x2_f32 multiplies a 32x2 slice of A
 // by a 2x32 slice of B; lane l supplies A[l%32][k(l)] and B[k(l)][l%32] and
 // lane group g = l/32 selects which of the two k values it carries.  Each
-// run of four k (4q .. 4q + 3) feeds two MFMA steps, with the k pairs
-// (4q, 4q + 2) and (4q + 1, 4q + 3), g = 0 the smaller k: every C element
-// sums the pairs (0, 2), (1, 3), (4, 6), (5, 7), ... in that order into one
-// accumulator whatever the tile configuration, so all configurations give
-// the same bits and requests of any sizes may share one launch.
+// run of eight k (8m .. 8m + 7) feeds four MFMA steps, with the k pairs
+// (8m + t, 8m + 4 + t) for t = 0 .. 3, g = 0 the smaller k: every C element
+// sums the pairs (0, 4), (1, 5), (2, 6), (3, 7), (8, 12), ... in that order
+// into one accumulator whatever the tile configuration, so all
+// configurations give the same bits and requests of any sizes may share one
+// launch.
 //
 // In LDS the k index of a tile is stored permuted, so that the KH = BK/2
 // values a lane multiplies in the KH steps of a tile sit side by side: k =
-// 4q + 2h + t (h, t in {0, 1}) goes to k' = h * KH + 2q + t.  A sits as
+// 8m + 4h + t (h in {0, 1}, t in 0 .. 3) goes to k' = h * KH + 4m + t.  A
+// run of four k stays contiguous, so a fetched float4 is still one 16-byte
+// LDS write, to the same banks as without the permutation.  A sits as
 // As[m][k'] (rows padded by 4 floats), and a lane's A fragments of a whole
-// tile are read with 16-byte LDS reads; a fetched float4 of A (four
-// consecutive k) is written as its two halves.  B has two stagings, chosen
-// per tile configuration by the tuner:
+// tile are read with 16-byte LDS reads.  B has two stagings, chosen per tile
+// configuration by the tuner:
 //  * BT: Bs[n][k'], B transposed on the way in (each thread fetches four
 //    k-rows of one column, coalesced along n); B fragments are then 16-byte
 //    reads like A's;
@@ -195,29 +197,25 @@ __global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(MI
         }
       }
     };
-    // k-permuted LDS layout: k = 4q, 4q + 1 go to k' = 2q, 2q + 1 and
-    // k = 4q + 2, 4q + 3 to KH + 2q, KH + 2q + 1
+    // k-permuted LDS layout: the float4 of k = 4q .. 4q + 3 goes to k' =
+    // (q % 2) * KH + 4 (q / 2) .. + 3
     auto store_tile = [&](int buf, auto slot_tag) {
       constexpr int SL = decltype(slot_tag)::value;
 #pragma unroll
       for (int i = 0; i < A4; ++i) {
         const int f = tid + i * NT;
         const int r = f / (BK / 4), q = f % (BK / 4);
-        const f32x4 x = ra[SL][i];
-        *reinterpret_cast<f32x2*>(&As[buf][r * AST + 2 * q]) = x.xy;
-        *reinterpret_cast<f32x2*>(&As[buf][r * AST + KH + 2 * q]) = x.zw;
+        *reinterpret_cast<f32x4*>(&As[buf][r * AST + (q & 1) * KH + 4 * (q >> 1)]) = ra[SL][i];
       }
 #pragma unroll
       for (int i = 0; i < B4; ++i) {
         const int f = tid + i * NT;
         if (BT) {
           const int c = f % BN, kq = f / BN;
-          const f32x4 x = rb[SL][i];
-          *reinterpret_cast<f32x2*>(&Bs[buf][c * BST + 2 * kq]) = x.xy;
-          *reinterpret_cast<f32x2*>(&Bs[buf][c * BST + KH + 2 * kq]) = x.zw;
+          *reinterpret_cast<f32x4*>(&Bs[buf][c * BST + (kq & 1) * KH + 4 * (kq >> 1)]) = rb[SL][i];
         } else {
           const int r = f / (BN / 4), c = (f % (BN / 4)) * 4;
-          const int rp = ((r >> 1) & 1) * KH + ((r >> 2) << 1) + (r & 1);
+          const int rp = ((r >> 2) & 1) * KH + ((r >> 3) << 2) + (r & 3);
           *reinterpret_cast<f32x4*>(&Bs[buf][rp * BST + c]) = rb[SL][i];
         }
       }
