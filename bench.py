@@ -489,6 +489,10 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--graphs", type=int, default=0, help="replay repeated batches as HIP graphs")
     ap.add_argument("--copy-threads", type=int, default=8, help="manager threads for shared memory <-> pinned copies")
+    ap.add_argument("--early-copy-in", type=int, default=1, choices=(0, 1),
+                    help="start a rank's next input while the running batch finishes (gvm_config.early_copy_in)")
+    ap.add_argument("--trace", default=None,
+                    help="write the per-request trace of the copy-inclusive steps there (Chrome trace JSON)")
     ap.add_argument("--rank-threads", action="store_true",
                     help="run the ranks as threads of this process (for profilers that cannot follow forks)")
     ap.add_argument("--loopback", action="store_true", help=argparse.SUPPRESS)  # host-protocol dry run, no GPU
@@ -536,6 +540,7 @@ def main(argv=None):
                                hbm_budget_bytes=max(2 << 30, 2 * nranks * space),
                                mode=G.GVM_MODE_BATCH, policy=G.GVM_POLICY_AUTO, batch_window_us=5_000_000,
                                use_graphs=1 if a.graphs else 0, copy_threads=copy_threads, name=ns,
+                               early_copy_in=a.early_copy_in,
                                backend=G.GVM_BACKEND_LOOPBACK if a.loopback else G.GVM_BACKEND_HIP)
     log(f"GVM: {nranks} ranks, {a.workload}")
     G.check(G.gvm_init(cfg), "gvm_init")
@@ -568,6 +573,8 @@ def main(argv=None):
         bar.wait()                      # 3: go (timed steps with copies)
         bar.wait()                      # 4: timed steps done
         e2e_stats = G.gvm_stats_json()
+        if a.trace:
+            G.check(G.gvm_trace_dump(a.trace), "trace dump")
         bar.wait()                      # 5: resident warm-up
         bar.wait()                      # 6: resident warm-up done
         G.gvm_stats_reset()
@@ -661,7 +668,7 @@ def main(argv=None):
         "data": "synthetic (seeded by rank)",
         "config": {"workload": WORKLOADS[a.workload], "name": a.workload,
                    "ranks": nranks, "mode": "batch", "policy": "auto", "graphs": bool(a.graphs),
-                   "copy_threads": copy_threads,
+                   "copy_threads": copy_threads, "early_copy_in": bool(a.early_copy_in),
                    "timed": "every step: shared memory -> HBM copies, kernels, HBM -> shared memory copies, "
                             "completions", "rank_kind": "threads" if a.rank_threads else "processes"},
         "roofline": roof,

@@ -169,12 +169,20 @@ typedef struct gvm_config {
                                    (two concurrent streams in one direction cut the link's
                                    duplex rate).  0: one class, first-come first-served
                                    throughout.  Default 8 MiB */
+  uint32_t early_copy_in;       /* batch mode: 1 (default) = while a batch runs, a rank whose
+                                   request has been answered starts moving its next request's
+                                   input (shared memory -> pinned -> HBM) as soon as the request
+                                   arrives, once every input of the running batch is on its
+                                   way; the request still joins the next request barrier
+                                   (Section 5) and its kernel runs with that batch.  0: inputs
+                                   move only after the barrier.  No effect with batch_timing
+                                   or use_graphs, in serving mode, or for resident inputs */
   char name[GVM_NAME_MAX];      /* shared-memory namespace; "" = "gvm.<uid>" */
 } gvm_config;
 
 /* Fill `cfg` with defaults (nranks 8, 64 MiB per rank, budget 16 GiB, batch mode,
  * AUTO policy, window 2000 us, HIP backend, r 0.02, sigma 0.30, small requests up
- * to 8 MiB). */
+ * to 8 MiB, early copy-in on). */
 void gvm_config_default(gvm_config* cfg);
 
 /* The CU masks the manager uses for gvm_config.latency_cus (extension; no

@@ -34,6 +34,7 @@ void gvm_config_default(gvm_config* cfg) {
   cfg->bs_rate = 0.02f;
   cfg->bs_volatility = 0.30f;
   cfg->small_request_bytes = 8u << 20;
+  cfg->early_copy_in = 1;
   cfg->name[0] = 0;
 }
 

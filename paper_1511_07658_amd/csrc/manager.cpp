@@ -262,7 +262,7 @@ void Manager::service(std::promise<int>* ready) {
       idle_since = 0;
       continue;
     }
-    if (inflight_ > 0) {
+    if (inflight_ > 0 && !early_idle()) {
       // device work outstanding: retire finished batches meanwhile, then
       // poll its events, yielding the core politely
       flush_deferred();
@@ -289,8 +289,9 @@ void Manager::service(std::promise<int>* ready) {
     std::atomic_thread_fence(std::memory_order_seq_cst);
     if (!any_request_waiting()) {
       if (cfg_.mode == GVM_MODE_BATCH && cfg_.batch_window_us) {
-        for (const auto& rt : ranks_)
-          if (!rt.queue.empty()) timeout = std::min<int64_t>(timeout, int64_t(cfg_.batch_window_us) * 1000 / 4 + 1000);
+        bool waiting = !early_.empty();
+        for (const auto& rt : ranks_) waiting |= !rt.queue.empty();
+        if (waiting) timeout = std::min<int64_t>(timeout, int64_t(cfg_.batch_window_us) * 1000 / 4 + 1000);
       }
       futex_wait(&ctl_->bell, v, timeout);
     }
@@ -299,7 +300,10 @@ void Manager::service(std::promise<int>* ready) {
     idle_since = 0;
   }
 
-  // Shutdown: let device work finish, answer what is still queued.
+  // Shutdown: let device work finish (requests admitted early run as a
+  // last batch), answer what is still queued.
+  staged_.insert(staged_.end(), early_.begin(), early_.end());
+  early_.clear();
   while (inflight_ > 0) {
     launch_ready();
     complete_jobs();
@@ -560,7 +564,7 @@ bool Manager::complete_jobs() {
     any = true;
     if (!alive) reap_rank(r);  // a dead rank process is found by check_liveness()
   }
-  if (cfg_.mode == GVM_MODE_BATCH && batch_open_ && inflight_ == 0) batch_open_ = false;
+  if (cfg_.mode == GVM_MODE_BATCH && batch_open_ && inflight_ == early_.size()) batch_open_ = false;
   return any;
 }
 
@@ -573,29 +577,44 @@ void Manager::flush_deferred() {
   if (cfg_.batch_timing) timing_json_ = dev_->timing_json();
 }
 
+// Move an admitted job's copy-in along: each input piece goes to the device
+// as soon as it is staged.  True once the job is ready to launch (its whole
+// input staged, and sent when it goes in pieces).
+bool Manager::forward_pieces(Job* j) {
+  if (j->stage == kStageCopyIn) {
+    if (j->pieces) {
+      while (j->in_sent < j->in_pieces && j->in_pending[j->in_sent].load(std::memory_order_acquire) == 0) {
+        const uint64_t off = static_cast<uint64_t>(j->in_sent) * piece_bytes();
+        const int rc = dev_->stream_in(j, off, std::min<uint64_t>(piece_bytes(), j->lay.in_bytes - off));
+        if (rc != GVM_OK && j->status == GVM_OK) j->status = rc;
+        ++j->in_sent;
+      }
+      if (j->in_sent == j->in_pieces) j->stage = kStageReady;
+    } else if (j->copies.load(std::memory_order_acquire) == 0) {
+      j->stage = kStageReady;
+    }
+  }
+  return j->stage == kStageReady;
+}
+
+// Early copy-in holds nothing the service loop must poll for: the batch has
+// retired and every early job is ready (its input staged and sent), so the
+// loop may sleep until the remaining ranks ring.
+bool Manager::early_idle() const {
+  if (early_.empty() || inflight_ != early_.size()) return false;
+  for (const Job* j : early_)
+    if (j->stage != kStageReady) return false;
+  return true;
+}
+
 // Launch admitted jobs whose inputs have reached the pinned staging.  A
 // batch (batch mode) goes to the device as a whole once every input is in;
 // in serving mode every ready job goes as soon as its copy-in lands.
 bool Manager::launch_ready() {
+  for (Job* j : early_) forward_pieces(j);
   if (staged_.empty()) return false;
   bool all = true;
-  for (Job* j : staged_) {
-    if (j->stage == kStageCopyIn) {
-      if (j->pieces) {
-        // each input piece goes to the device as soon as it is staged
-        while (j->in_sent < j->in_pieces && j->in_pending[j->in_sent].load(std::memory_order_acquire) == 0) {
-          const uint64_t off = static_cast<uint64_t>(j->in_sent) * piece_bytes();
-          const int rc = dev_->stream_in(j, off, std::min<uint64_t>(piece_bytes(), j->lay.in_bytes - off));
-          if (rc != GVM_OK && j->status == GVM_OK) j->status = rc;
-          ++j->in_sent;
-        }
-        if (j->in_sent == j->in_pieces) j->stage = kStageReady;
-      } else if (j->copies.load(std::memory_order_acquire) == 0) {
-        j->stage = kStageReady;
-      }
-    }
-    all &= (j->stage == kStageReady);
-  }
+  for (Job* j : staged_) all &= forward_pieces(j);
   // A batch of kernels that run as one grouped launch waits for all of its
   // inputs; per-rank launches (PS-2, what AUTO picks when large data moves) start
   // as soon as each input has landed, overlapping the others' copies.  With
@@ -818,15 +837,43 @@ bool Manager::schedule() {
     oldest = std::min(oldest, rt.queue.front().t_arrive_ns);
     newest = std::max(newest, rt.queue.front().t_arrive_ns);
   }
-  if (heads.empty()) return any;
+  if (heads.empty() && early_.empty()) return any;
   std::sort(heads.begin(), heads.end());
 
   std::vector<Job*> jobs;
   if (cfg_.mode == GVM_MODE_BATCH) {
+    if (batch_open_) {
+      // Early copy-in: once every input of the running batch is on its way
+      // (nothing of it left in staged_), a rank whose request has been
+      // answered moves its next input now, while the batch's results leave
+      // over the link in the other direction.  The request still waits for
+      // the barrier below before its kernel runs.
+      const bool early = cfg_.early_copy_in && !cfg_.batch_timing && !cfg_.use_graphs;
+      if (early && staged_.empty()) {
+        for (auto& h : heads) {
+          const Queued& q = ranks_[h.second].queue.front();
+          if (q.status != GVM_OK || (q.req.flags & GVM_F_IN_RESIDENT)) continue;
+          const uint64_t t = q.t_arrive_ns;
+          std::vector<Job*> got;
+          if (admit(h.second, got) == kRejected) any = true;
+          for (Job* j : got) {
+            if (early_.empty() || t < early_oldest_ns_) early_oldest_ns_ = t;
+            early_newest_ns_ = early_.empty() ? t : std::max(early_newest_ns_, t);
+            early_.push_back(j);
+            any = true;
+          }
+        }
+      }
+      return any;
+    }
     // Request barrier (Section 5): run when every attached rank has a
-    // request, or when the window since the oldest one has passed.
-    if (batch_open_) return any;
-    const bool all = heads.size() >= live;
+    // request (queued, or admitted early), or when the window since the
+    // oldest one has passed.
+    if (!early_.empty()) {
+      oldest = std::min(oldest, early_oldest_ns_);
+      newest = std::max(newest, early_newest_ns_);
+    }
+    const bool all = heads.size() + early_.size() >= live;
     const bool expired = now_ns() - oldest >= static_cast<uint64_t>(cfg_.batch_window_us) * 1000ull;
     if (!all && !expired) return any;
     {
@@ -853,6 +900,9 @@ bool Manager::schedule() {
       Admit a = admit(h.second, jobs);
       if (a == kRejected) any = true;
     }
+    // the early requests lead: their copies started first
+    jobs.insert(jobs.begin(), early_.begin(), early_.end());
+    early_.clear();
   } else {
     for (auto& h : heads) {
       if (inflight_ >= cfg_.max_inflight) break;

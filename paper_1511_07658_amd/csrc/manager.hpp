@@ -90,6 +90,8 @@ class Manager {
   void flush_deferred();           // retire finished batches, refresh the statistics
   bool schedule();
   bool launch_ready();
+  bool forward_pieces(Job* j);
+  bool early_idle() const;
   Admit admit(int r, std::vector<Job*>& jobs);
   void respond(int r, uint64_t ticket, uint32_t kernel_id, int status, const Job* j, uint64_t t_submit);
   void release_slot(int r);
@@ -108,6 +110,11 @@ class Manager {
   std::vector<RankRt> ranks_;
   CopyEngine copy_;                // shm <-> pinned staging copies
   std::vector<Job*> staged_;       // admitted, waiting for their copy-in
+  // batch mode, early copy-in: admitted while a batch runs, copy-in under
+  // way, held back until the next request barrier
+  std::vector<Job*> early_;
+  uint64_t early_oldest_ns_ = 0;   // arrivals of the oldest and the newest of them
+  uint64_t early_newest_ns_ = 0;
   std::thread thread_;
   std::atomic<bool> stop_{false};
   bool started_ = false;

@@ -409,6 +409,28 @@ int main(int argc, char** argv) {
           printf("{\"test\":\"pcie_pieces\",\"piece_bytes\":%zu,\"streams_per_direction\":%d,\"h2d_GBps\":%.1f,"
                  "\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n", piece, ns, pb[0], pb[1], pb[2]);
         }
+        {
+          // the mix of the copy-inclusive batches (vector add, SGEMM): twice
+          // as many bytes in as out, 8 MiB pieces, one stream per direction,
+          // an output piece queued after every second input piece
+          const size_t piece = size_t(8) << 20, np = bytes / piece;
+          double mix = 0;
+          for (int rep = 0; rep < 4; ++rep) {
+            const double t0 = now_s();
+            for (size_t i = 0; i < np; ++i) {
+              CK(hipMemcpyAsync(static_cast<char*>(d1) + i * piece, static_cast<char*>(h1) + i * piece, piece,
+                                hipMemcpyHostToDevice, ps[0]));
+              if (i % 2 == 0)
+                CK(hipMemcpyAsync(static_cast<char*>(h2) + (i / 2) * piece, static_cast<char*>(d2) + (i / 2) * piece,
+                                  piece, hipMemcpyDeviceToHost, ps[4]));
+            }
+            CK(hipStreamSynchronize(ps[0]));
+            CK(hipStreamSynchronize(ps[4]));
+            const double moved = static_cast<double>((np + (np + 1) / 2) * piece);
+            if (rep > 0) mix = std::max(mix, moved / (now_s() - t0) / 1e9);
+          }
+          printf("{\"test\":\"pcie_in2_out1\",\"piece_bytes\":%zu,\"GBps\":%.1f}\n", piece, mix);
+        }
         for (auto& x : ps) CK(hipStreamDestroy(x));
       }
       CK(hipHostFree(h1));

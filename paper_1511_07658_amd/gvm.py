@@ -76,6 +76,7 @@ class gvm_config(ctypes.Structure):
         ("batch_timing", ctypes.c_uint32),
         ("latency_cus", ctypes.c_uint32),
         ("small_request_bytes", ctypes.c_uint32),
+        ("early_copy_in", ctypes.c_uint32),
         ("name", ctypes.c_char * GVM_NAME_MAX),
     ]
 

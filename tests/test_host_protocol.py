@@ -147,6 +147,54 @@ def test_batch_barrier_holds_until_all_ranks_submit(ns_name):
         G.gvm_detach(1)
 
 
+@pytest.mark.parametrize("early", [1, 0])
+def test_batch_early_copy_in_moves_inputs_before_the_barrier(ns_name, early):
+    """Batch mode, two SPMD ranks of very different sizes: the small rank is
+    answered first and resubmits while the large rank's result is still
+    being copied out.  With early copy-in its next request is admitted (its
+    input starts moving) before the large rank has submitted, yet its
+    kernel is launched only after that submit (the request barrier); without
+    it, admission waits for the barrier.  Every result carries its own
+    bytes."""
+    sizes = [1024, 4 << 20]
+    steps = 12
+    with Manager(ns_name, nranks=2, batch_window_us=5_000_000, early_copy_in=early, copy_threads=1,
+                 shm_bytes_per_rank=(3 * max(sizes)) * 4 + (1 << 20), hbm_budget_bytes=512 << 20):
+        stamps = [[None] * steps for _ in range(2)]
+        errs = []
+        go = threading.Barrier(2)
+
+        def rank(r):
+            assert G.gvm_attach_ns(ns_name, r) == 0
+            n = sizes[r]
+            go.wait()
+            for step in range(steps):
+                inp = np.arange(2 * n, dtype=np.float32) + 3 * step + r
+                out = np.zeros(n, np.float32)
+                t = G.gvm_submit(r, G.GVM_K_VECADD, inp, out, n)
+                st, ts = G.gvm_wait_timed(r, t, 20_000_000_000)
+                if t < 0 or st != 0:
+                    errs.append((r, step, st, G.gvm_last_error()))
+                elif not np.array_equal(out, inp[:n]):
+                    errs.append((r, step, "wrong bytes"))
+                stamps[r][step] = [int(x) for x in ts]
+            assert G.gvm_detach(r) == 0
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(2)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+    ahead = 0
+    for step in range(steps):
+        small, large = stamps[0][step], stamps[1][step]
+        assert small[2] >= large[0] and large[2] >= small[0], step  # kernels after the barrier
+        ahead += small[1] < large[0]                              # admitted before the barrier
+    if early:
+        assert ahead > 0
+    else:
+        assert ahead == 0
+
+
 @pytest.mark.parametrize("timing", [0, 1])
 def test_large_requests_move_in_pieces(ns_name, timing):
     # inputs of 5 and 9 pieces (8 MiB each, the last one short), outputs
