@@ -379,7 +379,7 @@ int main(int argc, char** argv) {
       }
       printf("{\"test\":\"pcie_pinned\",\"alloc\":\"%s\",\"bytes\":%zu,\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n",
              names[f], bytes, best[0], best[1], best[2]);
-      if (f == 0) {
+      {
         // the same bytes in pieces of 2 to 16 MiB on one stream per
         // direction, and in 4 MiB pieces dealt round-robin over 2 or 4
         // streams per direction (one direction at a time, then both)
@@ -406,8 +406,8 @@ int main(int argc, char** argv) {
               if (rep > 0) pb[dir] = std::max(pb[dir], moved / (now_s() - t0) / 1e9);
             }
           }
-          printf("{\"test\":\"pcie_pieces\",\"piece_bytes\":%zu,\"streams_per_direction\":%d,\"h2d_GBps\":%.1f,"
-                 "\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n", piece, ns, pb[0], pb[1], pb[2]);
+          printf("{\"test\":\"pcie_pieces\",\"alloc\":\"%s\",\"piece_bytes\":%zu,\"streams_per_direction\":%d,"
+                 "\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n", names[f], piece, ns, pb[0], pb[1], pb[2]);
         }
         {
           // the mix of the copy-inclusive batches (vector add, SGEMM): twice
@@ -429,7 +429,8 @@ int main(int argc, char** argv) {
             const double moved = static_cast<double>((np + (np + 1) / 2) * piece);
             if (rep > 0) mix = std::max(mix, moved / (now_s() - t0) / 1e9);
           }
-          printf("{\"test\":\"pcie_in2_out1\",\"piece_bytes\":%zu,\"GBps\":%.1f}\n", piece, mix);
+          printf("{\"test\":\"pcie_in2_out1\",\"alloc\":\"%s\",\"piece_bytes\":%zu,\"GBps\":%.1f}\n", names[f], piece,
+                 mix);
         }
         for (auto& x : ps) CK(hipStreamDestroy(x));
       }

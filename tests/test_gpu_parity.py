@@ -563,6 +563,34 @@ def _c4_space(jobs):
     return max((G.in_elems(k, n) + G.out_elems(k, n)) * 4 for js in jobs for (k, _, n, _, _) in js) + (1 << 20)
 
 
+@pytest.mark.parametrize("mode", [G.GVM_MODE_BATCH, G.GVM_MODE_SERVING])
+def test_staging_carries_fresh_bytes_every_step(ns_name, mode):
+    # Eight steps through the same ranks (and so the same pinned staging),
+    # every step with new inputs: copies in pieces both ways (vector add of
+    # 3M, Black-Scholes of 1M, SGEMM 512), whole copies on the kernel's stream
+    # (vector add of 20000), zero-copy and copy-in ranks.  Every result
+    # matches the oracle for its own step, so no step reads a stale byte of
+    # staging that the host or the device wrote before.
+    steps = 8
+    specs = [(G.GVM_K_VECADD, 3_000_001, False), (G.GVM_K_BLACKSCHOLES, 1 << 20, False),
+             (G.GVM_K_SGEMM, 512, True), (G.GVM_K_VECADD, 20_000, False)]
+    jobs = [[(k, 41, n, req, integer) for req in range(steps)] for k, n, integer in specs]
+    with hip_manager(ns_name, nranks=len(specs), mode=mode, shm_bytes_per_rank=48 << 20,
+                     batch_window_us=5_000_000):
+        for zero_copy in (False, True):
+            res = run_ranks(ns_name, jobs, zero_copy=zero_copy, barrier=threading.Barrier(len(specs)))
+            for r, (k, n, integer) in enumerate(specs):
+                outs = check_ok(res[r])
+                assert len(outs) == steps
+                for req, o in enumerate(outs):
+                    if k == G.GVM_K_VECADD:
+                        assert_vecadd(o, 41, r, n, req)
+                    elif k == G.GVM_K_BLACKSCHOLES:
+                        assert_bs(o, 41, r, n, req)
+                    else:
+                        assert_sgemm(o, 41, r, n, req, integer=True)
+
+
 def test_config4_uneven_batch_full_scale(ns_name):
     # 32 ranks in one batch: 16 vector adds of n = floor(2^U[16,24]) and 16
     # SGEMMs of sizes from {256, ..., 2048 step 64}, copies over PCIe in
