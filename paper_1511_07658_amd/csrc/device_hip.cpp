@@ -454,6 +454,8 @@ class HipDevice final : public Device {
     pre_copies_.clear();
     for (hipEvent_t e : free_sync_) (void)hipEventDestroy(e);
     for (hipEvent_t e : free_timed_) (void)hipEventDestroy(e);
+    for (hipEvent_t e : free_marks_) (void)hipEventDestroy(e);
+    free_marks_.clear();
     free_sync_.clear();
     free_timed_.clear();
     for (hipStream_t s : rank_streams_) (void)hipStreamDestroy(s);
@@ -557,6 +559,22 @@ class HipDevice final : public Device {
     return e;
   }
 
+  // A timing mark around a kernel launch, read only by hipEventElapsedTime:
+  // no system-scope fence when it is reached (a fence writes back and
+  // invalidates the caches, which added 10-14 us to a launch's measured
+  // time on some devices).  Nothing waits on it or queries it; the stream
+  // order after a launch comes from ordinary events.
+  hipEvent_t launch_mark() {
+    hipEvent_t e = nullptr;
+    if (!free_marks_.empty()) {
+      e = free_marks_.back();
+      free_marks_.pop_back();
+    } else if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+      return nullptr;
+    }
+    return e;
+  }
+
   // Number of grouped launches the grouped policy makes for `jobs`.
   static size_t grouped_launches(const std::vector<Job*>& jobs) {
     std::vector<PlanJob> pj;
@@ -654,30 +672,27 @@ class HipDevice final : public Device {
     std::vector<PlanJob> pj;
     for (const Job* j : jobs) pj.push_back(plan_job(j));
     for (const PlanGroup& g : plan_groups(pj, static_cast<int>(streams.size()))) {
-      const int rc = launch_group(g, jobs, streams[static_cast<size_t>(g.stream)], b, true, nullptr);
+      const int rc = launch_group(g, jobs, streams[static_cast<size_t>(g.stream)], b, true);
       if (rc != GVM_OK) return rc;
     }
     return GVM_OK;
   }
 
   // One grouped launch of the requests `g.jobs` of `jobs` on stream `s`.
-  // `timed`: bracketed by timing events, and *end receives the closing one
-  // (it also marks the end of the launch on its stream); otherwise *end is
-  // left null.
-  int launch_group(const PlanGroup& g, const std::vector<Job*>& jobs, hipStream_t s, Batch* b, bool timed,
-                   hipEvent_t* end) {
+  // `timed`: bracketed by timing marks (a caller that orders other work
+  // after the launch records an event of its own).
+  int launch_group(const PlanGroup& g, const std::vector<Job*>& jobs, hipStream_t s, Batch* b, bool timed) {
     const int k = g.kernel_id;
     const size_t cnt = g.jobs.size();
     if (cnt == 0 || cnt > static_cast<size_t>(kMaxGroup)) return fail(GVM_EINVAL, "group of %zu requests", cnt);
     std::vector<Job*> v;
     for (int i : g.jobs) v.push_back(jobs[static_cast<size_t>(i)]);
-    if (end) *end = nullptr;
     TimedLaunch t{};
     t.kernel_id = k;
     t.requests = static_cast<uint32_t>(cnt);
     if (timed) {
-      t.e0 = timed_event();
-      t.e1 = timed_event();
+      t.e0 = launch_mark();
+      t.e1 = launch_mark();
       if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
     }
     for (Job* j : v) {
@@ -751,7 +766,6 @@ class HipDevice final : public Device {
     if (timed) {
       HIPCHK(hipEventRecord(t.e1, s));
       b->timed.push_back(t);
-      if (end) *end = t.e1;
     }
     return GVM_OK;
   }
@@ -829,8 +843,8 @@ class HipDevice final : public Device {
       t.bytes += by;
     }
     t.requests = static_cast<uint32_t>(jobs.size());
-    t.e0 = timed_event();
-    t.e1 = timed_event();
+    t.e0 = launch_mark();
+    t.e1 = launch_mark();
     if (!t.e0 || !t.e1) return fail(GVM_EDEVICE, "hipEventCreate failed");
     HIPCHK(hipEventRecord(t.e0, c0));
     HIPCHK(hipGraphLaunch(it->second.exec, c0));
@@ -875,14 +889,11 @@ class HipDevice final : public Device {
           rc = enqueue_out(jobs[static_cast<size_t>(o.job)], s);
           break;
         case kOpLaunch: {
-          hipEvent_t end = nullptr;
-          rc = launch_group(p.groups[static_cast<size_t>(o.group)], jobs, s, b, timed, &end);
-          if (rc == GVM_OK && o.ev >= 0) {
-            if (!end) {  // untimed: a marker of its own
-              end = sync_event(b);
-              if (!end) return GVM_EDEVICE;
-              HIPCHK(hipEventRecord(end, s));
-            }
+          rc = launch_group(p.groups[static_cast<size_t>(o.group)], jobs, s, b, timed);
+          if (rc == GVM_OK && o.ev >= 0) {  // the end of the launch on its stream
+            hipEvent_t end = sync_event(b);
+            if (!end) return GVM_EDEVICE;
+            HIPCHK(hipEventRecord(end, s));
             pe.ev[static_cast<size_t>(o.ev)] = end;
             pe.stream[static_cast<size_t>(o.ev)] = s;
           }
@@ -945,8 +956,8 @@ class HipDevice final : public Device {
         ks.work_bytes += t.bytes;
         if (launch_us_.size() < 65536) launch_us_.push_back(ms * 1e3);
       }
-      free_timed_.push_back(t.e0);
-      free_timed_.push_back(t.e1);
+      free_marks_.push_back(t.e0);
+      free_marks_.push_back(t.e1);
     }
     if (b->span0 && b->span1) {
       float ms = 0.0f;
@@ -1038,6 +1049,7 @@ class HipDevice final : public Device {
   uint64_t staging_bytes_ = 0;
   std::vector<hipEvent_t> free_sync_;
   std::vector<hipEvent_t> free_timed_;
+  std::vector<hipEvent_t> free_marks_;  // launch_mark() events
   std::vector<Batch*> batches_;
   KernelStats stats_[kNumKernelIds];
   struct GraphEntry {

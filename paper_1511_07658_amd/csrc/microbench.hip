@@ -6,6 +6,8 @@
 //                         over float4s per thread, grid and cache policy
 //   mfma   <iters>        FP32 MFMA issue rate (v_mfma_f32_32x32x2_f32 chains)
 //   pcie   <MiB>          pinned host<->device copy rates, one direction and both
+//   link   <MiB>          the manager's transfer path alone: 8 MiB pieces to and from
+//                         non-coherent pinned memory, each way, both, and the 2:1 mix
 //   hostcopy <MiB>        CPU memcpy pageable <-> pinned, 1 and 8 threads
 //   latency <iters>       launch -> completion seen by the host (event query,
 //                         stream synchronize, kernel-written host flag)
@@ -172,9 +174,33 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// The mix of the copy-inclusive batches (vector add, SGEMM): twice as many
+// bytes in as out, 8 MiB pieces, one stream per direction, an output piece
+// queued after every second input piece; best of 3 timed rounds after one
+// warm-up (GB/s over both directions).
+static double pcie_in2_out1(void* d1, void* h1, void* d2, void* h2, size_t bytes, hipStream_t in, hipStream_t out) {
+  const size_t piece = size_t(8) << 20, np = bytes / piece;
+  double mix = 0;
+  for (int rep = 0; rep < 4; ++rep) {
+    const double t0 = now_s();
+    for (size_t i = 0; i < np; ++i) {
+      CK(hipMemcpyAsync(static_cast<char*>(d1) + i * piece, static_cast<char*>(h1) + i * piece, piece,
+                        hipMemcpyHostToDevice, in));
+      if (i % 2 == 0)
+        CK(hipMemcpyAsync(static_cast<char*>(h2) + (i / 2) * piece, static_cast<char*>(d2) + (i / 2) * piece, piece,
+                          hipMemcpyDeviceToHost, out));
+    }
+    CK(hipStreamSynchronize(in));
+    CK(hipStreamSynchronize(out));
+    const double moved = static_cast<double>((np + (np + 1) / 2) * piece);
+    if (rep > 0) mix = std::max(mix, moved / (now_s() - t0) / 1e9);
+  }
+  return mix;
+}
+
 int main(int argc, char** argv) {
   if (argc < 2) {
-    fprintf(stderr, "usage: %s copy <MiB> <reps> | mfma <iters> | pcie <MiB> | latency <iters> | init\n", argv[0]);
+    fprintf(stderr, "usage: %s copy <MiB> <reps> | mfma <iters> | pcie <MiB> | link <MiB> | latency <iters> | init\n", argv[0]);
     return 1;
   }
   const std::string what = argv[1];
@@ -409,34 +435,58 @@ int main(int argc, char** argv) {
           printf("{\"test\":\"pcie_pieces\",\"alloc\":\"%s\",\"piece_bytes\":%zu,\"streams_per_direction\":%d,"
                  "\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,\"duplex_GBps\":%.1f}\n", names[f], piece, ns, pb[0], pb[1], pb[2]);
         }
-        {
-          // the mix of the copy-inclusive batches (vector add, SGEMM): twice
-          // as many bytes in as out, 8 MiB pieces, one stream per direction,
-          // an output piece queued after every second input piece
-          const size_t piece = size_t(8) << 20, np = bytes / piece;
-          double mix = 0;
-          for (int rep = 0; rep < 4; ++rep) {
-            const double t0 = now_s();
-            for (size_t i = 0; i < np; ++i) {
-              CK(hipMemcpyAsync(static_cast<char*>(d1) + i * piece, static_cast<char*>(h1) + i * piece, piece,
-                                hipMemcpyHostToDevice, ps[0]));
-              if (i % 2 == 0)
-                CK(hipMemcpyAsync(static_cast<char*>(h2) + (i / 2) * piece, static_cast<char*>(d2) + (i / 2) * piece,
-                                  piece, hipMemcpyDeviceToHost, ps[4]));
-            }
-            CK(hipStreamSynchronize(ps[0]));
-            CK(hipStreamSynchronize(ps[4]));
-            const double moved = static_cast<double>((np + (np + 1) / 2) * piece);
-            if (rep > 0) mix = std::max(mix, moved / (now_s() - t0) / 1e9);
-          }
-          printf("{\"test\":\"pcie_in2_out1\",\"alloc\":\"%s\",\"piece_bytes\":%zu,\"GBps\":%.1f}\n", names[f], piece,
-                 mix);
-        }
+        printf("{\"test\":\"pcie_in2_out1\",\"alloc\":\"%s\",\"piece_bytes\":%d,\"GBps\":%.1f}\n", names[f],
+               8 << 20, pcie_in2_out1(d1, h1, d2, h2, bytes, ps[0], ps[4]));
         for (auto& x : ps) CK(hipStreamDestroy(x));
       }
       CK(hipHostFree(h1));
       CK(hipHostFree(h2));
     }
+    CK(hipFree(d1));
+    CK(hipFree(d2));
+  } else if (what == "link") {
+    // the copy path of the manager's piecewise transfers alone: 8 MiB pieces
+    // on one stream per direction between HBM and non-coherent pinned memory
+    // (the staging kind), host to device, device to host, both at once with
+    // equal bytes, and the 2:1 in/out mix
+    const size_t bytes = (argc > 2 ? strtoull(argv[2], nullptr, 10) : 256) << 20;
+    const size_t piece = size_t(8) << 20, np = bytes / piece;
+    void *d1, *d2, *h1, *h2;
+    CK(hipMalloc(&d1, bytes));
+    CK(hipMalloc(&d2, bytes));
+    CK(hipMemset(d2, 2, bytes));
+    CK(hipHostMalloc(&h1, bytes, hipHostMallocNonCoherent));
+    CK(hipHostMalloc(&h2, bytes, hipHostMallocNonCoherent));
+    memset(h1, 1, bytes);
+    memset(h2, 2, bytes);
+    hipStream_t in, out;
+    CK(hipStreamCreateWithFlags(&in, hipStreamNonBlocking));
+    CK(hipStreamCreateWithFlags(&out, hipStreamNonBlocking));
+    double rate[3] = {0, 0, 0};
+    for (int rep = 0; rep < 4; ++rep) {
+      for (int dir = 0; dir < 3; ++dir) {  // 0 H2D, 1 D2H, 2 both
+        const double t0 = now_s();
+        for (size_t i = 0; i < np; ++i) {
+          if (dir != 1)
+            CK(hipMemcpyAsync(static_cast<char*>(d1) + i * piece, static_cast<char*>(h1) + i * piece, piece,
+                              hipMemcpyHostToDevice, in));
+          if (dir != 0)
+            CK(hipMemcpyAsync(static_cast<char*>(h2) + i * piece, static_cast<char*>(d2) + i * piece, piece,
+                              hipMemcpyDeviceToHost, out));
+        }
+        CK(hipStreamSynchronize(in));
+        CK(hipStreamSynchronize(out));
+        const double moved = (dir == 2 ? 2.0 : 1.0) * static_cast<double>(np * piece);
+        if (rep > 0) rate[dir] = std::max(rate[dir], moved / (now_s() - t0) / 1e9);
+      }
+    }
+    const double mix = pcie_in2_out1(d1, h1, d2, h2, bytes, in, out);
+    printf("{\"test\":\"link\",\"alloc\":\"noncoherent\",\"piece_bytes\":%zu,\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,"
+           "\"duplex_GBps\":%.1f,\"in2_out1_GBps\":%.1f}\n", piece, rate[0], rate[1], rate[2], mix);
+    CK(hipStreamDestroy(in));
+    CK(hipStreamDestroy(out));
+    CK(hipHostFree(h1));
+    CK(hipHostFree(h2));
     CK(hipFree(d1));
     CK(hipFree(d2));
   } else if (what == "hostcopy") {
