@@ -45,6 +45,7 @@ struct Job {
   uint32_t in_pieces = 0, in_sent = 0;                 // input pieces; those whose H2D is queued
   std::unique_ptr<std::atomic<int>[]> in_pending;      // host copy chunks in flight per input piece
   uint32_t out_pieces = 0, out_taken = 0;              // output pieces; those handed to the host copy
+  void* in_done = nullptr;       // device-private: marks the last input piece on the copy FIFO
   int part = -1;                 // CU partition of its kernel (latency_cus): 0 latency class, 1 the rest
   bool small = false;            // serving: a small request (small_request_bytes), staging copies first
   // serving: a rank's second request in flight has a device slot of its own

@@ -197,8 +197,22 @@ class HipDevice final : public Device {
 
   int stream_in(Job* j, uint64_t off, uint64_t bytes) override {
     // timing records wait in pre_copies_ until the job's batch exists
-    return timed_copy(j->slot + off, j->pin + off, bytes, hipMemcpyHostToDevice, h2d_,
-                      cfg_.batch_timing ? &pre_copies_[j] : nullptr, off == 0);
+    const int rc = timed_copy(j->slot + off, j->pin + off, bytes, hipMemcpyHostToDevice, h2d_,
+                              cfg_.batch_timing ? &pre_copies_[j] : nullptr, off == 0);
+    if (rc != GVM_OK || off + bytes < j->lay.in_bytes || capturing_) return rc;
+    // the last piece: an event after it, so that the job's kernel waits for
+    // its own input and not for what was queued on the FIFO after it (the
+    // next batch's inputs, with early copy-in); the job's batch owns it
+    hipEvent_t e = nullptr;
+    if (!free_sync_.empty()) {
+      e = free_sync_.back();
+      free_sync_.pop_back();
+    } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      return fail(GVM_EDEVICE, "hipEventCreate failed");
+    }
+    HIPCHK(hipEventRecord(e, h2d_));
+    j->in_done = e;
+    return GVM_OK;
   }
 
   int out_pieces_done(Job* j) override {
@@ -228,6 +242,8 @@ class HipDevice final : public Device {
       for (Job* j : jobs) {
         j->status = rc;
         j->batch = nullptr;
+        if (j->in_done) free_sync_.push_back(static_cast<hipEvent_t>(j->in_done));
+        j->in_done = nullptr;
       }
       return rc;
     }
@@ -244,6 +260,7 @@ class HipDevice final : public Device {
       jobs[i]->batch = b;
       jobs[i]->done_index = static_cast<int>(i);
       jobs[i]->t_launch_ns = now_ns();
+      if (jobs[i]->in_done) b->sync.push_back(static_cast<hipEvent_t>(jobs[i]->in_done));  // recycled with b
       auto pre = pre_copies_.find(jobs[i]);
       if (pre != pre_copies_.end()) {
         b->copies.insert(b->copies.end(), pre->second.begin(), pre->second.end());
@@ -302,7 +319,11 @@ class HipDevice final : public Device {
         }
         if (j->copy_in) {
           rc = enqueue_in(j, h2d_);
-          if (rc == GVM_OK) rc = after(s, h2d_, b);
+          if (rc == GVM_OK && j->in_done) {
+            HIPCHK(hipStreamWaitEvent(s, static_cast<hipEvent_t>(j->in_done), 0));
+          } else if (rc == GVM_OK) {
+            rc = after(s, h2d_, b);
+          }
         }
         if (rc == GVM_OK) rc = enqueue_kernels(one, {s}, b);
         if (rc == GVM_OK && j->copy_out) {

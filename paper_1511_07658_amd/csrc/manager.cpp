@@ -607,11 +607,19 @@ bool Manager::early_idle() const {
   return true;
 }
 
+// Launch what is ready, then move the early requests' copy-in along (after
+// the launch, so that a grouped batch's wait for the copy FIFO covers its
+// own inputs only).
+bool Manager::launch_ready() {
+  const bool launched = launch_staged();
+  for (Job* j : early_) forward_pieces(j);
+  return launched;
+}
+
 // Launch admitted jobs whose inputs have reached the pinned staging.  A
 // batch (batch mode) goes to the device as a whole once every input is in;
 // in serving mode every ready job goes as soon as its copy-in lands.
-bool Manager::launch_ready() {
-  for (Job* j : early_) forward_pieces(j);
+bool Manager::launch_staged() {
   if (staged_.empty()) return false;
   bool all = true;
   for (Job* j : staged_) all &= forward_pieces(j);
@@ -628,8 +636,14 @@ bool Manager::launch_ready() {
     if (!all) return false;
     ready.swap(staged_);
   } else {
+    // Batch mode: at most kLaunchChunk per call.  Enqueueing a request's
+    // per-rank chain (waits, kernel, output pieces with an event each) takes
+    // the host about 45 us, so a 32-rank batch held the service loop for
+    // 1.5 ms while the first results were already back; between chunks the
+    // loop answers them, and those ranks' next inputs start (early copy-in).
+    const size_t cap = cfg_.mode == GVM_MODE_BATCH ? kLaunchChunk : staged_.size();
     std::vector<Job*> keep;
-    for (Job* j : staged_) (j->stage == kStageReady ? ready : keep).push_back(j);
+    for (Job* j : staged_) (j->stage == kStageReady && ready.size() < cap ? ready : keep).push_back(j);
     staged_.swap(keep);
     if (ready.empty()) return false;
   }
@@ -844,12 +858,14 @@ bool Manager::schedule() {
   if (cfg_.mode == GVM_MODE_BATCH) {
     if (batch_open_) {
       // Early copy-in: once every input of the running batch is on its way
-      // (nothing of it left in staged_), a rank whose request has been
-      // answered moves its next input now, while the batch's results leave
-      // over the link in the other direction.  The request still waits for
-      // the barrier below before its kernel runs.
+      // (its jobs still in staged_ wait only for their launch), a rank whose
+      // request has been answered moves its next input now, while the
+      // batch's results leave over the link in the other direction.  The
+      // request still waits for the barrier below before its kernel runs.
       const bool early = cfg_.early_copy_in && !cfg_.batch_timing && !cfg_.use_graphs;
-      if (early && staged_.empty()) {
+      bool inputs_sent = true;  // every input of the running batch is on the copy FIFO
+      for (const Job* j : staged_) inputs_sent &= j->stage == kStageReady;
+      if (early && inputs_sent) {
         for (auto& h : heads) {
           const Queued& q = ranks_[h.second].queue.front();
           if (q.status != GVM_OK || (q.req.flags & GVM_F_IN_RESIDENT)) continue;

@@ -80,6 +80,8 @@ class Manager {
   // the first is still in flight, so that its copy-in overlaps the first's
   // device work (Section 4.2.1, concurrency types (a) to (c), within a rank).
   static constexpr size_t kRankDepth = 2;
+  // batch mode: per-rank chains enqueued per service-loop iteration
+  static constexpr size_t kLaunchChunk = 4;
   size_t rank_depth_ = kRankDepth;  // GVM_RANK_DEPTH=1 keeps one request per rank (measurement)
   bool rank_can_take(const RankRt& rt) const;
 
@@ -90,6 +92,7 @@ class Manager {
   void flush_deferred();           // retire finished batches, refresh the statistics
   bool schedule();
   bool launch_ready();
+  bool launch_staged();
   bool forward_pieces(Job* j);
   bool early_idle() const;
   Admit admit(int r, std::vector<Job*>& jobs);
