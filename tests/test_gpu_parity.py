@@ -570,10 +570,14 @@ def test_staging_carries_fresh_bytes_every_step(ns_name, mode):
     # 3M, Black-Scholes of 1M, SGEMM 512), whole copies on the kernel's stream
     # (vector add of 20000), zero-copy and copy-in ranks.  Every result
     # matches the oracle for its own step, so no step reads a stale byte of
-    # staging that the host or the device wrote before.
+    # staging that the host or the device wrote before, and no kernel runs
+    # before its own input has landed.
+    # Twelve ranks: batch mode enqueues their per-rank chains four at a time
+    # while answering finished ones, so the early copy-in of a step's first
+    # answered ranks overlaps the launch of the rest of the batch.
     steps = 8
     specs = [(G.GVM_K_VECADD, 3_000_001, False), (G.GVM_K_BLACKSCHOLES, 1 << 20, False),
-             (G.GVM_K_SGEMM, 512, True), (G.GVM_K_VECADD, 20_000, False)]
+             (G.GVM_K_SGEMM, 512, True), (G.GVM_K_VECADD, 20_000, False)] * 3
     jobs = [[(k, 41, n, req, integer) for req in range(steps)] for k, n, integer in specs]
     with hip_manager(ns_name, nranks=len(specs), mode=mode, shm_bytes_per_rank=48 << 20,
                      batch_window_us=5_000_000):
