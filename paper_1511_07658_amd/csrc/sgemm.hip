@@ -148,6 +148,12 @@ __global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(MI
         return f32x4{p[0], p[1], p[2], p[3]};
       }
       f32x4 x = f32x4{0};
+      if (VEC) {
+        // n and c are multiples of 4: a group of four lies wholly inside or
+        // wholly outside the matrix, so one check and one 16-byte load
+        if (r < n && c < n) x = *reinterpret_cast<const f32x4*>(p);
+        return x;
+      }
       if (r < n) {
         if (c + 0 < n) x.x = p[0];
         if (c + 1 < n) x.y = p[1];
@@ -178,6 +184,9 @@ __global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(MI
           const float* p = B + static_cast<size_t>(gr) * n + gc;
           if (FAST || (cols_in && k_in)) {
             rb[SL][i] = f32x4{p[0], p[n], p[2 * n], p[3 * n]};
+          } else if (VEC) {
+            // n and gr are multiples of 4: the four k-rows are all in or all out
+            rb[SL][i] = (gc < n && gr < n) ? f32x4{p[0], p[n], p[2 * n], p[3 * n]} : f32x4{0};
           } else {
             f32x4 x = f32x4{0};
             if (gc < n) {
