@@ -722,8 +722,11 @@ class HipDevice final : public Device {
       t.flop += f;
       t.bytes += by;
     }
-    if (timed) HIPCHK(hipEventRecord(t.e0, s));
+    // The descriptors are built first, so that the opening mark is recorded
+    // right before the launch call: host work between the two would be
+    // counted as the kernel's time when the stream is idle.
     hipError_t e = hipSuccess;
+    auto mark = [&]() -> hipError_t { return timed ? hipEventRecord(t.e0, s) : hipSuccess; };
     if (k == GVM_K_VECADD || k == GVM_K_VECMUL) {
       VecGroup vg{};
       vg.count = static_cast<uint32_t>(cnt);
@@ -735,7 +738,7 @@ class HipDevice final : public Device {
         vg.d[i].n = v[i]->req.n;
       }
       finalize_vec_group(vg);
-      e = (k == GVM_K_VECADD) ? launch_vecadd_group(vg, s) : launch_vecmul_group(vg, s);
+      if ((e = mark()) == hipSuccess) e = (k == GVM_K_VECADD) ? launch_vecadd_group(vg, s) : launch_vecmul_group(vg, s);
     } else if (k == GVM_K_BLACKSCHOLES) {
       BsGroup bg{};
       bg.count = static_cast<uint32_t>(cnt);
@@ -753,7 +756,7 @@ class HipDevice final : public Device {
         bg.d[i].n = n;
       }
       finalize_bs_group(bg);
-      e = launch_bs_group(bg, s);
+      if ((e = mark()) == hipSuccess) e = launch_bs_group(bg, s);
     } else if (k == GVM_K_SGEMM) {
       GemmGroup gg{};
       gg.count = static_cast<uint32_t>(cnt);
@@ -768,7 +771,7 @@ class HipDevice final : public Device {
       const int cfgi = gemm_group_config(v);
       finalize_gemm_group(gg, cfgi);
       const bool mixed = v.front()->req.n != v.back()->req.n;
-      e = launch_sgemm_group(gg, cfgi, s, mixed ? gemm_mix_grid() : 0);
+      if ((e = mark()) == hipSuccess) e = launch_sgemm_group(gg, cfgi, s, mixed ? gemm_mix_grid() : 0);
     } else if (k == GVM_K_EP) {
       EpGroup eg{};
       eg.count = static_cast<uint32_t>(cnt);
@@ -779,7 +782,7 @@ class HipDevice final : public Device {
         eg.d[i].n = v[i]->req.n;
       }
       finalize_ep_group(eg);
-      e = launch_ep_group(eg, s);
+      if ((e = mark()) == hipSuccess) e = launch_ep_group(eg, s);
     } else {
       return fail(GVM_EINVAL, "unknown kernel id %d", k);
     }
