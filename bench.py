@@ -619,13 +619,15 @@ def main(argv=None):
     roof["launches_per_step"] = round(per_step_launches, 3)
     roof["algorithmic_bytes"] = round(ks["work_bytes"] / launches)
     roof["algorithmic_flop"] = round(ks["work_flop"] / launches)
-    # the kernel's work per resident step over the whole step (manager round
-    # trip included); with several launches of the kernel per step, which
-    # run concurrently on the two compute streams, each launch's own FLOP
-    # over its duration understates the pair
-    roof["step_achieved"] = round((flop_total if main_kernel == G.GVM_K_SGEMM else bytes_total)
-                                  / (res_elapsed / max(a.resident_steps, 1)) /
-                                  (1e12 if main_kernel == G.GVM_K_SGEMM else 1e9), 3)
+    # the kernel's work per resident step over the whole step, in the unit of
+    # `achieved` (manager round trip and any concurrent launch included)
+    step_s = res_elapsed / max(a.resident_steps, 1)
+    if main_kernel == G.GVM_K_SGEMM:
+        roof["step_achieved"] = round(flop_total / step_s / 1e12, 3)
+    elif main_kernel == G.GVM_K_EP:
+        roof["step_achieved"] = round(pairs_total * EP_FP64_OPS_PER_PAIR / step_s / 1e12, 3)
+    else:
+        roof["step_achieved"] = round(bytes_total / step_s / 1e9, 3)
     if per_step_launches > 1.0:
         roof["note"] = "launches of one step overlap; step_achieved is the kernel's work per resident step"
 
