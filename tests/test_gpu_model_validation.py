@@ -4,9 +4,8 @@ paper's model-validation experiment of Section 6).
 For each kernel and programming style, the per-rank transfer and compute
 times are profiled with one rank (medians over 24 requests after 4 of
 warm-up, each copy and launch timed with device events on the same copy
-FIFOs and kernel streams the batches use), then N = 1..8 ranks run one
-request each
-as one batch, and the device phase of the batch (first copy-in to last
+FIFOs and kernel streams the batches use), then N = 1..64 ranks (1..8 for
+VecMul) run one request each as one batch, and the device phase of the batch (first copy-in to last
 copy-out, device events) is compared with the closed forms (Eq. 2/4 for
 PS-1, Eq. 3/7 for PS-2) and with the discrete-event schedule under the
 paper's single-queue rules and under independent queues.  Every kernel here
@@ -36,9 +35,11 @@ pytestmark = pytest.mark.gpu
 # repeated batches), SGEMM 1024, and the compute-intensive case: EP-like with
 # one work unit (2^15 pairs), i.e. one workgroup per request, the "kernel
 # size one" of the paper's EP(M24) validation
-CASES = [("vecadd", G.GVM_K_VECADD, 1 << 22, 5), ("vecmul", G.GVM_K_VECMUL, 1 << 24, 15),
-         ("sgemm", G.GVM_K_SGEMM, 1024, 5), ("ep", G.GVM_K_EP, 1 << 15, 5)]
-NS_LIST = [1, 2, 4, 8]
+# N runs to 64 ranks (one request each per batch) except for VecMul, whose
+# 256 MB per rank stops at 8
+NS_WIDE = [1, 2, 4, 8, 16, 32, 64]
+CASES = [("vecadd", G.GVM_K_VECADD, 1 << 22, 5, NS_WIDE), ("vecmul", G.GVM_K_VECMUL, 1 << 24, 15, [1, 2, 4, 8]),
+         ("sgemm", G.GVM_K_SGEMM, 1024, 5, NS_WIDE), ("ep", G.GVM_K_EP, 1 << 15, 5, NS_WIDE)]
 PROFILE_WARM, PROFILE_REPS = 4, 24
 
 
@@ -72,16 +73,17 @@ def _run(ns, kernel_id, n, nranks, reps):
 
 def test_execution_model_on_mi355x(ns_name):
     rows = []
-    for name, kid, n, reps in CASES:
+    for name, kid, n, reps, ns_list in CASES:
+        space = (G.in_elems(kid, n) + G.out_elems(kid, n)) * 4 + (1 << 20)
         for policy, pname in ((G.GVM_POLICY_PS1, "PS1"), (G.GVM_POLICY_PS2, "PS2")):
             ns = f"{ns_name}.{name}.{pname}"
-            cfg = G.gvm_config_default(nranks=8, shm_bytes_per_rank=(3 << 26) + (1 << 20), hbm_budget_bytes=4 << 30,
+            cfg = G.gvm_config_default(nranks=ns_list[-1], shm_bytes_per_rank=space, hbm_budget_bytes=8 << 30,
                                        policy=policy, batch_timing=1, batch_window_us=10_000_000, name=ns)
             G.check(G.gvm_init(cfg), "gvm_init")
             try:
                 # one untimed batch over every rank first: the first copy into a
                 # fresh device slot runs several times slower than later ones
-                _run(ns, kid, n, NS_LIST[-1], 1)
+                _run(ns, kid, n, ns_list[-1], 1)
                 # profile one rank: T_in, T_out, T_comp as medians of the timed
                 # copies and launches after a warm-up
                 G.gvm_stats_reset()
@@ -91,7 +93,7 @@ def test_execution_model_on_mi355x(ns_name):
                 t_in = statistics.median(tm["h2d_us"][PROFILE_WARM:]) * 1e-6
                 t_out = statistics.median(tm["d2h_us"][PROFILE_WARM:]) * 1e-6
                 t_comp = statistics.median(tm["launch_us"][PROFILE_WARM:]) * 1e-6
-                for N in NS_LIST:
+                for N in ns_list:
                     G.gvm_stats_reset()
                     st = _run(ns, kid, n, N, reps)
                     spans = st["timing"]["batch_device_us"]
