@@ -87,7 +87,10 @@ enum gvm_kernel {
 /* ------------------------------------------------------------ manager modes */
 enum gvm_mode {
   GVM_MODE_BATCH = 0,   /* request barrier of Section 5: wait until every attached rank
-                           has a request (or batch_window_us expires), run them together */
+                           has a request (or batch_window_us expires), run them together.
+                           With early_copy_in the inputs may move before the barrier; the
+                           kernels never start before it.  Per-rank chains (PS2) are
+                           enqueued a few at a time, finished requests answered between */
   GVM_MODE_SERVING = 1  /* continuous admission: run requests as soon as device memory
                            (hbm_budget_bytes) and in-flight slots allow; up to two
                            requests of a rank in flight (see gvm_submit) */
@@ -95,7 +98,8 @@ enum gvm_mode {
 
 /* Enqueue policy for a set of requests run together (Section 4.2.1):
  *   PS1      all copy-ins, then all kernels, then all copy-outs (Listing PS-1)
- *   PS2      per rank: copy-in, kernel, copy-out on the rank's stream (Listing PS-2)
+ *   PS2      per rank: copy-in, kernel, copy-out on the rank's stream (Listing PS-2);
+ *            the kernel waits for its own input, the copies keep one FIFO per direction
  *   GROUPED  copy-ins per rank, then ONE persistent launch per kernel id that
  *            covers every rank's request, then copy-outs per rank
  *   AUTO     GROUPED when no request of the set moves more than 1 MiB over
