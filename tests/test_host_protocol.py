@@ -195,6 +195,39 @@ def test_batch_early_copy_in_moves_inputs_before_the_barrier(ns_name, early):
         assert ahead == 0
 
 
+def test_batch_per_rank_chains_launch_in_chunks(ns_name):
+    """Batch mode with large copies (AUTO picks per-rank chains): the ready
+    requests of a batch are handed to the device at most four per service
+    iteration, so twelve ranks take at least three launch calls per step,
+    and every result still carries its own bytes."""
+    nranks, steps, n = 12, 5, 600_000          # 7.2 MB in, 2.4 MB out: pieces, not local
+    with Manager(ns_name, nranks=nranks, batch_window_us=5_000_000, copy_threads=2,
+                 shm_bytes_per_rank=(3 * n) * 4 + (1 << 20), hbm_budget_bytes=1 << 30):
+        errs = []
+        go = threading.Barrier(nranks)
+
+        def rank(r):
+            assert G.gvm_attach_ns(ns_name, r) == 0
+            go.wait()
+            for step in range(steps):
+                inp = np.arange(2 * n, dtype=np.float32) + 5 * step + r
+                out = np.zeros(n, np.float32)
+                t = G.gvm_submit(r, G.GVM_K_VECADD, inp, out, n)
+                if t < 0 or G.gvm_wait(r, t, 20_000_000_000) != 0:
+                    errs.append((r, step, G.gvm_last_error()))
+                elif not np.array_equal(out, inp[:n]):
+                    errs.append((r, step, "wrong bytes"))
+            assert G.gvm_detach(r) == 0
+
+        ths = [threading.Thread(target=rank, args=(r,)) for r in range(nranks)]
+        [t.start() for t in ths]
+        [t.join() for t in ths]
+        assert not errs, errs
+        st = G.gvm_stats_json()
+        assert st["requests_done"] == nranks * steps
+        assert st["batches"] >= 3 * steps, st["batches"]
+
+
 @pytest.mark.parametrize("timing", [0, 1])
 def test_large_requests_move_in_pieces(ns_name, timing):
     # inputs of 5 and 9 pieces (8 MiB each, the last one short), outputs
