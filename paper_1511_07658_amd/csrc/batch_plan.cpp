@@ -23,7 +23,7 @@ double job_us(const PlanJob& j) {
 
 }  // namespace
 
-std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstreams) {
+std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstreams, bool longest_first) {
   // One grouped launch per kernel id (an SGEMM request gets the same bits
   // from every tile configuration, so any sizes may share one launch).
   std::map<int, std::vector<int>> classes;
@@ -49,7 +49,8 @@ std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstream
     for (int j : out[g].jobs) us[g] += job_us(jobs[static_cast<size_t>(j)]);
   std::vector<size_t> order(out.size());
   for (size_t g = 0; g < order.size(); ++g) order[g] = g;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return us[a] > us[b]; });
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t b) { return longest_first ? us[a] > us[b] : us[a] < us[b]; });
   std::vector<PlanGroup> sorted;
   for (size_t k = 0; k < order.size(); ++k) {
     sorted.push_back(std::move(out[order[k]]));
@@ -58,9 +59,9 @@ std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstream
   return sorted;
 }
 
-BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool graph) {
+BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool graph, int compute_streams, bool longest_first) {
   BatchPlan p;
-  p.groups = plan_groups(jobs, 2);
+  p.groups = plan_groups(jobs, compute_streams == 1 ? 1 : 2, longest_first);
   p.stream_of.assign(jobs.size(), kPlanC0);
   for (const PlanGroup& g : p.groups)
     for (int j : g.jobs) p.stream_of[static_cast<size_t>(j)] = g.stream == 0 ? kPlanC0 : kPlanC1;

@@ -73,7 +73,8 @@ struct BatchPlan {
 
 // The grouped launches of `jobs` dealt round robin over `nstreams` streams
 // (one group per kernel id, split every kPlanMaxGroup requests).
-std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstreams);
+// `longest_first` false: shortest first instead.
+std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstreams, bool longest_first = true);
 
 // Grouped policy: copy-ins (local ones on C0 ahead of its kernels, the rest
 // on the H2D FIFO), the grouped launches on C0 and C1 after the inputs they
@@ -85,6 +86,9 @@ std::vector<PlanGroup> plan_groups(const std::vector<PlanJob>& jobs, int nstream
 // before the launch C0 waits for the H2D FIFO that holds the input pieces,
 // and after it the output pieces leave on the D2H FIFO.  The completions
 // follow the launch.
-BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool graph);
+// `compute_streams` 1: every launch on C0, one after another, in the order
+// `longest_first` gives.
+BatchPlan plan_grouped(const std::vector<PlanJob>& jobs, bool graph, int compute_streams = 2,
+                       bool longest_first = true);
 
 }  // namespace gvm

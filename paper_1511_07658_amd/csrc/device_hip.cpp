@@ -98,6 +98,17 @@ int gemm_mix_grid() {
   return env > 0 ? env : (1 << 24);
 }
 
+// Order of a grouped batch's launches: 0 = dealt over both compute streams,
+// longest first (default); 1 = one stream, longest first; 2 = one stream,
+// shortest first.  GVM_PLAN_SERIAL overrides.
+int plan_serial() {
+  static const int env = [] {
+    const char* e = getenv("GVM_PLAN_SERIAL");
+    return e ? atoi(e) : 0;
+  }();
+  return env;
+}
+
 class HipDevice final : public Device {
  public:
   ~HipDevice() override { close(); }
@@ -806,7 +817,8 @@ class HipDevice final : public Device {
     if (jobs[0]->part >= 0 && part_streams_.size() == 2)
       st[kPlanC0] = st[kPlanC1] = part_streams_[static_cast<size_t>(jobs[0]->part)];
     if (!cfg_.use_graphs) {
-      const BatchPlan p = plan_grouped(pj, false);
+      const int ser = plan_serial();
+      const BatchPlan p = plan_grouped(pj, false, ser ? 1 : 2, ser != 2);
       PlanEvents ev(p);
       return run_ops(p.ops, p, st, b, true, ev);
     }

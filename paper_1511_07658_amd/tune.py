@@ -10,7 +10,7 @@ so the tile choice stays a pure function of n: a rank's SGEMM result does
 not depend on what it is grouped with.
 
     python -m paper_1511_07658_amd.tune [--sizes 256,512,...] [--group 8] [--reps 10] [--write] [--json out.json]
-    python -m paper_1511_07658_amd.tune --from-json out.json    # table from a saved sweep
+    python -m paper_1511_07658_amd.tune --from-json a.json,b.json    # table from saved sweeps (mean time)
 
 Timing needs the GPU; rebuild the library after writing the table.
 """
@@ -120,6 +120,20 @@ def tune(sizes, group=8, reps=10, configs=None):
     return results
 
 
+def merge_sweeps(sweeps):
+    """One result per size from several saved sweeps: the mean time of each
+    configuration over the sweeps that timed it, fastest mean first (ties to
+    0.1 us go to the lower configuration index)."""
+    out = {}
+    for n in sorted({int(k) for s in sweeps for k in s}):
+        runs = [s[str(n)]["us"] for s in sweeps if str(n) in s]
+        names = [c for c in CONFIG_NAMES if any(c in r for r in runs)]
+        mean = {c: sum(r[c] for r in runs if c in r) / sum(1 for r in runs if c in r) for c in names}
+        best = min(names, key=lambda c: (round(mean[c], 1), CONFIG_NAMES.index(c)))
+        out[n] = {"best": CONFIG_NAMES.index(best), "us": {c: round(v, 2) for c, v in mean.items()}}
+    return out
+
+
 def write_table(results, path=TABLE):
     """The compiled-in table (every configuration gives a request the same
     bits, so the fastest one is taken)."""
@@ -150,12 +164,15 @@ def main(argv=None):
     ap.add_argument("--write", action="store_true")
     ap.add_argument("--json", default=None)
     ap.add_argument("--from-json", default=None,
-                    help="write the table from a saved sweep (the --json output of a run on the GPU) without timing")
+                    help="write the table from saved sweeps (comma-separated --json outputs of runs on the GPU; "
+                         "the mean time of each configuration decides) without timing")
     a = ap.parse_args(argv)
     if a.from_json:
-        with open(a.from_json) as f:
-            saved = json.load(f)
-        write_table({int(n): r for n, r in saved.items()})
+        sweeps = []
+        for path in a.from_json.split(","):
+            with open(path) as f:
+                sweeps.append(json.load(f))
+        write_table(merge_sweeps(sweeps))
         print(f"wrote {TABLE} from {a.from_json}; rebuild the library", file=sys.stderr)
         return 0
     sizes = [int(s) for s in a.sizes.split(",")] if a.sizes else [64, 128, 192] + list(range(256, 2049, 64))

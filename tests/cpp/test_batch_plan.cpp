@@ -256,13 +256,19 @@ PlanJob job(int k, uint64_t n, bool in, bool out, bool pieces = false) {
 
 int failures = 0;
 
+// Every launch order: both compute streams longest first, one stream longest
+// first, one stream shortest first.
 void expect_ok(const char* name, const std::vector<PlanJob>& jobs, bool graph) {
-  std::string why;
-  const BatchPlan p = plan_grouped(jobs, graph);
-  const char* err = check(p, jobs, graph, &why);
-  if (err) {
-    if (++failures > 20) return;
-    printf("FAIL %s (%s): %s %s\n", name, graph ? "graph" : "eager", err, why.c_str());
+  const int streams[3] = {2, 1, 1};
+  const bool longest[3] = {true, true, false};
+  for (int v = 0; v < 3; ++v) {
+    std::string why;
+    const BatchPlan p = plan_grouped(jobs, graph, streams[v], longest[v]);
+    const char* err = check(p, jobs, graph, &why);
+    if (err) {
+      if (++failures > 20) return;
+      printf("FAIL %s (%s, order %d): %s %s\n", name, graph ? "graph" : "eager", v, err, why.c_str());
+    }
   }
 }
 

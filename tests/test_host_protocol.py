@@ -600,6 +600,28 @@ def test_tile_configuration_names_match_the_compiled_table():
     assert 0 <= mix < tune.NUM_CONFIGS
 
 
+def test_tuner_merges_sweeps_by_mean_time(tmp_path):
+    # two saved sweeps: the mean time decides, a configuration timed in one
+    # sweep only keeps that time, ties to 0.1 us go to the lower index, and
+    # neighbouring sizes with one winner share a table row
+    from paper_1511_07658_amd import tune
+    a, b, c = tune.CONFIG_NAMES[3], tune.CONFIG_NAMES[16], tune.CONFIG_NAMES[27]
+    s1 = {"512": {"best": 3, "us": {a: 10.0, b: 12.0}}, "1024": {"best": 16, "us": {b: 134.0, c: 137.0}},
+          "2048": {"best": 3, "us": {a: 50.0, b: 50.04}}}
+    s2 = {"512": {"best": 16, "us": {a: 11.0, b: 9.5}}, "1024": {"best": 27, "us": {b: 137.0, c: 133.0}},
+          "1536": {"best": 27, "us": {c: 40.0}}}
+    m = tune.merge_sweeps([s1, s2])
+    assert m[512]["best"] == 3 and m[512]["us"][a] == 10.5 and m[512]["us"][b] == 10.75
+    assert m[1024]["best"] == 27 and m[1024]["us"][c] == 135.0
+    assert m[1536]["best"] == 27
+    assert m[2048]["best"] == 3  # 50.0 and 50.04 tie at 0.1 us
+    import re
+    path = tmp_path / "tiles.inc"
+    tune.write_table(m, path=str(path))
+    rows = re.findall(r"\{(\d+)u, (\d+)\}", path.read_text())
+    assert rows == [("512", "3"), ("1536", "27"), (str(1 << 30), "3")]
+
+
 def test_serving_pipelines_two_requests_of_a_rank(ns_name):
     """Serving mode admits a rank's second plain request while its first is
     still in flight (its copy-in overlaps the first's copies and device
