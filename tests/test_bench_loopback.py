@@ -27,6 +27,23 @@ def test_bench_line_on_loopback():
     assert line["unit"] == "GFLOP/s" and line["n_gpus"] == 1 and line["steps"] == 2
     assert line["results_unchanged_by_virtualization"] is True
     assert line["roofline"]["bound"] == "mfma"
+    # the resident leg's untimed steps cover about 60 ms of estimated device work
+    sys.path.insert(0, ROOT)
+    import bench
+    w = bench.resident_warmup_steps(bench.rank_specs("mixed32"))
+    assert line["device_phase"]["warmup_steps"] == w and 40 <= w <= 200
+
+
+def test_resident_warmup_covers_the_clock_climb():
+    sys.path.insert(0, ROOT)
+    import bench
+    for name in ("mixed32", "sgemm8", "vecadd16", "bs16", "ep8", "vecadd4"):
+        specs = bench.rank_specs(name)
+        w = bench.resident_warmup_steps(specs)
+        assert 3 <= w <= 5000, (name, w)
+    # 8 x 1024^2 SGEMM: 17.18 GFLOP at 110 TFLOP/s is 156 us, plus 50 us per step
+    assert bench.resident_warmup_steps(bench.rank_specs("sgemm8")) == 292
+    assert bench.resident_warmup_steps(bench.rank_specs("sgemm8"), target_ms=0.1) == 3
 
 
 def test_bench_refuses_more_than_one_gpu():
