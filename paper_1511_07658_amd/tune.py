@@ -2,14 +2,16 @@
 
 For every matrix size n of the search (default: the multiples of 64 in
 [256, 2048] plus the small sizes), runs a grouped launch of ``--group``
-identical-size requests (resident in HBM) through the GVM manager once per
+identical-size requests (resident in HBM) through the GVM manager for every
 compiled tile configuration, times the launches with the manager's HIP
-events, and keeps the fastest configuration.  The result is written as the
+events, and keeps the fastest configuration.  Each size starts with about
+60 ms of untimed launches (the engine clock climbs for about 20 ms under
+load), then passes over the configurations in index order and in reverse.  The result is written as the
 compiled-in table ``csrc/gemm_tiles.inc`` (rows of {largest n, config}),
 so the tile choice stays a pure function of n: a rank's SGEMM result does
 not depend on what it is grouped with.
 
-    python -m paper_1511_07658_amd.tune [--sizes 256,512,...] [--group 8] [--reps 10] [--write] [--json out.json]
+    python -m paper_1511_07658_amd.tune [--sizes 256,512,...] [--group 8] [--reps 10] [--rounds 2] [--write] [--json out.json]
     python -m paper_1511_07658_amd.tune --from-json a.json,b.json    # table from saved sweeps (mean time)
 
 Timing needs the GPU; rebuild the library after writing the table.
@@ -43,13 +45,24 @@ CONFIG_NAMES = ["64x64x16T", "128x64x16T", "128x128x16T", "128x128x32T", "256x12
                 "256x256x16R2", "64x128x16R2W4"]
 
 
-def _time_size(ns, n, group, reps, configs):
+def warmup_launches(n, group, target_ms=60.0):
+    """Launches of the first configuration, untimed, before a size is timed:
+    about `target_ms` of device work at 110 TFLOP/s.  From an idle device
+    (the ranks' uploads) the engine clock climbs for about 20 ms under load;
+    configurations timed during the climb would be timed on a lower clock
+    than the ones after them."""
+    us = group * 2.0 * n ** 3 / 110e6 + 20.0
+    return max(2, min(2000, int(-(-target_ms * 1e3 // us))))
+
+
+def _time_size(ns, n, group, reps, configs, rounds=2):
     """Mean device time (us) of one grouped launch of `group` n x n GEMMs,
-    per tile configuration."""
-    times = {}
+    per tile configuration: after a warm-up, `rounds` passes over the
+    configurations, in index order and then in reverse, so that a slow drift
+    of the clock weighs on every configuration alike."""
     bar = threading.Barrier(group + 1)
     stop = threading.Event()
-    plan = {"config": None}
+    plan = {"launches": reps}
     errors = []
 
     def rank(r):
@@ -66,7 +79,7 @@ def _time_size(ns, n, group, reps, configs):
                 bar.wait()
                 if stop.is_set():
                     break
-                for _ in range(reps + 2):
+                for _ in range(plan["launches"]):
                     t = G.check(G.gvm_submit_ex(r, 3, None, None, n, flags), "step")
                     G.check(G.gvm_wait(r, t, 60_000_000_000), "step")
                 bar.wait()
@@ -78,15 +91,24 @@ def _time_size(ns, n, group, reps, configs):
     ths = [threading.Thread(target=rank, args=(r,)) for r in range(group)]
     for t in ths:
         t.start()
+    total = {c: 0.0 for c in configs}
+    count = {c: 0 for c in configs}
     try:
         bar.wait()  # uploads done
-        for c in configs:
-            os.environ["GVM_SGEMM_CONFIG"] = str(c)
-            G.gvm_stats_reset()
-            bar.wait()          # go
-            bar.wait()          # done
-            st = G.gvm_stats_json()["kernels"]["sgemm"]
-            times[c] = st["device_ms"] / max(st["launches"], 1) * 1e3
+        os.environ["GVM_SGEMM_CONFIG"] = str(configs[0])
+        plan["launches"] = warmup_launches(n, group)
+        bar.wait()          # go (warm-up, untimed)
+        bar.wait()          # done
+        plan["launches"] = reps
+        for k in range(rounds):
+            for c in (configs if k % 2 == 0 else configs[::-1]):
+                os.environ["GVM_SGEMM_CONFIG"] = str(c)
+                G.gvm_stats_reset()
+                bar.wait()          # go
+                bar.wait()          # done
+                st = G.gvm_stats_json()["kernels"]["sgemm"]
+                total[c] += st["device_ms"]
+                count[c] += st["launches"]
         stop.set()
         bar.wait()
     finally:
@@ -95,10 +117,10 @@ def _time_size(ns, n, group, reps, configs):
             t.join()
     if errors:
         raise RuntimeError(errors[0])
-    return times
+    return {c: total[c] / max(count[c], 1) * 1e3 for c in configs}
 
 
-def tune(sizes, group=8, reps=10, configs=None):
+def tune(sizes, group=8, reps=10, configs=None, rounds=2):
     configs = list(range(NUM_CONFIGS)) if configs is None else configs
     ns = f"gvm.tune.{os.getpid()}"
     nmax = max(sizes)
@@ -110,7 +132,7 @@ def tune(sizes, group=8, reps=10, configs=None):
     try:
         for n in sizes:
             # sizes change the resident input, so every size re-attaches
-            t = _time_size(ns, n, group, reps, configs)
+            t = _time_size(ns, n, group, reps, configs, rounds)
             best = min(t, key=lambda c: (round(t[c], 1), c))
             results[n] = {"best": best, "us": {CONFIG_NAMES[c]: round(v, 2) for c, v in t.items()},
                           "tflops": round(group * 2.0 * n ** 3 / (t[best] * 1e-6) / 1e12, 2)}
@@ -159,7 +181,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", default=None, help="comma-separated sizes (default 64,128,192 and 256..2048 step 64)")
     ap.add_argument("--group", type=int, default=8)
-    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--reps", type=int, default=10, help="launches per configuration per round")
+    ap.add_argument("--rounds", type=int, default=2,
+                    help="passes over the configurations after the warm-up (index order, then reverse)")
     ap.add_argument("--configs", default=None)
     ap.add_argument("--write", action="store_true")
     ap.add_argument("--json", default=None)
@@ -177,7 +201,7 @@ def main(argv=None):
         return 0
     sizes = [int(s) for s in a.sizes.split(",")] if a.sizes else [64, 128, 192] + list(range(256, 2049, 64))
     configs = [int(c) for c in a.configs.split(",")] if a.configs else None
-    res = tune(sizes, a.group, a.reps, configs)
+    res = tune(sizes, a.group, a.reps, configs, a.rounds)
     if a.json:
         with open(a.json, "w") as f:
             json.dump(res, f, indent=1)
