@@ -90,10 +90,12 @@ enum gvm_mode {
                            has a request (or batch_window_us expires), run them together.
                            With early_copy_in the inputs may move before the barrier; the
                            kernels never start before it.  Per-rank chains (PS2) are
-                           enqueued a few at a time, finished requests answered between */
+                           enqueued a few at a time, finished requests answered between.
+                           Large copies move in 16 MiB pieces */
   GVM_MODE_SERVING = 1  /* continuous admission: run requests as soon as device memory
                            (hbm_budget_bytes) and in-flight slots allow; up to two
-                           requests of a rank in flight (see gvm_submit) */
+                           requests of a rank in flight (see gvm_submit).  Large copies
+                           move in 8 MiB pieces, the unit a small request waits behind */
 };
 
 /* Enqueue policy for a set of requests run together (Section 4.2.1):

@@ -1,5 +1,7 @@
 #include "common.hpp"
 
+#include <atomic>
+
 #include <errno.h>
 #include <linux/futex.h>
 #include <signal.h>
@@ -66,13 +68,19 @@ bool request_layout(int kernel_id, uint64_t n, Layout* out) {
   }
 }
 
+namespace {
+std::atomic<uint64_t> g_piece_bytes{8ull << 20};
+}  // namespace
+
+void set_piece_bytes(uint64_t bytes) { g_piece_bytes.store(bytes, std::memory_order_relaxed); }
+
 uint64_t piece_bytes() {
-  static const uint64_t b = [] {
+  static const uint64_t env = [] {
     const char* e = getenv("GVM_PIECE_MB");
-    const long mb = e ? atol(e) : 8;
-    return static_cast<uint64_t>(mb >= 1 && mb <= 64 ? mb : 8) << 20;
+    const long mb = e ? atol(e) : 0;
+    return mb >= 1 && mb <= 64 ? static_cast<uint64_t>(mb) << 20 : uint64_t(0);
   }();
-  return b;
+  return env ? env : g_piece_bytes.load(std::memory_order_relaxed);
 }
 
 int cu_partition_masks(uint32_t latency_cus, uint32_t* latency_mask, uint32_t* bulk_mask) {

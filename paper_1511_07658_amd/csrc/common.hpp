@@ -33,9 +33,11 @@ constexpr int kNumKernelIds = 6;  // kernel ids 1..5; index 0 collects mixed gra
 // Requests move between the ranks' shared memory, the pinned staging and the
 // device in pieces of this size (unless batch_timing asks for whole copies):
 // each piece's next hop starts as soon as it lands.
-// Bytes of one piece of a piecewise copy (default 8 MiB; GVM_PIECE_MB, read
-// once, overrides with 1..64).
+// Bytes of one piece of a piecewise copy: set by the manager at init (16 MiB
+// in batch mode, 8 MiB in serving mode); GVM_PIECE_MB, read once, overrides
+// with 1..64.
 uint64_t piece_bytes();
+void set_piece_bytes(uint64_t bytes);
 inline uint32_t piece_count(uint64_t bytes) { return static_cast<uint32_t>((bytes + piece_bytes() - 1) / piece_bytes()); }
 
 // A request whose copies total at most this many bytes keeps them on the
