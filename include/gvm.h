@@ -91,7 +91,7 @@ enum gvm_mode {
                            With early_copy_in the inputs may move before the barrier; the
                            kernels never start before it.  Per-rank chains (PS2) are
                            enqueued a few at a time, finished requests answered between.
-                           Large copies move in 16 MiB pieces */
+                           Large copies move in 32 MiB pieces */
   GVM_MODE_SERVING = 1  /* continuous admission: run requests as soon as device memory
                            (hbm_budget_bytes) and in-flight slots allow; up to two
                            requests of a rank in flight (see gvm_submit).  Large copies

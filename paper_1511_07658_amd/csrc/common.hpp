@@ -33,7 +33,7 @@ constexpr int kNumKernelIds = 6;  // kernel ids 1..5; index 0 collects mixed gra
 // Requests move between the ranks' shared memory, the pinned staging and the
 // device in pieces of this size (unless batch_timing asks for whole copies):
 // each piece's next hop starts as soon as it lands.
-// Bytes of one piece of a piecewise copy: set by the manager at init (16 MiB
+// Bytes of one piece of a piecewise copy: set by the manager at init (32 MiB
 // in batch mode, 8 MiB in serving mode); GVM_PIECE_MB, read once, overrides
 // with 1..64.
 uint64_t piece_bytes();

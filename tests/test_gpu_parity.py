@@ -567,7 +567,7 @@ def _c4_space(jobs):
 def test_staging_carries_fresh_bytes_every_step(ns_name, mode):
     # Eight steps through the same ranks (and so the same pinned staging),
     # every step with new inputs: copies in pieces both ways (vector add of
-    # 4.5M: 3 input and 2 result pieces of 16 MiB in batch mode, 5 and 3 of
+    # 9M: 3 input and 2 result pieces of 32 MiB in batch mode, 9 and 5 of
     # 8 MiB in serving mode; Black-Scholes of 1M, SGEMM 512), whole copies on the kernel's stream
     # (vector add of 20000), zero-copy and copy-in ranks.  Every result
     # matches the oracle for its own step, so no step reads a stale byte of
@@ -577,10 +577,10 @@ def test_staging_carries_fresh_bytes_every_step(ns_name, mode):
     # while answering finished ones, so the early copy-in of a step's first
     # answered ranks overlaps the launch of the rest of the batch.
     steps = 8
-    specs = [(G.GVM_K_VECADD, 4_500_001, False), (G.GVM_K_BLACKSCHOLES, 1 << 20, False),
+    specs = [(G.GVM_K_VECADD, 9_000_001, False), (G.GVM_K_BLACKSCHOLES, 1 << 20, False),
              (G.GVM_K_SGEMM, 512, True), (G.GVM_K_VECADD, 20_000, False)] * 3
     jobs = [[(k, 41, n, req, integer) for req in range(steps)] for k, n, integer in specs]
-    with hip_manager(ns_name, nranks=len(specs), mode=mode, shm_bytes_per_rank=64 << 20,
+    with hip_manager(ns_name, nranks=len(specs), mode=mode, shm_bytes_per_rank=112 << 20,
                      batch_window_us=5_000_000):
         for zero_copy in (False, True):
             res = run_ranks(ns_name, jobs, zero_copy=zero_copy, barrier=threading.Barrier(len(specs)))

@@ -232,8 +232,8 @@ def test_batch_per_rank_chains_launch_in_chunks(ns_name):
 @pytest.mark.parametrize("timing", [0, 1])
 def test_large_requests_move_in_pieces(ns_name, timing, mode):
     # serving mode: inputs of 5 and 9 pieces (8 MiB each, the last one
-    # short), outputs of 3 and 5; batch mode: 3 and 5 pieces of 16 MiB, and
-    # 2 and 3; with batch_timing the copies are whole instead
+    # short), outputs of 3 and 5; batch mode: 2 and 3 pieces of 32 MiB, and
+    # 1 and 2; with batch_timing the copies are whole instead
     sizes = [5_000_003, 9_000_001]
     with Manager(ns_name, nranks=2, mode=mode, batch_timing=timing,
                  shm_bytes_per_rank=(3 * max(sizes) + 8) * 4 + (1 << 20), hbm_budget_bytes=1 << 30):
