@@ -6,7 +6,7 @@
 //                         over float4s per thread, grid and cache policy
 //   mfma   <iters>        FP32 MFMA issue rate (v_mfma_f32_32x32x2_f32 chains)
 //   pcie   <MiB>          pinned host<->device copy rates, one direction and both
-//   link   <MiB>          the manager's transfer path alone: 8 MiB pieces to and from
+//   link   <MiB> [piece]  the manager's transfer path alone: 8 MiB (or [piece] MiB) pieces to and from
 //                         non-coherent pinned memory, each way, both, and the 2:1 mix
 //   hostcopy <MiB>        CPU memcpy pageable <-> pinned, 1 and 8 threads
 //   latency <iters>       launch -> completion seen by the host (event query,
@@ -178,8 +178,9 @@ static double now_s() {
 // bytes in as out, 8 MiB pieces, one stream per direction, an output piece
 // queued after every second input piece; best of 3 timed rounds after one
 // warm-up (GB/s over both directions).
-static double pcie_in2_out1(void* d1, void* h1, void* d2, void* h2, size_t bytes, hipStream_t in, hipStream_t out) {
-  const size_t piece = size_t(8) << 20, np = bytes / piece;
+static double pcie_in2_out1(void* d1, void* h1, void* d2, void* h2, size_t bytes, hipStream_t in, hipStream_t out,
+                            size_t piece = size_t(8) << 20) {
+  const size_t np = bytes / piece;
   double mix = 0;
   for (int rep = 0; rep < 4; ++rep) {
     const double t0 = now_s();
@@ -200,7 +201,7 @@ static double pcie_in2_out1(void* d1, void* h1, void* d2, void* h2, size_t bytes
 
 int main(int argc, char** argv) {
   if (argc < 2) {
-    fprintf(stderr, "usage: %s copy <MiB> <reps> | mfma <iters> | pcie <MiB> | link <MiB> | latency <iters> | init\n", argv[0]);
+    fprintf(stderr, "usage: %s copy <MiB> <reps> | mfma <iters> | pcie <MiB> | link <MiB> [piece MiB] | latency <iters> | init\n", argv[0]);
     return 1;
   }
   const std::string what = argv[1];
@@ -445,12 +446,17 @@ int main(int argc, char** argv) {
     CK(hipFree(d1));
     CK(hipFree(d2));
   } else if (what == "link") {
-    // the copy path of the manager's piecewise transfers alone: 8 MiB pieces
-    // on one stream per direction between HBM and non-coherent pinned memory
-    // (the staging kind), host to device, device to host, both at once with
-    // equal bytes, and the 2:1 in/out mix
+    // the copy path of the manager's piecewise transfers alone: pieces (8 MiB,
+    // or the third argument in MiB) on one stream per direction between HBM
+    // and non-coherent pinned memory (the staging kind), host to device,
+    // device to host, both at once with equal bytes, and the 2:1 in/out mix
     const size_t bytes = (argc > 2 ? strtoull(argv[2], nullptr, 10) : 256) << 20;
-    const size_t piece = size_t(8) << 20, np = bytes / piece;
+    const size_t piece = (argc > 3 ? strtoull(argv[3], nullptr, 10) : 8) << 20;
+    if (piece == 0 || bytes < piece || bytes % piece) {
+      fprintf(stderr, "link: <MiB> must be a positive multiple of the piece size\n");
+      return 1;
+    }
+    const size_t np = bytes / piece;
     void *d1, *d2, *h1, *h2;
     CK(hipMalloc(&d1, bytes));
     CK(hipMalloc(&d2, bytes));
@@ -480,7 +486,7 @@ int main(int argc, char** argv) {
         if (rep > 0) rate[dir] = std::max(rate[dir], moved / (now_s() - t0) / 1e9);
       }
     }
-    const double mix = pcie_in2_out1(d1, h1, d2, h2, bytes, in, out);
+    const double mix = pcie_in2_out1(d1, h1, d2, h2, bytes, in, out, piece);
     printf("{\"test\":\"link\",\"alloc\":\"noncoherent\",\"piece_bytes\":%zu,\"h2d_GBps\":%.1f,\"d2h_GBps\":%.1f,"
            "\"duplex_GBps\":%.1f,\"in2_out1_GBps\":%.1f}\n", piece, rate[0], rate[1], rate[2], mix);
     CK(hipStreamDestroy(in));
